@@ -1,0 +1,195 @@
+/*
+ * sos.h -- C ABI of libsos: the loss, gradient and first-order loop of the
+ * over-parameterised sum-of-squares method (Keren, Osadchy, Poranne,
+ * "A practical, fast method for solving sum-of-squares problems for very
+ * large polynomials"), on one AMD Instinct MI355X (gfx950).
+ *
+ * The problem (Section 1.1, eq. basicsos and eq. nonconvex): a polynomial p
+ * of degree 2d in n variables is a sum of squares iff p = m_d^T G m_d for a
+ * PSD Gram matrix G, m_d being the vector of all monomials of degree <= d.
+ * Writing G = W W^T with an unconstrained N x k factor W, the method
+ * minimises
+ *
+ *     L(W) = || coeff(m_d^T W W^T m_d) - p ||^2
+ *
+ * in coefficient space with Adam (Section 3), using a full-rank, over-
+ * parameterised W (Section 1.3).
+ *
+ * Conventions used by every entry point:
+ *   - Basis order: all monomials of degree <= d, higher total degree first,
+ *     then lexicographically larger exponent vector first with x1 most
+ *     significant (the order of the n = d = 2 example of Section 1.1).
+ *     N = C(n+d, d).  Coefficient monomials (degree <= 2d) use the same
+ *     order; M = C(n+2d, 2d) and p, r, c are indexed by it.
+ *   - coeff(G)_beta = sum over ORDERED pairs (i, j) with alpha_i + alpha_j =
+ *     beta of G_ij.  The residual is r = coeff(W W^T) - p, the loss
+ *     L = ||r||^2 (not normalised, Section 3), the gradient 4 R W with
+ *     R_ij = r[rank(alpha_i + alpha_j)].
+ *   - W is N x k, row-major (row i = basis monomial i, column l = square l),
+ *     leading dimension k.  Its element type is double for SOS_FP64 and
+ *     float for every other precision (an FP32 master copy).
+ *   - d_* arguments are device pointers owned by the caller; h_* are host
+ *     pointers.  The library never allocates device memory: the caller
+ *     provides a workspace (sos_plan_bind) and per-problem optimiser state.
+ *   - `stream` is a hipStream_t passed as void* (NULL: the null stream).
+ *     Device work is enqueued on it; only sos_solve, sos_verify and
+ *     sos_exponents block the host.
+ *   - Return value: SOS_OK (0), a positive status, or a negative error.  On
+ *     error sos_last_error() returns a message (thread-local).  Arguments
+ *     are validated before anything is enqueued.  No entry point aborts the
+ *     process or throws across the ABI.
+ *   - A plan's workspace holds scratch of the call in flight: calls that
+ *     use one plan must be ordered (one stream, or synchronised); separate
+ *     plans may run concurrently.
+ */
+#ifndef SOS_H
+#define SOS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sos_plan_s* sos_plan_t;
+
+/* Arithmetic of the two contractions (Gram forward, R W backward).  The
+ * residual r, the loss and the certificate are FP64 in every mode.        */
+enum sos_precision {
+  SOS_FP64 = 0,    /* W double; FP64 MFMA for both contractions            */
+  SOS_FP32 = 1,    /* W float;  FP32 MFMA for both contractions            */
+  SOS_BF16X3 = 2,  /* W float master; each operand split into bf16 hi + lo,
+                      three bf16 MFMA products (hi*hi + hi*lo + lo*hi) with
+                      FP32 accumulation                                    */
+};
+
+enum sos_status {
+  SOS_OK = 0,
+  SOS_NOT_CONVERGED = 1, /* sos_solve: budget spent before the target      */
+  SOS_EINVAL = -1,       /* bad argument                                   */
+  SOS_ERANGE = -2,       /* problem outside the supported sizes            */
+  SOS_ENOMEM = -3,       /* workspace too small                            */
+  SOS_EHIP = -4,         /* HIP runtime error                              */
+  SOS_ENUMERIC = -5,     /* loss became NaN or Inf                         */
+};
+
+/* Flags for sos_loss_grad / sos_step. */
+enum sos_flags {
+  /* Forward in FP64: the FP32 master W is converted exactly to FP64 and the
+   * Gram tiles use FP64 MFMA.  Used to reach residuals below the FP32 or
+   * split-bf16 floor; ignored for SOS_FP64 (already exact).               */
+  SOS_FLAG_EXACT_FORWARD = 1,
+  /* sos_step only: the workspace's operand copies of W (bf16 hi/lo, or
+   * transposed copies) were written by the previous sos_step of this plan
+   * on this same W, so the split pass is skipped.                         */
+  SOS_FLAG_COPIES_VALID = 2,
+};
+
+/* Adam hyper-parameters (Kingma and Ba; the paper's optimiser, Section 3). */
+typedef struct {
+  double lr, beta1, beta2, eps;
+} sos_adam_t;
+
+/* sos_solve options. */
+typedef struct {
+  double tol;            /* target: FP64 ||r|| / ||p|| <= tol                */
+  int64_t max_steps;     /* step budget                                     */
+  int64_t check_every;   /* read the loss back every this many steps        */
+  int32_t ladder;        /* 1: start with the plan's fast forward and switch
+                            to SOS_FLAG_EXACT_FORWARD when it stalls        */
+  int32_t stall_checks;  /* checks without `stall_ratio` improvement that
+                            count as a stall (ladder switch)                */
+  double stall_ratio;    /* e.g. 0.7: progress needs rel < 0.7 * best       */
+} sos_solve_opts_t;
+
+typedef struct {
+  int64_t steps;         /* steps taken                                     */
+  int64_t exact_steps;   /* of which with the FP64 forward                  */
+  double loss;           /* last loss (as measured at the last check)       */
+  double rel;            /* FP64-verified ||r||/||p|| of the returned W     */
+  double best_rel;       /* best relative residual seen at any check        */
+  int32_t status;        /* SOS_OK or SOS_NOT_CONVERGED                     */
+  int32_t phase;         /* 0: fast forward, 1: exact forward at the end    */
+} sos_result_t;
+
+/* Plan a problem (host only; enumerates the bases of Section 1.1, builds
+ * the ranking tables and sizes the buffers).  n, d, rank >= 1;
+ * SOS_ERANGE if 2d > 15, n > 16, M >= 2^31 or N*N >= 2^31.
+ * The plan must be bound to a workspace before any device call.          */
+int sos_plan(int n, int d, int rank, int precision, sos_plan_t* out);
+
+/* Sizes: basis length N, coefficient count M, workspace bytes (one per
+ * plan, see sos_plan_bind) and optimiser-state bytes (one per problem:
+ * Adam moments m, v and the best W seen, each N x rank in W's type).
+ * Any output pointer may be NULL.                                         */
+int sos_plan_query(sos_plan_t plan, int64_t* N, int64_t* M, size_t* ws_bytes,
+                   size_t* state_bytes);
+
+/* Attach a device workspace of at least ws_bytes (256-byte aligned) and
+ * upload the ranking tables into it (asynchronously on `stream`).  The
+ * workspace must stay allocated while the plan is used.                   */
+int sos_plan_bind(sos_plan_t plan, void* d_ws, size_t ws_bytes, void* stream);
+
+/* Free the host side of a plan (the workspace stays the caller's). */
+void sos_plan_destroy(sos_plan_t plan);
+
+/* Exponent vectors in the library's order: which = 0 gives the N basis
+ * monomials, which = 1 the M coefficient monomials; h_out holds rows x n
+ * bytes.  Host only; needs no binding.                                    */
+int sos_exponents(sos_plan_t plan, int which, uint8_t* h_out);
+
+/* Test hook: d_out[i*N + j] = rank of alpha_i + alpha_j among the
+ * coefficient monomials, computed by the same in-kernel ranking the
+ * forward and backward use.  d_out holds N*N int32.                       */
+int sos_pair_ranks(sos_plan_t plan, int32_t* d_out, void* stream);
+
+/* Loss and gradient at W (eq. nonconvex; gradient 4 R W).
+ *   d_W:    N x rank, row-major (double for SOS_FP64, else float); read only
+ *   d_p:    M doubles
+ *   d_loss: 1 double, receives L = ||r||^2
+ *   d_grad: N x rank in W's type, receives 4 R W; may be NULL (forward only)
+ *   d_r:    M doubles, receives r = coeff(W W^T) - p; may be NULL
+ *   flags:  SOS_FLAG_EXACT_FORWARD or 0                                    */
+int sos_loss_grad(sos_plan_t plan, const void* d_W, const double* d_p, double* d_loss,
+                  void* d_grad, double* d_r, int flags, void* stream);
+
+/* One Adam step at iteration t (1-based): computes the loss and gradient
+ * at W (written to d_loss), then updates W, m, v in place.
+ *   d_state: state_bytes from sos_plan_query; zero it before t = 1.
+ *   flags:   SOS_FLAG_EXACT_FORWARD and/or SOS_FLAG_COPIES_VALID.          */
+int sos_step(sos_plan_t plan, void* d_W, void* d_state, int64_t t, const double* d_p,
+             const sos_adam_t* adam, double* d_loss, int flags, void* stream);
+
+/* The first-order loop (Section 3): Adam steps from the given W until the
+ * FP64-verified relative residual ||r||/||p|| <= opts->tol or max_steps.
+ * Success is judged on the best iterate (the minimum error over all
+ * iterations, Section 3): on return W holds the best W found.  Returns
+ * SOS_OK only if sos_verify of that W meets tol, else SOS_NOT_CONVERGED.
+ * d_state is zeroed by the call.  Blocks until done.                      */
+int sos_solve(sos_plan_t plan, void* d_W, void* d_state, const double* d_p,
+              const sos_adam_t* adam, const sos_solve_opts_t* opts, sos_result_t* h_res,
+              void* stream);
+
+/* Certificate check (eq. basicsos): FP64 Gram of the exactly converted W,
+ * r = coeff(W W^T) - p in FP64, *h_rel = ||r|| / ||p||.  d_r may be NULL.
+ * Blocks until done.                                                      */
+int sos_verify(sos_plan_t plan, const void* d_W, const double* d_p, double* h_rel,
+               double* d_r, void* stream);
+
+/* Serving: one Adam step for `count` independent problems in one set of
+ * launches.  plans[q] (bound, distinct workspaces), W[q], state[q], t[q],
+ * p[q] as in sos_step; d_losses[q] receives problem q's loss.  All plans
+ * must share the precision.                                               */
+int sos_step_batch(const sos_plan_t* plans, void* const* d_W, void* const* d_state,
+                   const int64_t* t, const double* const* d_p, const sos_adam_t* adam,
+                   double* d_losses, int count, void* stream);
+
+/* Message for the last error on this thread ("" if none). */
+const char* sos_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SOS_H */

@@ -1,0 +1,246 @@
+"""Python binding of libsos: the over-parameterised SOS method on MI355X.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libsos.so`` (built by ``paper_2410_19844_amd.build``).  PyTorch
+provides device memory and the stream; tensors are passed to the C ABI as
+raw data pointers.  Importing this package fails loudly if the library is
+missing; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libsos.so")
+
+FP64, FP32, BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+FLAG_EXACT_FORWARD = 1
+FLAG_COPIES_VALID = 2
+OK, NOT_CONVERGED = 0, 1
+
+
+class SosError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libsos error {code}: {msg}")
+        self.code = code
+
+
+class _Adam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_double), ("beta1", ctypes.c_double),
+                ("beta2", ctypes.c_double), ("eps", ctypes.c_double)]
+
+
+class _SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_steps", ctypes.c_int64),
+                ("check_every", ctypes.c_int64), ("ladder", ctypes.c_int32),
+                ("stall_checks", ctypes.c_int32), ("stall_ratio", ctypes.c_double)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("exact_steps", ctypes.c_int64),
+                ("loss", ctypes.c_double), ("rel", ctypes.c_double),
+                ("best_rel", ctypes.c_double), ("status", ctypes.c_int32),
+                ("phase", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: run `python -m paper_2410_19844_amd.build`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P, V, I, I64 = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+    sig = {
+        "sos_plan": (I, [I, I, I, I, ctypes.POINTER(P)]),
+        "sos_plan_query": (I, [P, ctypes.POINTER(I64), ctypes.POINTER(I64),
+                               ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+        "sos_plan_bind": (I, [P, V, ctypes.c_size_t, V]),
+        "sos_plan_destroy": (None, [P]),
+        "sos_exponents": (I, [P, I, V]),
+        "sos_pair_ranks": (I, [P, V, V]),
+        "sos_loss_grad": (I, [P, V, V, V, V, V, I, V]),
+        "sos_step": (I, [P, V, V, I64, V, ctypes.POINTER(_Adam), V, I, V]),
+        "sos_solve": (I, [P, V, V, V, ctypes.POINTER(_Adam), ctypes.POINTER(_SolveOpts),
+                          ctypes.POINTER(_Result), V]),
+        "sos_verify": (I, [P, V, V, ctypes.POINTER(ctypes.c_double), V, V]),
+        "sos_step_batch": (I, [ctypes.POINTER(P), ctypes.POINTER(V), ctypes.POINTER(V),
+                               ctypes.POINTER(I64), ctypes.POINTER(V), ctypes.POINTER(_Adam), V, I, V]),
+        "sos_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTS = ("sos_plan", "sos_plan_query", "sos_plan_bind", "sos_plan_destroy", "sos_exponents",
+           "sos_pair_ranks", "sos_loss_grad", "sos_step", "sos_solve", "sos_verify",
+           "sos_step_batch", "sos_last_error")
+
+
+def _check(rc: int, allow=(OK,)):
+    if rc not in allow:
+        raise SosError(rc, _lib.sos_last_error().decode())
+    return rc
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+@dataclass
+class Adam:
+    lr: float = 1e-3
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+
+    def c(self):
+        return _Adam(self.lr, self.beta1, self.beta2, self.eps)
+
+
+def sos_plan(n: int, d: int, rank: int, precision="fp32"):
+    """Host-only plan (no device memory).  See ``Plan`` for a bound plan."""
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    h = ctypes.c_void_p()
+    _check(_lib.sos_plan(n, d, rank, prec, ctypes.byref(h)))
+    return h
+
+
+class Plan:
+    """A bound plan: host tables plus a device workspace owned by this object."""
+
+    def __init__(self, n: int, d: int, rank: int, precision="fp32", device="cuda", stream=None):
+        self.n, self.d, self.rank = n, d, rank
+        self.prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self._h = sos_plan(n, d, rank, self.prec)
+        N, M = ctypes.c_int64(), ctypes.c_int64()
+        ws, st = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(_lib.sos_plan_query(self._h, ctypes.byref(N), ctypes.byref(M), ctypes.byref(ws), ctypes.byref(st)))
+        self.N, self.M = N.value, M.value
+        self.ws_bytes, self.state_bytes = ws.value, st.value
+        self.wdtype = torch.float64 if self.prec == FP64 else torch.float32
+        self.device = torch.device(device)
+        self.ws = None
+        if self.device.type == "cuda":
+            self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-self.ws.data_ptr()) % 256
+            self._ws_view = self.ws[off:off + self.ws_bytes]
+            _check(_lib.sos_plan_bind(self._h, ctypes.c_void_p(self._ws_view.data_ptr()),
+                                      self.ws_bytes, _stream(stream)))
+
+    _destroy = _lib.sos_plan_destroy
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._destroy(h)
+            self._h = None
+
+    # -- host queries ------------------------------------------------------
+    def exponents(self, which: int = 0):
+        import numpy as np
+        rows = self.N if which == 0 else self.M
+        out = np.empty((rows, self.n), dtype=np.uint8)
+        _check(_lib.sos_exponents(self._h, which, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    # -- device calls ------------------------------------------------------
+    def new_state(self):
+        return torch.zeros(self.state_bytes, dtype=torch.uint8, device=self.device)
+
+    def _w(self, W):
+        if W.dtype != self.wdtype or not W.is_contiguous() or tuple(W.shape) != (self.N, self.rank):
+            raise ValueError(f"W must be a contiguous {self.wdtype} tensor of shape ({self.N}, {self.rank})")
+        return W
+
+    def _p(self, p):
+        if p.dtype != torch.float64 or not p.is_contiguous() or p.numel() != self.M:
+            raise ValueError(f"p must be a contiguous float64 tensor of {self.M} elements")
+        return p
+
+    def pair_ranks(self, stream=None):
+        out = torch.empty((self.N, self.N), dtype=torch.int32, device=self.device)
+        _check(_lib.sos_pair_ranks(self._h, _ptr(out), _stream(stream)))
+        return out
+
+    def loss_grad(self, W, p, grad=True, want_r=False, exact=False, stream=None):
+        self._w(W), self._p(p)
+        loss = torch.empty(1, dtype=torch.float64, device=self.device)
+        g = torch.empty_like(W) if grad else None
+        r = torch.empty(self.M, dtype=torch.float64, device=self.device) if want_r else None
+        _check(_lib.sos_loss_grad(self._h, _ptr(W), _ptr(p), _ptr(loss), _ptr(g), _ptr(r),
+                                  FLAG_EXACT_FORWARD if exact else 0, _stream(stream)))
+        return loss, g, r
+
+    def step(self, W, state, t, p, adam: Adam, loss=None, flags=0, stream=None):
+        self._w(W), self._p(p)
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float64, device=self.device)
+        _check(_lib.sos_step(self._h, _ptr(W), _ptr(state), int(t), _ptr(p), ctypes.byref(adam.c()),
+                             _ptr(loss), int(flags), _stream(stream)))
+        return loss
+
+    def verify(self, W, p, want_r=False, stream=None):
+        self._w(W), self._p(p)
+        rel = ctypes.c_double()
+        r = torch.empty(self.M, dtype=torch.float64, device=self.device) if want_r else None
+        _check(_lib.sos_verify(self._h, _ptr(W), _ptr(p), ctypes.byref(rel), _ptr(r), _stream(stream)))
+        return (rel.value, r) if want_r else rel.value
+
+    def solve(self, W, p, adam: Adam, tol=1e-8, max_steps=10000, check_every=50, ladder=True,
+              stall_checks=4, stall_ratio=0.7, state=None, stream=None):
+        self._w(W), self._p(p)
+        state = self.new_state() if state is None else state
+        opts = _SolveOpts(tol, max_steps, check_every, 1 if ladder else 0, stall_checks, stall_ratio)
+        res = _Result()
+        _check(_lib.sos_solve(self._h, _ptr(W), _ptr(state), _ptr(p), ctypes.byref(adam.c()),
+                              ctypes.byref(opts), ctypes.byref(res), _stream(stream)),
+               allow=(OK, NOT_CONVERGED))
+        return {f: getattr(res, f) for f, _ in _Result._fields_}
+
+
+def step_batch(plans, Ws, states, ts, ps, adam: Adam, losses, stream=None):
+    """One Adam step for several independent problems (serving)."""
+    n = len(plans)
+    P = (ctypes.c_void_p * n)(*[pl._h for pl in plans])
+    Wv = (ctypes.c_void_p * n)(*[W.data_ptr() for W in Ws])
+    Sv = (ctypes.c_void_p * n)(*[s.data_ptr() for s in states])
+    Tv = (ctypes.c_int64 * n)(*[int(t) for t in ts])
+    Pv = (ctypes.c_void_p * n)(*[p.data_ptr() for p in ps])
+    _check(_lib.sos_step_batch(P, Wv, Sv, Tv, Pv, ctypes.byref(adam.c()), _ptr(losses), n, _stream(stream)))
+    return losses
+
+
+class SosLoss(torch.autograd.Function):
+    """L(W) = ||coeff(m_d^T W W^T m_d) - p||^2 with the hand-derived gradient 4 R W.
+
+    The forward already produces r, so it computes the gradient in the same
+    call and keeps it for backward (which scales it by the incoming grad).
+    """
+
+    @staticmethod
+    def forward(ctx, W, p, plan: Plan, exact: bool = False):
+        loss, g, _ = plan.loss_grad(W.detach().contiguous(), p, grad=True, exact=exact)
+        ctx.save_for_backward(g)
+        return loss.reshape(())
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (g,) = ctx.saved_tensors
+        return (grad_out.to(g.dtype) * g, None, None, None)
+
+
+def rel_residual(loss: float, p_norm: float) -> float:
+    return math.sqrt(max(loss, 0.0)) / (p_norm if p_norm > 0 else 1.0)

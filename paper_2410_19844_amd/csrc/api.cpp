@@ -1,0 +1,290 @@
+// C ABI of libsos (declared in include/sos.h): argument checks, call
+// sequencing on the caller's stream, and the host side of the solve loop.
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <utility>
+
+#include "sos_internal.h"
+
+namespace sos {
+
+static thread_local std::string g_last_error;
+
+int set_error(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_error(hipError_t e, const char* what) {
+  return set_error(SOS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define SOS_HIP(call, what)                          \
+  do {                                               \
+    hipError_t e_ = (call);                          \
+    if (e_ != hipSuccess) return hip_error(e_, what); \
+  } while (0)
+
+static int check_bound(const sos_plan_s* p, const char* fn) {
+  if (!p) return set_error(SOS_EINVAL, std::string(fn) + ": plan is NULL");
+  if (!p->bound) return set_error(SOS_EINVAL, std::string(fn) + ": plan is not bound to a workspace");
+  return SOS_OK;
+}
+
+static size_t slot_bytes(const sos_plan_s* p) { return p->state_bytes / 4; }
+static size_t w_elem(const sos_plan_s* p) { return p->prec == SOS_FP64 ? 8 : 4; }
+static double* scal(const sos_plan_s* p) { return (double*)(p->ws + p->lay.scal); }
+
+// r <- coeff(W W^T) - p in the workspace, L = ||r||^2 -> d_loss.
+static int run_forward(sos_plan_s* p, const void* W, const double* d_p, bool exact, bool prep,
+                       double* d_loss, hipStream_t s) {
+  if (p->prec == SOS_FP64) exact = false;
+  if (prep || exact) SOS_HIP(launch_prep(p, W, exact, s), "prep");
+  SOS_HIP(launch_init_r(p, d_p, s), "init_r");
+  SOS_HIP(launch_gram(p, exact, s), "gram");
+  SOS_HIP(launch_sumsq(p, (const double*)(p->ws + p->lay.r), p->M, d_loss, s), "loss");
+  return SOS_OK;
+}
+
+static int run_step(sos_plan_s* p, void* W, void* state, int64_t t, const double* d_p,
+                    const sos_adam_t& h, double* d_loss, int flags, hipStream_t s) {
+  const bool exact = (flags & SOS_FLAG_EXACT_FORWARD) != 0;
+  int rc = run_forward(p, W, d_p, exact, true, d_loss, s);
+  if (rc) return rc;
+  void* g = p->ws + p->lay.g;
+  SOS_HIP(launch_backward(p, g, s), "backward");
+  char* st = (char*)state;
+  SOS_HIP(launch_adam(p, W, st, st + slot_bytes(p), g, t, h, s), "adam");
+  return SOS_OK;
+}
+
+static int check_adam(const sos_adam_t* h, const char* fn) {
+  if (!h) return set_error(SOS_EINVAL, std::string(fn) + ": adam is NULL");
+  if (!(h->lr > 0) || !(h->beta1 >= 0 && h->beta1 < 1) || !(h->beta2 >= 0 && h->beta2 < 1) || !(h->eps >= 0))
+    return set_error(SOS_EINVAL, std::string(fn) + ": Adam needs lr > 0, 0 <= beta < 1, eps >= 0");
+  return SOS_OK;
+}
+
+}  // namespace sos
+
+using namespace sos;
+
+extern "C" {
+
+int sos_plan(int n, int d, int rank, int precision, sos_plan_t* out) {
+  try {
+    return plan_create(n, d, rank, precision, out);
+  } catch (...) {
+    return set_error(SOS_ENOMEM, "sos_plan: host allocation failed");
+  }
+}
+
+int sos_plan_query(sos_plan_t p, int64_t* N, int64_t* M, size_t* ws_bytes, size_t* state_bytes) {
+  if (!p) return set_error(SOS_EINVAL, "sos_plan_query: plan is NULL");
+  if (N) *N = p->N;
+  if (M) *M = p->M;
+  if (ws_bytes) *ws_bytes = p->lay.bytes;
+  if (state_bytes) *state_bytes = p->state_bytes;
+  return SOS_OK;
+}
+
+int sos_plan_bind(sos_plan_t p, void* d_ws, size_t ws_bytes, void* stream) {
+  if (!p) return set_error(SOS_EINVAL, "sos_plan_bind: plan is NULL");
+  if (!d_ws) return set_error(SOS_EINVAL, "sos_plan_bind: workspace is NULL");
+  if (((uintptr_t)d_ws) % 256) return set_error(SOS_EINVAL, "sos_plan_bind: workspace must be 256-byte aligned");
+  if (ws_bytes < p->lay.bytes)
+    return set_error(SOS_ENOMEM, "sos_plan_bind: workspace smaller than sos_plan_query's ws_bytes");
+  hipStream_t s = (hipStream_t)stream;
+  p->ws = (char*)d_ws;
+  p->ws_size = ws_bytes;
+  SOS_HIP(hipMemcpyAsync(p->ws + p->lay.codes, p->codes.data(), p->codes.size() * 4, hipMemcpyHostToDevice, s),
+          "sos_plan_bind: codes");
+  SOS_HIP(hipMemcpyAsync(p->ws + p->lay.tables, p->tables.data(), p->tables.size() * 4, hipMemcpyHostToDevice, s),
+          "sos_plan_bind: tables");
+  SOS_HIP(hipStreamSynchronize(s), "sos_plan_bind");
+  p->bound = true;
+  return SOS_OK;
+}
+
+void sos_plan_destroy(sos_plan_t p) { delete p; }
+
+int sos_exponents(sos_plan_t p, int which, uint8_t* h_out) {
+  if (!p || !h_out) return set_error(SOS_EINVAL, "sos_exponents: NULL argument");
+  if (which == 0) {
+    std::memcpy(h_out, p->basis.data(), p->basis.size());
+    return SOS_OK;
+  }
+  if (which == 1) {
+    std::vector<uint8_t> e;
+    try {
+      enumerate_monomials(p->n, 2 * p->d, e);
+    } catch (...) {
+      return set_error(SOS_ENOMEM, "sos_exponents: host allocation failed");
+    }
+    std::memcpy(h_out, e.data(), e.size());
+    return SOS_OK;
+  }
+  return set_error(SOS_EINVAL, "sos_exponents: which must be 0 (basis) or 1 (coefficients)");
+}
+
+int sos_pair_ranks(sos_plan_t p, int32_t* d_out, void* stream) {
+  if (int rc = check_bound(p, "sos_pair_ranks")) return rc;
+  if (!d_out) return set_error(SOS_EINVAL, "sos_pair_ranks: d_out is NULL");
+  SOS_HIP(launch_pair_ranks(p, d_out, (hipStream_t)stream), "sos_pair_ranks");
+  return SOS_OK;
+}
+
+int sos_loss_grad(sos_plan_t p, const void* d_W, const double* d_p, double* d_loss, void* d_grad,
+                  double* d_r, int flags, void* stream) {
+  if (int rc = check_bound(p, "sos_loss_grad")) return rc;
+  if (!d_W || !d_p || !d_loss) return set_error(SOS_EINVAL, "sos_loss_grad: d_W, d_p and d_loss are required");
+  if (flags & ~(int)SOS_FLAG_EXACT_FORWARD) return set_error(SOS_EINVAL, "sos_loss_grad: unknown flags");
+  hipStream_t s = (hipStream_t)stream;
+  int rc = run_forward(p, d_W, d_p, (flags & SOS_FLAG_EXACT_FORWARD) != 0, true, d_loss, s);
+  if (rc) return rc;
+  if (d_grad) SOS_HIP(launch_backward(p, d_grad, s), "sos_loss_grad: backward");
+  if (d_r)
+    SOS_HIP(hipMemcpyAsync(d_r, p->ws + p->lay.r, p->M * 8, hipMemcpyDeviceToDevice, s), "sos_loss_grad: r");
+  return SOS_OK;
+}
+
+int sos_step(sos_plan_t p, void* d_W, void* d_state, int64_t t, const double* d_p, const sos_adam_t* adam,
+             double* d_loss, int flags, void* stream) {
+  if (int rc = check_bound(p, "sos_step")) return rc;
+  if (int rc = check_adam(adam, "sos_step")) return rc;
+  if (!d_W || !d_state || !d_p || !d_loss) return set_error(SOS_EINVAL, "sos_step: NULL device pointer");
+  if (t < 1) return set_error(SOS_EINVAL, "sos_step: t is 1-based");
+  if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_COPIES_VALID))
+    return set_error(SOS_EINVAL, "sos_step: unknown flags");
+  return run_step(p, d_W, d_state, t, d_p, *adam, d_loss, flags, (hipStream_t)stream);
+}
+
+int sos_verify(sos_plan_t p, const void* d_W, const double* d_p, double* h_rel, double* d_r, void* stream) {
+  if (int rc = check_bound(p, "sos_verify")) return rc;
+  if (!d_W || !d_p || !h_rel) return set_error(SOS_EINVAL, "sos_verify: NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  double* sc = scal(p);
+  int rc = run_forward(p, d_W, d_p, true, true, sc + 0, s);
+  if (rc) return rc;
+  SOS_HIP(launch_sumsq(p, d_p, p->M, sc + 1, s), "sos_verify: ||p||");
+  double h[2];
+  SOS_HIP(hipMemcpyAsync(h, sc, sizeof(h), hipMemcpyDeviceToHost, s), "sos_verify: readback");
+  if (d_r) SOS_HIP(hipMemcpyAsync(d_r, p->ws + p->lay.r, p->M * 8, hipMemcpyDeviceToDevice, s), "sos_verify: r");
+  SOS_HIP(hipStreamSynchronize(s), "sos_verify");
+  const double np = std::sqrt(h[1]);
+  *h_rel = std::sqrt(h[0]) / (np > 0 ? np : 1.0);
+  return SOS_OK;
+}
+
+int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const sos_adam_t* adam,
+              const sos_solve_opts_t* o, sos_result_t* res, void* stream) {
+  if (int rc = check_bound(p, "sos_solve")) return rc;
+  if (int rc = check_adam(adam, "sos_solve")) return rc;
+  if (!d_W || !d_state || !d_p || !o || !res) return set_error(SOS_EINVAL, "sos_solve: NULL argument");
+  if (o->max_steps < 0 || o->check_every < 1 || !(o->tol >= 0))
+    return set_error(SOS_EINVAL, "sos_solve: needs max_steps >= 0, check_every >= 1, tol >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  std::memset(res, 0, sizeof(*res));
+  const size_t slot = slot_bytes(p), wbytes = (size_t)p->N * p->k * w_elem(p);
+  char* st = (char*)d_state;
+  char* best = st + 2 * slot;
+  char* cand = st + 3 * slot;
+  SOS_HIP(hipMemsetAsync(st, 0, 2 * slot, s), "sos_solve: zero state");
+  double* sc = scal(p);
+  SOS_HIP(launch_sumsq(p, d_p, p->M, sc + 1, s), "sos_solve: ||p||");
+  double pn2 = 0;
+  SOS_HIP(hipMemcpyAsync(&pn2, sc + 1, 8, hipMemcpyDeviceToHost, s), "sos_solve: readback");
+  SOS_HIP(hipStreamSynchronize(s), "sos_solve");
+  const double pnorm = pn2 > 0 ? std::sqrt(pn2) : 1.0;
+
+  const bool can_ladder = o->ladder && p->prec != SOS_FP64;
+  int phase = 0;
+  double best_rel = std::numeric_limits<double>::infinity(), ref_rel = best_rel;
+  bool have_best = false;
+  int stall = 0;
+  int64_t t = 0, exact_steps = 0;
+  double last_loss = 0;
+  bool done = false;
+  while (t < o->max_steps && !done) {
+    ++t;
+    const bool check = (t % o->check_every == 0) || t == o->max_steps;
+    if (check) SOS_HIP(hipMemcpyAsync(cand, d_W, wbytes, hipMemcpyDeviceToDevice, s), "sos_solve: snapshot");
+    const int flags = phase == 1 ? SOS_FLAG_EXACT_FORWARD : 0;
+    int rc = run_step(p, d_W, st, t, d_p, *adam, sc + 0, flags, s);
+    if (rc) return rc;
+    if (phase == 1) ++exact_steps;
+    if (!check) continue;
+    SOS_HIP(hipMemcpyAsync(&last_loss, sc + 0, 8, hipMemcpyDeviceToHost, s), "sos_solve: loss");
+    SOS_HIP(hipStreamSynchronize(s), "sos_solve");
+    if (!std::isfinite(last_loss)) {
+      if (have_best) SOS_HIP(hipMemcpy(d_W, best, wbytes, hipMemcpyDeviceToDevice), "sos_solve: restore");
+      res->steps = t;
+      res->exact_steps = exact_steps;
+      res->loss = last_loss;
+      res->phase = phase;
+      return set_error(SOS_ENUMERIC, "sos_solve: loss is not finite");
+    }
+    const double rel = std::sqrt(last_loss) / pnorm;
+    if (rel < best_rel) {
+      best_rel = rel;
+      std::swap(best, cand);  // the snapshot is the iterate this loss belongs to
+      have_best = true;
+    }
+    if (rel < o->stall_ratio * ref_rel) {
+      ref_rel = rel;
+      stall = 0;
+    } else {
+      ++stall;
+    }
+    bool switch_phase = can_ladder && phase == 0 && o->stall_checks > 0 && stall >= o->stall_checks;
+    if (rel <= o->tol) {
+      double vrel = 0;
+      int vrc = sos_verify(p, best, d_p, &vrel, nullptr, stream);
+      if (vrc) return vrc;
+      if (vrel <= o->tol) done = true;
+      else if (can_ladder && phase == 0) switch_phase = true;
+    }
+    if (switch_phase) {
+      phase = 1;
+      stall = 0;
+      best_rel = ref_rel = std::numeric_limits<double>::infinity();  // exact values from here on
+    }
+  }
+  if (have_best) SOS_HIP(hipMemcpyAsync(d_W, best, wbytes, hipMemcpyDeviceToDevice, s), "sos_solve: best W");
+  double vrel = 0;
+  int vrc = sos_verify(p, d_W, d_p, &vrel, nullptr, stream);
+  if (vrc) return vrc;
+  res->steps = t;
+  res->exact_steps = exact_steps;
+  res->loss = last_loss;
+  res->rel = vrel;
+  res->best_rel = best_rel;
+  res->phase = phase;
+  res->status = vrel <= o->tol ? SOS_OK : SOS_NOT_CONVERGED;
+  return res->status;
+}
+
+int sos_step_batch(const sos_plan_t* plans, void* const* d_W, void* const* d_state, const int64_t* t,
+                   const double* const* d_p, const sos_adam_t* adam, double* d_losses, int count,
+                   void* stream) {
+  if (count < 0 || (count > 0 && (!plans || !d_W || !d_state || !t || !d_p || !d_losses)))
+    return set_error(SOS_EINVAL, "sos_step_batch: NULL argument");
+  if (int rc = check_adam(adam, "sos_step_batch")) return rc;
+  for (int q = 0; q < count; ++q) {
+    if (int rc = check_bound(plans[q], "sos_step_batch")) return rc;
+    if (q > 0 && plans[q]->prec != plans[0]->prec)
+      return set_error(SOS_EINVAL, "sos_step_batch: all plans must share the precision");
+    if (t[q] < 1) return set_error(SOS_EINVAL, "sos_step_batch: t is 1-based");
+  }
+  for (int q = 0; q < count; ++q) {
+    int rc = run_step(plans[q], d_W[q], d_state[q], t[q], d_p[q], *adam, d_losses + q, 0, (hipStream_t)stream);
+    if (rc) return rc;
+  }
+  return SOS_OK;
+}
+
+const char* sos_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,649 @@
+// gfx950 kernels of the SOS hot path.
+//
+//   k_prep        operand copies of W (padded, zero-filled; bf16 hi/lo split;
+//                 transposed copies for the backward)
+//   k_init_r      r <- -p
+//   k_gram        forward: Gram tiles G_IJ = W_I W_J^T on MFMA over the upper
+//                 triangle of tiles, reduced straight into the FP64 residual
+//                 r[rank(alpha_i + alpha_j)] by atomic adds (eq. nonconvex)
+//   k_sumsq_*     L = sum r^2 (deterministic two-pass reduction)
+//   k_gather      R_ij = r[rank(alpha_i + alpha_j)] in the operand type
+//   k_rw          backward: g = 4 R W on MFMA
+//   k_adam        bias-corrected Adam (Kingma and Ba), in place
+//
+// Every GEMM here is "NT": C[i][j] = sum_k A[i][k] * B[j][k], both operands
+// K-contiguous, padded so that tiles never read out of bounds.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "sos_internal.h"
+
+namespace sos {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Ranking: rank(alpha_i + alpha_j) from the additive codes (see plan.cpp).
+// ---------------------------------------------------------------------------
+struct RankCtx {
+  const uint32_t* __restrict__ codes;  // N x nwords
+  const int32_t* __restrict__ tables;  // ngroups x 4096
+  int nwords, ngroups;
+};
+
+__device__ __forceinline__ int rank_of_sum(const RankCtx& c, int i, int j) {
+  int r = 0;
+#pragma unroll
+  for (int w = 0; w < kMaxWords; ++w) {
+    if (w < c.nwords) {
+      const uint32_t s = c.codes[(size_t)i * c.nwords + w] + c.codes[(size_t)j * c.nwords + w];
+      r += c.tables[(2 * w) * kGroupEntries + (s & 0xFFFu)];
+      if (2 * w + 1 < c.ngroups) r += c.tables[(2 * w + 1) * kGroupEntries + ((s >> 16) & 0xFFFu)];
+    }
+  }
+  return r;
+}
+
+__global__ void k_pair_ranks(RankCtx c, int N, int32_t* __restrict__ out) {
+  const int64_t total = (int64_t)N * N;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / N), j = (int)(e % N);
+    out[e] = rank_of_sum(c, i, j);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Operand preparation
+// ---------------------------------------------------------------------------
+struct PrepArgs {
+  const void* W;       // N x k, ld k (double for FP64 plans, float otherwise)
+  int N, k;
+  int64_t Np, Kp;      // forward copies: rows Np, ld Kp
+  int64_t Kp2, Np2;    // transposed copies: rows Kp2, ld Np2
+  void* a_hi; void* a_lo; float* a_f32;
+  void* t_hi; void* t_lo;
+};
+
+// 64 x 64 tiles through LDS so that both the row-major and the transposed
+// copies are written with coalesced stores.  Mode: 0 = FP64, 1 = FP32,
+// 2 = bf16 hi/lo split (plus the FP32 copy when a_f32 != nullptr).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
+  using WT = typename std::conditional<MODE == 0, double, float>::type;
+  __shared__ WT tile[64][65];
+  const int64_t i0 = (int64_t)blockIdx.y * 64, l0 = (int64_t)blockIdx.x * 64;
+  const WT* W = (const WT*)a.W;
+  const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
+  for (int r = ty; r < 64; r += 4) {
+    const int64_t i = i0 + r, l = l0 + tx;
+    WT v = 0;
+    if (i < a.N && l < a.k) v = W[i * a.k + l];
+    tile[r][tx] = v;
+    if (i < a.Np && l < a.Kp) {
+      const int64_t o = i * a.Kp + l;
+      if (MODE == 0) ((double*)a.a_hi)[o] = (double)v;
+      else if (MODE == 1) ((float*)a.a_hi)[o] = (float)v;
+      else {
+        const __bf16 h = (__bf16)(float)v;
+        ((__bf16*)a.a_hi)[o] = h;
+        ((__bf16*)a.a_lo)[o] = (__bf16)((float)v - (float)h);
+        if (a.a_f32) a.a_f32[o] = (float)v;
+      }
+    }
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int64_t l = l0 + r, i = i0 + tx;
+    if (l < a.Kp2 && i < a.Np2) {
+      const WT v = tile[tx][r];
+      const int64_t o = l * a.Np2 + i;
+      if (MODE == 0) ((double*)a.t_hi)[o] = (double)v;
+      else if (MODE == 1) ((float*)a.t_hi)[o] = (float)v;
+      else {
+        const __bf16 h = (__bf16)(float)v;
+        ((__bf16*)a.t_hi)[o] = h;
+        ((__bf16*)a.t_lo)[o] = (__bf16)((float)v - (float)h);
+      }
+    }
+  }
+}
+
+__global__ void k_init_r(const double* __restrict__ p, double* __restrict__ r, int64_t M) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < M;
+       e += (int64_t)gridDim.x * blockDim.x)
+    r[e] = -p[e];
+}
+
+// ---------------------------------------------------------------------------
+// Sum of squares (deterministic: fixed grid, fixed order)
+// ---------------------------------------------------------------------------
+constexpr int kSumBlocks = 512;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ double block_sum(double v) {
+  __shared__ double part[16];
+  v = wave_sum(v);
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  if (l == 0) part[w] = v;
+  __syncthreads();
+  double s = 0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < (int)(blockDim.x / 64); ++q) s += part[q];
+  return s;
+}
+
+__global__ __launch_bounds__(256) void k_sumsq_partial(const double* __restrict__ x, int64_t M,
+                                                       double* __restrict__ partial) {
+  double s = 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < M;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const double v = x[e];
+    s += v * v;
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_sumsq_final(const double* __restrict__ partial,
+                                                     double* __restrict__ out) {
+  double s = 0;
+  for (int q = threadIdx.x; q < kSumBlocks; q += blockDim.x) s += partial[q];
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Tiled NT GEMM core: 128 x 128 output tile, 256 threads = 4 waves (2 x 2),
+// each wave 64 x 64.  Operands staged through double-buffered LDS.
+// ---------------------------------------------------------------------------
+constexpr int BM = 128;
+constexpr int kThreads = 256;
+
+// Mode F64: double operands, f64 16x16x4 MFMA.  Output of one 16x16 block:
+// lane l, register q holds row (l / 16) + 4 q, column l % 16.
+struct MF64 {
+  using GT = double;  // global operand element
+  using LT = double;  // LDS element
+  static constexpr int NARR = 1;
+  static constexpr int BK = 16;
+  static constexpr int LDS_LD = BK + 2;  // elements per LDS row (padded)
+  static constexpr int NACC = 64;        // doubles per lane
+  using Acc = double;
+};
+// Mode EXACT: float operands in memory, converted exactly to double, f64 MFMA.
+struct MEX : MF64 {
+  using GT = float;
+};
+// Mode F32: float operands, f32 32x32x2 MFMA.  Output of one 32x32 block:
+// lane l, register q holds row (q / 4) * 8 + (l / 32) * 4 + q % 4, column l % 32.
+struct MF32 {
+  using GT = float;
+  using LT = float;
+  static constexpr int NARR = 1;
+  static constexpr int BK = 32;
+  static constexpr int LDS_LD = BK + 4;
+  static constexpr int NACC = 64;
+  using Acc = float;
+};
+// Mode BF3: bf16 hi and lo arrays, three 32x32x16 bf16 MFMA products.
+struct MBF3 {
+  using GT = __bf16;
+  using LT = __bf16;
+  static constexpr int NARR = 2;
+  static constexpr int BK = 32;
+  static constexpr int LDS_LD = BK + 8;
+  static constexpr int NACC = 64;
+  using Acc = float;
+};
+
+template <class Md>
+struct Stage {
+  // one operand tile: NARR arrays of BM rows x LDS_LD elements
+  typename Md::LT a[Md::NARR][BM * Md::LDS_LD];
+  typename Md::LT b[Md::NARR][BM * Md::LDS_LD];
+};
+
+// global -> registers -> LDS.  The tile is BM rows of BK elements; each thread
+// moves 16-byte chunks of the global rows.
+template <class Md>
+struct Loader {
+  using GT = typename Md::GT;
+  using LT = typename Md::LT;
+  static constexpr int ROW_BYTES = Md::BK * (int)sizeof(GT);
+  static constexpr int CPR = ROW_BYTES / 16;                       // chunks per row
+  static constexpr int CHUNKS = BM * CPR;                          // per array
+  static constexpr int PER_THREAD = CHUNKS / kThreads;
+  static constexpr int EPC = 16 / (int)sizeof(GT);                 // elements per chunk
+  static_assert(CHUNKS % kThreads == 0, "tile must split evenly");
+  uint4 reg[Md::NARR][PER_THREAD];
+
+  __device__ __forceinline__ void load(const GT* const* base, int64_t ld, int64_t row0, int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < Md::NARR; ++q)
+#pragma unroll
+      for (int c = 0; c < PER_THREAD; ++c) {
+        const int ch = threadIdx.x + c * kThreads;
+        const int row = ch / CPR, cc = ch % CPR;
+        reg[q][c] = *(const uint4*)(base[q] + (row0 + row) * ld + k0 + cc * EPC);
+      }
+  }
+  __device__ __forceinline__ void store(LT (*dst)[BM * Md::LDS_LD]) {
+#pragma unroll
+    for (int q = 0; q < Md::NARR; ++q)
+#pragma unroll
+      for (int c = 0; c < PER_THREAD; ++c) {
+        const int ch = threadIdx.x + c * kThreads;
+        const int row = ch / CPR, cc = ch % CPR;
+        LT* d = &dst[q][row * Md::LDS_LD + cc * EPC];
+        if constexpr (sizeof(GT) == sizeof(LT)) {
+          *(uint4*)d = reg[q][c];
+        } else {  // float -> double, exact
+          const float* f = (const float*)&reg[q][c];
+#pragma unroll
+          for (int e = 0; e < EPC; ++e) d[e] = (double)f[e];
+        }
+      }
+  }
+};
+
+// MFMA over one LDS stage.  acc is the wave's 64 x 64 block, NACC per lane.
+template <class Md>
+__device__ __forceinline__ void mma_stage(const Stage<Md>& s, typename Md::Acc* acc, int wm, int wn);
+
+template <>
+__device__ __forceinline__ void mma_stage<MF64>(const Stage<MF64>& s, double* acc, int wm, int wn) {
+  const int l = threadIdx.x % 64;
+#pragma unroll
+  for (int kk = 0; kk < MF64::BK / 4; ++kk) {
+    double a[4], b[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      a[q] = s.a[0][(wm * 64 + q * 16 + l % 16) * MF64::LDS_LD + kk * 4 + l / 16];
+      b[q] = s.b[0][(wn * 64 + q * 16 + l % 16) * MF64::LDS_LD + kk * 4 + l / 16];
+    }
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) {
+        f64x4 c;
+        double* p = acc + (bi * 4 + bj) * 4;
+        c[0] = p[0]; c[1] = p[1]; c[2] = p[2]; c[3] = p[3];
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], c, 0, 0, 0);
+        p[0] = c[0]; p[1] = c[1]; p[2] = c[2]; p[3] = c[3];
+      }
+  }
+}
+
+template <>
+__device__ __forceinline__ void mma_stage<MEX>(const Stage<MEX>& s, double* acc, int wm, int wn) {
+  mma_stage<MF64>(reinterpret_cast<const Stage<MF64>&>(s), acc, wm, wn);
+}
+
+template <>
+__device__ __forceinline__ void mma_stage<MF32>(const Stage<MF32>& s, float* acc, int wm, int wn) {
+  const int l = threadIdx.x % 64;
+#pragma unroll
+  for (int kk = 0; kk < MF32::BK / 2; ++kk) {
+    float a[2], b[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      a[q] = s.a[0][(wm * 64 + q * 32 + l % 32) * MF32::LDS_LD + kk * 2 + l / 32];
+      b[q] = s.b[0][(wn * 64 + q * 32 + l % 32) * MF32::LDS_LD + kk * 2 + l / 32];
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        f32x16 c;
+        float* p = acc + (bi * 2 + bj) * 16;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) c[e] = p[e];
+        c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[bi], b[bj], c, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) p[e] = c[e];
+      }
+  }
+}
+
+template <>
+__device__ __forceinline__ void mma_stage<MBF3>(const Stage<MBF3>& s, float* acc, int wm, int wn) {
+  const int l = threadIdx.x % 64;
+#pragma unroll
+  for (int kk = 0; kk < MBF3::BK / 16; ++kk) {
+    bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int ra = (wm * 64 + q * 32 + l % 32) * MBF3::LDS_LD + kk * 16 + (l / 32) * 8;
+      const int rb = (wn * 64 + q * 32 + l % 32) * MBF3::LDS_LD + kk * 16 + (l / 32) * 8;
+      ah[q] = *(const bf16x8*)&s.a[0][ra];
+      al[q] = *(const bf16x8*)&s.a[1][ra];
+      bh[q] = *(const bf16x8*)&s.b[0][rb];
+      bl[q] = *(const bf16x8*)&s.b[1][rb];
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        f32x16 c;
+        float* p = acc + (bi * 2 + bj) * 16;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) c[e] = p[e];
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[bi], bh[bj], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bl[bj], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bh[bj], c, 0, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) p[e] = c[e];
+      }
+  }
+}
+
+// (row, col) inside the wave's 64 x 64 block of accumulator element e.
+template <class Md>
+__device__ __forceinline__ void acc_pos(int e, int& row, int& col) {
+  const int l = threadIdx.x % 64;
+  if constexpr (Md::BK == 16) {  // f64 16x16 blocks, 4 x 4 of them
+    const int blk = e / 4, q = e % 4;
+    row = (blk / 4) * 16 + l / 16 + 4 * q;
+    col = (blk % 4) * 16 + l % 16;
+  } else {  // 32x32 blocks, 2 x 2 of them
+    const int blk = e / 16, q = e % 16;
+    row = (blk / 2) * 32 + (q / 4) * 8 + (l / 32) * 4 + q % 4;
+    col = (blk % 2) * 32 + l % 32;
+  }
+}
+
+template <class Md>
+__device__ __forceinline__ void gemm_tile(const typename Md::GT* const* A, const typename Md::GT* const* B,
+                                          int64_t ld, int64_t K, int64_t a_row0, int64_t b_row0,
+                                          Stage<Md>* st, typename Md::Acc* acc) {
+  const int wave = threadIdx.x / 64;
+  const int wm = wave / 2, wn = wave % 2;
+#pragma unroll
+  for (int e = 0; e < Md::NACC; ++e) acc[e] = 0;
+  Loader<Md> la, lb;
+  la.load(A, ld, a_row0, 0);
+  lb.load(B, ld, b_row0, 0);
+  la.store(st[0].a);
+  lb.store(st[0].b);
+  __syncthreads();
+  const int64_t nk = K / Md::BK;
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    if (kt + 1 < nk) {
+      la.load(A, ld, a_row0, (kt + 1) * Md::BK);
+      lb.load(B, ld, b_row0, (kt + 1) * Md::BK);
+    }
+    mma_stage<Md>(st[cur], acc, wm, wn);
+    if (kt + 1 < nk) {
+      la.store(st[cur ^ 1].a);
+      lb.store(st[cur ^ 1].b);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Forward: gram tiles over the upper triangle, scattered into r.
+// ---------------------------------------------------------------------------
+struct GramArgs {
+  const void* A[2];   // operand arrays (hi[, lo]); rows Np, ld Kp
+  int64_t ld, K;      // ld = K = Kp
+  int N, T;           // T = Np / BM tiles per side
+  RankCtx rk;
+  double* r;
+};
+
+__device__ __forceinline__ void tri_tile(int b, int& I, int& J) {
+  // b -> (I, J), I <= J, enumerating column J = 0, 1, ... with I = 0..J
+  int j = (int)((sqrtf(8.0f * (float)b + 1.0f) - 1.0f) * 0.5f);
+  while ((j + 1) * (j + 2) / 2 <= b) ++j;
+  while (j * (j + 1) / 2 > b) --j;
+  J = j;
+  I = b - j * (j + 1) / 2;
+}
+
+template <class Md>
+__global__ __launch_bounds__(kThreads) void k_gram(GramArgs g) {
+  extern __shared__ __align__(16) char smem[];
+  Stage<Md>* st = (Stage<Md>*)smem;
+  int I, J;
+  tri_tile(blockIdx.x, I, J);
+  const typename Md::GT* ops[2] = {(const typename Md::GT*)g.A[0], (const typename Md::GT*)g.A[1]};
+  typename Md::Acc acc[Md::NACC];
+  gemm_tile<Md>(ops, ops, g.ld, g.K, (int64_t)I * BM, (int64_t)J * BM, st, acc);
+  const int wave = threadIdx.x / 64;
+  const int wm = wave / 2, wn = wave % 2;
+#pragma unroll
+  for (int e = 0; e < Md::NACC; ++e) {
+    int row, col;
+    acc_pos<Md>(e, row, col);
+    const int i = I * BM + wm * 64 + row, j = J * BM + wn * 64 + col;
+    if (i < g.N && j < g.N && i <= j) {
+      const double w = (i == j) ? 1.0 : 2.0;
+      unsafeAtomicAdd(g.r + rank_of_sum(g.rk, i, j), w * (double)acc[e]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Backward: R from r, then g = 4 R W.
+// ---------------------------------------------------------------------------
+template <int MODE>  // 0 FP64, 1 FP32, 2 bf16 hi/lo
+__global__ __launch_bounds__(256) void k_gather(RankCtx rk, const double* __restrict__ r, int N,
+                                                int64_t Np, int64_t ld, void* R_hi, void* R_lo) {
+  const int64_t total = Np * ld;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / ld), j = (int)(e % ld);
+    double v = 0.0;
+    if (i < N && j < N) v = r[rank_of_sum(rk, i, j)];
+    if (MODE == 0) ((double*)R_hi)[e] = v;
+    else if (MODE == 1) ((float*)R_hi)[e] = (float)v;
+    else {
+      const float f = (float)v;
+      const __bf16 h = (__bf16)f;
+      ((__bf16*)R_hi)[e] = h;
+      ((__bf16*)R_lo)[e] = (__bf16)(f - (float)h);
+    }
+  }
+}
+
+struct RwArgs {
+  const void* A[2];   // R arrays: rows Np, ld K
+  const void* B[2];   // W^T arrays: rows Kp2, ld K
+  int64_t K;          // = Np2
+  int N, k;
+  void* g;            // N x k, ld k (double or float)
+  bool g_double;
+};
+
+template <class Md>
+__global__ __launch_bounds__(kThreads) void k_rw(RwArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  Stage<Md>* st = (Stage<Md>*)smem;
+  const int I = blockIdx.y, Lt = blockIdx.x;
+  const typename Md::GT* A[2] = {(const typename Md::GT*)a.A[0], (const typename Md::GT*)a.A[1]};
+  const typename Md::GT* B[2] = {(const typename Md::GT*)a.B[0], (const typename Md::GT*)a.B[1]};
+  typename Md::Acc acc[Md::NACC];
+  gemm_tile<Md>(A, B, a.K, a.K, (int64_t)I * BM, (int64_t)Lt * BM, st, acc);
+  const int wave = threadIdx.x / 64;
+  const int wm = wave / 2, wn = wave % 2;
+#pragma unroll
+  for (int e = 0; e < Md::NACC; ++e) {
+    int row, col;
+    acc_pos<Md>(e, row, col);
+    const int i = I * BM + wm * 64 + row, l = Lt * BM + wn * 64 + col;
+    if (i < a.N && l < a.k) {
+      const double v = 4.0 * (double)acc[e];
+      if (a.g_double) ((double*)a.g)[(int64_t)i * a.k + l] = v;
+      else ((float*)a.g)[(int64_t)i * a.k + l] = (float)v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adam (bias-corrected), in place.  bc1 = 1 - b1^t, bc2 = 1 - b2^t.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void k_adam(T* __restrict__ W, T* __restrict__ m, T* __restrict__ v,
+                                              const T* __restrict__ g, int64_t n, T lr, T b1, T b2,
+                                              T eps, T bc1, T bc2) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const T ge = g[e];
+    const T me = b1 * m[e] + (T(1) - b1) * ge;
+    const T ve = b2 * v[e] + (T(1) - b2) * ge * ge;
+    m[e] = me;
+    v[e] = ve;
+    W[e] -= lr * (me / bc1) / (sqrt(ve / bc2) + eps);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static inline int grid_for(int64_t n, int threads = 256, int cap = 65536) {
+  int64_t b = (n + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (int)b;
+}
+
+static RankCtx rank_ctx(const sos_plan_s* p) {
+  RankCtx c;
+  c.codes = (const uint32_t*)(p->ws + p->lay.codes);
+  c.tables = (const int32_t*)(p->ws + p->lay.tables);
+  c.nwords = p->nwords;
+  c.ngroups = p->ngroups;
+  return c;
+}
+
+hipError_t launch_pair_ranks(const sos_plan_s* p, int32_t* out, hipStream_t s) {
+  k_pair_ranks<<<grid_for(p->N * p->N), 256, 0, s>>>(rank_ctx(p), (int)p->N, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep(const sos_plan_s* p, const void* W, bool want_f32, hipStream_t s) {
+  PrepArgs a;
+  a.W = W; a.N = (int)p->N; a.k = p->k;
+  a.Np = p->Np; a.Kp = p->Kp; a.Kp2 = p->Kp2; a.Np2 = p->Np2;
+  a.a_hi = p->ws + p->lay.a_hi;
+  a.a_lo = p->prec == SOS_BF16X3 ? p->ws + p->lay.a_lo : nullptr;
+  a.a_f32 = (p->prec == SOS_BF16X3 && want_f32) ? (float*)(p->ws + p->lay.a_f32) : nullptr;
+  a.t_hi = p->ws + p->lay.t_hi;
+  a.t_lo = p->prec == SOS_BF16X3 ? p->ws + p->lay.t_lo : nullptr;
+  const int64_t rows = p->Np > p->Np2 ? p->Np : p->Np2;
+  const int64_t cols = p->Kp2 > p->Kp ? p->Kp2 : p->Kp;
+  dim3 grid((unsigned)(cols / 64), (unsigned)(rows / 64));
+  if (p->prec == SOS_FP64) k_prep<0><<<grid, 256, 0, s>>>(a);
+  else if (p->prec == SOS_FP32) k_prep<1><<<grid, 256, 0, s>>>(a);
+  else k_prep<2><<<grid, 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_r(const sos_plan_s* p, const double* d_p, hipStream_t s) {
+  k_init_r<<<grid_for(p->M), 256, 0, s>>>(d_p, (double*)(p->ws + p->lay.r), p->M);
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq(const sos_plan_s* p, const double* x, int64_t M, double* out, hipStream_t s) {
+  double* partial = (double*)(p->ws + p->lay.scal) + 8;
+  k_sumsq_partial<<<kSumBlocks, 256, 0, s>>>(x, M, partial);
+  k_sumsq_final<<<1, 256, 0, s>>>(partial, out);
+  return hipGetLastError();
+}
+
+template <class Md>
+static hipError_t gram_launch(const sos_plan_s* p, const void* a0, const void* a1, hipStream_t s) {
+  GramArgs g;
+  g.A[0] = a0; g.A[1] = a1;
+  g.ld = p->Kp; g.K = p->Kp;
+  g.N = (int)p->N;
+  g.T = (int)(p->Np / BM);
+  g.rk = rank_ctx(p);
+  g.r = (double*)(p->ws + p->lay.r);
+  const int tiles = g.T * (g.T + 1) / 2;
+  const size_t sm = 2 * sizeof(Stage<Md>);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_gram<Md>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  k_gram<Md><<<tiles, kThreads, sm, s>>>(g);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram(const sos_plan_s* p, bool exact, hipStream_t s) {
+  const char* ws = p->ws;
+  if (p->prec == SOS_FP64) return gram_launch<MF64>(p, ws + p->lay.a_hi, nullptr, s);
+  if (exact) {
+    const void* a = (p->prec == SOS_FP32) ? ws + p->lay.a_hi : ws + p->lay.a_f32;
+    return gram_launch<MEX>(p, a, nullptr, s);
+  }
+  if (p->prec == SOS_FP32) return gram_launch<MF32>(p, ws + p->lay.a_hi, nullptr, s);
+  return gram_launch<MBF3>(p, ws + p->lay.a_hi, ws + p->lay.a_lo, s);
+}
+
+template <class Md>
+static hipError_t rw_launch(const sos_plan_s* p, void* g, hipStream_t s) {
+  RwArgs a;
+  const char* ws = p->ws;
+  a.A[0] = ws + p->lay.R_hi; a.A[1] = p->prec == SOS_BF16X3 ? ws + p->lay.R_lo : nullptr;
+  a.B[0] = ws + p->lay.t_hi; a.B[1] = p->prec == SOS_BF16X3 ? ws + p->lay.t_lo : nullptr;
+  a.K = p->Np2; a.N = (int)p->N; a.k = p->k;
+  a.g = g; a.g_double = (p->prec == SOS_FP64);
+  const size_t sm = 2 * sizeof(Stage<Md>);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_rw<Md>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  dim3 grid((unsigned)(p->Kp2 / BM), (unsigned)(p->Np / BM));
+  k_rw<Md><<<grid, kThreads, sm, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_backward(const sos_plan_s* p, void* g, hipStream_t s) {
+  char* ws = p->ws;
+  const RankCtx rk = rank_ctx(p);
+  const double* r = (const double*)(ws + p->lay.r);
+  const int64_t total = p->Np * p->Np2;
+  void* Rh = ws + p->lay.R_hi;
+  void* Rl = p->prec == SOS_BF16X3 ? ws + p->lay.R_lo : nullptr;
+  if (p->prec == SOS_FP64) k_gather<0><<<grid_for(total), 256, 0, s>>>(rk, r, (int)p->N, p->Np, p->Np2, Rh, Rl);
+  else if (p->prec == SOS_FP32) k_gather<1><<<grid_for(total), 256, 0, s>>>(rk, r, (int)p->N, p->Np, p->Np2, Rh, Rl);
+  else k_gather<2><<<grid_for(total), 256, 0, s>>>(rk, r, (int)p->N, p->Np, p->Np2, Rh, Rl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (p->prec == SOS_FP64) return rw_launch<MF64>(p, g, s);
+  if (p->prec == SOS_FP32) return rw_launch<MF32>(p, g, s);
+  return rw_launch<MBF3>(p, g, s);
+}
+
+hipError_t launch_adam(const sos_plan_s* p, void* W, void* m, void* v, const void* g, int64_t t,
+                       const sos_adam_t& h, hipStream_t s) {
+  const int64_t n = p->N * (int64_t)p->k;
+  const double bc1 = 1.0 - pow(h.beta1, (double)t), bc2 = 1.0 - pow(h.beta2, (double)t);
+  if (p->prec == SOS_FP64)
+    k_adam<double><<<grid_for(n), 256, 0, s>>>((double*)W, (double*)m, (double*)v, (const double*)g, n,
+                                               h.lr, h.beta1, h.beta2, h.eps, bc1, bc2);
+  else
+    k_adam<float><<<grid_for(n), 256, 0, s>>>((float*)W, (float*)m, (float*)v, (const float*)g, n,
+                                              (float)h.lr, (float)h.beta1, (float)h.beta2, (float)h.eps,
+                                              (float)bc1, (float)bc2);
+  return hipGetLastError();
+}
+
+}  // namespace sos

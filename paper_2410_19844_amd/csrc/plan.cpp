@@ -1,0 +1,164 @@
+// Host-side plan: monomial bases, the additive ranking code, rank tables and
+// the workspace layout.
+//
+// Ranking (Section 1.1 order).  Monomials of degree <= D in n variables are
+// ordered by total degree (higher first), then lexicographically (larger
+// exponent vector first, x1 most significant).  For gamma with t = |gamma|
+// and suffix sums u_f = gamma_{f+1} + ... + gamma_n (f = 1..n-1), the
+// position of gamma is
+//
+//   rank_D(gamma) = [C(D+n, n) - C(t+n, n)]                  (all higher degrees)
+//                 + sum_{f=1}^{n-1} C(u_f + n-f-1, n-f)      (same degree, lex-larger)
+//
+// The f-th term counts the degree-t monomials that agree with gamma on
+// x1..x_{f-1} and have a larger exponent of x_f: their remaining u_f - 1 - s
+// units (s >= 0) are spread over n-f variables, and summing the counts over s
+// gives C(u_f + n-f-1, n-f).  Every term depends on one field of the code
+// (t or one u_f), which is what makes per-group table lookups possible.
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+#include "sos_internal.h"
+
+namespace sos {
+
+static int64_t binom(int64_t a, int64_t b) {
+  if (b < 0 || a < b) return 0;
+  b = std::min(b, a - b);
+  int64_t r = 1;
+  for (int64_t i = 1; i <= b; ++i) r = r * (a - b + i) / i;
+  return r;
+}
+
+static void compositions(int n, int v, int left, std::vector<uint8_t>& cur, std::vector<uint8_t>& out) {
+  if (v == n - 1) {
+    cur[v] = (uint8_t)left;
+    out.insert(out.end(), cur.begin(), cur.end());
+    return;
+  }
+  for (int e = left; e >= 0; --e) {  // larger exponent of x_{v+1} first
+    cur[v] = (uint8_t)e;
+    compositions(n, v + 1, left - e, cur, out);
+  }
+}
+
+void enumerate_monomials(int n, int D, std::vector<uint8_t>& out) {
+  out.clear();
+  std::vector<uint8_t> cur(n, 0);
+  for (int t = D; t >= 0; --t) compositions(n, 0, t, cur, out);
+}
+
+static int64_t field_term(int n, int D, int f, int value) {
+  if (f == 0) return binom(D + n, n) - binom(value + n, n);
+  return binom(value + n - f - 1, n - f);
+}
+
+int64_t rank_closed_form(int n, int D, const uint8_t* e) {
+  int t = 0;
+  for (int v = 0; v < n; ++v) t += e[v];
+  int64_t r = field_term(n, D, 0, t);
+  int u = t;
+  for (int f = 1; f < n; ++f) {
+    u -= e[f - 1];
+    r += field_term(n, D, f, u);
+  }
+  return r;
+}
+
+static inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+int plan_create(int n, int d, int rank, int prec, sos_plan_s** out) {
+  if (!out) return set_error(SOS_EINVAL, "sos_plan: out is NULL");
+  *out = nullptr;
+  if (n < 1 || d < 1 || rank < 1)
+    return set_error(SOS_EINVAL, "sos_plan: n, d and rank must be >= 1");
+  if (prec != SOS_FP64 && prec != SOS_FP32 && prec != SOS_BF16X3)
+    return set_error(SOS_EINVAL, "sos_plan: unknown precision");
+  if (2 * d > 15 || n > 16)
+    return set_error(SOS_ERANGE, "sos_plan: needs 2d <= 15 and n <= 16 (4-bit code fields)");
+  const int64_t N = binom(n + d, d), M = binom(n + 2 * d, 2 * d);
+  if (M >= (int64_t(1) << 31) || N * N >= (int64_t(1) << 31))
+    return set_error(SOS_ERANGE, "sos_plan: M and N*N must stay below 2^31");
+  if ((int64_t)rank * N >= (int64_t(1) << 34))
+    return set_error(SOS_ERANGE, "sos_plan: N*rank too large");
+
+  sos_plan_s* p = new (std::nothrow) sos_plan_s;
+  if (!p) return set_error(SOS_ENOMEM, "sos_plan: host allocation failed");
+  p->n = n; p->d = d; p->k = rank; p->prec = prec; p->N = N; p->M = M;
+  p->ngroups = (n + kFieldsPerGroup - 1) / kFieldsPerGroup;
+  p->nwords = (p->ngroups + 1) / 2;
+
+  enumerate_monomials(n, d, p->basis);
+  if ((int64_t)p->basis.size() != N * n) {
+    delete p;
+    return set_error(SOS_EINVAL, "sos_plan: internal enumeration count mismatch");
+  }
+
+  // codes
+  p->codes.assign(N * p->nwords, 0u);
+  for (int64_t i = 0; i < N; ++i) {
+    const uint8_t* e = &p->basis[i * n];
+    int t = 0;
+    for (int v = 0; v < n; ++v) t += e[v];
+    int u = t;
+    for (int f = 0; f < n; ++f) {
+      if (f > 0) u -= e[f - 1];
+      const int val = (f == 0) ? t : u;
+      const int g = f / kFieldsPerGroup, w = g / 2;
+      const int shift = (g % 2) * 16 + (f % kFieldsPerGroup) * 4;
+      p->codes[i * p->nwords + w] |= (uint32_t)val << shift;
+    }
+  }
+  // tables: T_g[idx] = sum over the group's fields of field_term(field value)
+  const int D = 2 * d;
+  p->tables.assign((size_t)p->ngroups * kGroupEntries, 0);
+  for (int g = 0; g < p->ngroups; ++g) {
+    for (int idx = 0; idx < kGroupEntries; ++idx) {
+      int64_t s = 0;
+      bool valid = true;
+      for (int q = 0; q < kFieldsPerGroup; ++q) {
+        const int f = g * kFieldsPerGroup + q;
+        const int val = (idx >> (4 * q)) & 15;
+        if (f >= n) {
+          if (val != 0) valid = false;
+          continue;
+        }
+        if (val > D) valid = false;
+        else s += field_term(n, D, f, val);
+      }
+      p->tables[(size_t)g * kGroupEntries + idx] = valid ? (int32_t)s : 0;
+    }
+  }
+
+  // padded extents and workspace layout
+  p->Np = round_up(N, kPadRows);
+  p->Kp = round_up(rank, kPadK);
+  p->Np2 = round_up(N, kPadK);
+  p->Kp2 = round_up(rank, kPadRows);
+  const size_t wel = (prec == SOS_FP64) ? 8 : 4;          // W / gradient element
+  const size_t oel = (prec == SOS_FP64) ? 8 : (prec == SOS_FP32 ? 4 : 2);  // operand element
+  Layout& L = p->lay;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = round_up(off + bytes, 256); return o; };
+  L.codes = take((size_t)N * p->nwords * 4);
+  L.tables = take(p->tables.size() * 4);
+  L.r = take((size_t)M * 8);
+  L.scal = take(1024 * 8);   // [0..7] scalars, [8..519] reduction partials
+  L.a_hi = take((size_t)p->Np * p->Kp * oel);
+  if (prec == SOS_BF16X3) L.a_lo = take((size_t)p->Np * p->Kp * oel);
+  L.t_hi = take((size_t)p->Kp2 * p->Np2 * oel);
+  if (prec == SOS_BF16X3) L.t_lo = take((size_t)p->Kp2 * p->Np2 * oel);
+  L.R_hi = take((size_t)p->Np * p->Np2 * oel);
+  if (prec == SOS_BF16X3) L.R_lo = take((size_t)p->Np * p->Np2 * oel);
+  // split-precision plans keep an FP32 padded copy of W for the exact FP64 forward
+  // (FP32 plans use a_hi, which already is that copy)
+  if (prec == SOS_BF16X3) L.a_f32 = take((size_t)p->Np * p->Kp * 4);
+  L.g = take((size_t)N * rank * wel);
+  L.bytes = off;
+  p->state_bytes = round_up((size_t)N * rank * wel, 256) * 4;  // m, v, best W, candidate W
+  *out = p;
+  return SOS_OK;
+}
+
+}  // namespace sos

@@ -1,0 +1,86 @@
+// Internal declarations shared by the host plan, the C ABI and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sos.h"
+
+namespace sos {
+
+// Ranking code layout.  Every basis monomial alpha gets n 4-bit fields:
+//   field 0 = |alpha|, field f (1..n-1) = alpha_{f+1} + ... + alpha_n
+// (suffix sums).  Fields are additive, and with 2d <= 15 the sum of two
+// codes never carries out of a field, so code(alpha_i) + code(alpha_j) is
+// the code of alpha_i + alpha_j.  Fields are packed three to a 12-bit group;
+// each 32-bit word holds two groups in its two 16-bit halves.  The rank of a
+// degree-<=2d monomial is a sum over groups of a 4096-entry table lookup
+// (see plan.cpp for the closed form the tables hold).
+constexpr int kFieldsPerGroup = 3;
+constexpr int kGroupEntries = 4096;
+constexpr int kMaxWords = 3;     // n <= 16  ->  at most 6 groups
+
+// Tile sizes shared by host (padding, grids) and device.
+constexpr int kPadRows = 256;    // operand rows padded to this multiple (zero rows)
+constexpr int kPadK = 64;        // operand K extents padded to this multiple (zero columns)
+
+struct Layout {
+  // byte offsets into the workspace
+  size_t codes = 0, tables = 0, r = 0, scal = 0;
+  size_t a_hi = 0, a_lo = 0;     // W operand copies, rows = Np, ld = Kp   (forward A/B)
+  size_t t_hi = 0, t_lo = 0;     // W^T operand copies, rows = Kp2, ld = Np2 (backward B)
+  size_t R_hi = 0, R_lo = 0;     // R operand, rows = Np, ld = Np2           (backward A)
+  size_t a_f32 = 0;              // FP32 padded W (split-precision plans), rows = Np, ld = Kp
+  size_t g = 0;                  // gradient scratch, N x k in W's type
+  size_t bytes = 0;
+};
+
+}  // namespace sos
+
+struct sos_plan_s {
+  int n = 0, d = 0, k = 0, prec = 0;
+  int64_t N = 0, M = 0;
+  int ngroups = 0, nwords = 0;
+  std::vector<uint8_t> basis;      // N x n exponents, library order
+  std::vector<uint32_t> codes;     // N x nwords
+  std::vector<int32_t> tables;     // ngroups x 4096
+  // padded extents
+  int64_t Np = 0;    // N rounded up to kPadRows   (rows of W copies, rows of R)
+  int64_t Kp = 0;    // k rounded up to kPadK      (ld of W copies)
+  int64_t Np2 = 0;   // N rounded up to kPadK      (ld of R and W^T copies)
+  int64_t Kp2 = 0;   // k rounded up to kPadRows   (rows of W^T copies)
+  sos::Layout lay;
+  size_t state_bytes = 0;
+  char* ws = nullptr;
+  size_t ws_size = 0;
+  bool bound = false;
+};
+
+namespace sos {
+
+// host plan (plan.cpp)
+int plan_create(int n, int d, int rank, int prec, sos_plan_s** out);
+void enumerate_monomials(int n, int D, std::vector<uint8_t>& out);  // library order
+int64_t rank_closed_form(int n, int D, const uint8_t* e);
+
+// error handling (api.cpp)
+int set_error(int code, const std::string& msg);
+int hip_error(hipError_t e, const char* what);
+
+}  // namespace sos
+
+namespace sos {
+// kernel launchers (kernels.hip)
+hipError_t launch_pair_ranks(const sos_plan_s* p, int32_t* out, hipStream_t s);
+hipError_t launch_prep(const sos_plan_s* p, const void* W, bool want_f32, hipStream_t s);
+hipError_t launch_init_r(const sos_plan_s* p, const double* d_p, hipStream_t s);
+hipError_t launch_sumsq(const sos_plan_s* p, const double* x, int64_t M, double* out, hipStream_t s);
+hipError_t launch_gram(const sos_plan_s* p, bool exact, hipStream_t s);
+hipError_t launch_backward(const sos_plan_s* p, void* g, hipStream_t s);
+hipError_t launch_adam(const sos_plan_s* p, void* W, void* m, void* v, const void* g, int64_t t,
+                       const sos_adam_t& h, hipStream_t s);
+}  // namespace sos
