@@ -1,0 +1,183 @@
+"""Benchmark of the SOS hot path on one MI355X.
+
+Default: one Adam step of the whole path (split, gram-scatter forward, loss,
+R gather, R W backward, Adam) at n=12, d=6 (N = 18,564 basis monomials,
+M = 2,704,156 coefficients, rank k = N), split-bf16 contractions, FP32
+master W, FP64 residual.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--precision bf16x3|fp32|fp64]
+                  [--workload n12d6|n10d5|n6d4] [--exact] [--no-cpu-baseline]
+                  [--mode step|ttt] [--tol 1e-8] [--max-steps S]
+
+--mode ttt runs sos_solve from the same start to an FP64-verified relative
+residual <= tol and reports the time to target instead of steps/s.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAKS_TFLOPS = {"bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6}
+DTYPE = {"bf16x3": "bf16", "fp32": "fp32", "fp64": "fp64"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="bf16x3", choices=list(PEAKS_TFLOPS))
+    ap.add_argument("--workload", default="n12d6")
+    ap.add_argument("--exact", action="store_true", help="FP64 forward (the finishing phase)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=1024)
+    ap.add_argument("--mode", default="step", choices=["step", "ttt"])
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--max-steps", type=int, default=3000)
+    ap.add_argument("--lr", type=float, default=None)
+    return ap.parse_args()
+
+
+def make_inputs(S, torch, wl, prec):
+    """W0 -> p on the GPU (exact FP64 forward of the FP32-rounded W0), W init."""
+    dev = torch.device("cuda")
+    from workloads import CONFIGS
+    c = CONFIGS[wl]
+    W0 = torch.tensor(c.W0(), dtype=torch.float32, device=dev)
+    pl0 = S.Plan(c.n, c.d, c.w0_rank, "fp32")
+    zeros = torch.zeros(c.M, dtype=torch.float64, device=dev)
+    _, _, p = pl0.loss_grad(W0, zeros, grad=False, want_r=True, exact=True)
+    del pl0, W0, zeros
+    wdt = torch.float64 if prec == "fp64" else torch.float32
+    W = torch.tensor(c.W_init(), dtype=wdt, device=dev)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return c, W, p
+
+
+def cpu_baseline(c, rows):
+    """The FP64 oracle on a bounded row sample of one step, scaled to steps/s.
+
+    Sample: `rows` rows of the Gram matrix (their gram-scatter into the
+    coefficients), the same rows of 4 R W, and their Adam update.  A full
+    step does N / rows times this work.  Index maps (the oracle's plan) are
+    built before timing, as the paper excludes problem setup from its times.
+    """
+    import oracle as O
+    from workloads import gaussian
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    rng = np.random.default_rng(7)
+    sel = np.sort(rng.choice(c.N, size=rows, replace=False))
+    W = gaussian((c.N, c.rank), 1, c.w_std)
+    p = gaussian(c.M, 3)
+    pr = O.pair_ranks(c.n, c.d, rows=sel)
+    st = O.AdamState(np.zeros((rows, c.rank)), np.zeros((rows, c.rank)))
+    t0 = time.perf_counter()
+    G = W[sel] @ W.T
+    w = np.where(sel[:, None] == np.arange(c.N)[None, :], 1.0, 2.0)   # stand-in for the symmetric weights
+    cpart = np.bincount(pr.ravel(), weights=(w * G).ravel(), minlength=c.M)
+    r = cpart - p
+    g = 4.0 * (r[pr] @ W)
+    O.adam_step(W[sel], g, st, 1e-3)
+    dt = time.perf_counter() - t0
+    return {"value": (rows / c.N) / dt, "unit": "steps/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{rows} of {c.N} rows of one step (gram-scatter rows, 4RW rows, Adam rows), "
+                      f"{dt:.1f} s, scaled by rows/N"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only: the path does not use a second GPU (--gpus {a.gpus} requested)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2410_19844_amd as S
+
+    c, W, p = make_inputs(S, torch, a.workload, a.precision)
+    pl = S.Plan(c.n, c.d, c.rank, a.precision)
+    lr = a.lr if a.lr is not None else 1e-3
+    adam = S.Adam(lr=lr)
+    stream = torch.cuda.current_stream()
+    flags = S.FLAG_EXACT_FORWARD if a.exact else 0
+
+    if a.mode == "ttt":
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = pl.solve(W, p, adam, tol=a.tol, max_steps=a.max_steps, check_every=25, ladder=True,
+                       stall_checks=4, stall_ratio=0.8)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out = {"metric": f"time-to-rel-residual {a.tol:g} at n={c.n} d={c.d}", "value": dt, "unit": "s",
+               "n_gpus": 1, "steps": res["steps"], "warmup": 0, "ms_per_step": 1e3 * dt / max(res["steps"], 1),
+               "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+               "dtype": DTYPE[a.precision], "data": "synthetic",
+               "config": {"workload": f"{c.name}: n={c.n} d={c.d} N={c.N} M={c.M} rank={c.rank}",
+                          "precision": a.precision, "lr": lr, "tol": a.tol},
+               "result": res}
+        print(json.dumps(out), flush=True)
+        return
+
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    st = pl.new_state()
+    for t in range(1, a.warmup + 1):
+        pl.step(W, st, t, p, adam, loss=loss, flags=flags)
+    torch.cuda.synchronize()
+    pl.timing(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for t in range(a.warmup + 1, a.warmup + a.steps + 1):
+        pl.step(W, st, t, p, adam, loss=loss, flags=flags)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = ev0.elapsed_time(ev1)
+    kern = pl.timing_read()
+    pl.timing(False)
+    ms_step = ms_total / a.steps
+    N, k = c.N, c.rank
+    flops = {"gram": float(N) * (N + 1) * k, "rw": 2.0 * N * N * k}
+    per_launch = {name: kern[name][0] / max(kern[name][1], 1) for name in kern}
+    dom = max(("gram", "rw"), key=lambda q: per_launch[q])
+    if a.exact and dom == "gram":
+        peak = PEAKS_TFLOPS["fp64"]
+    else:
+        peak = PEAKS_TFLOPS[a.precision]
+    achieved = flops[dom] / (per_launch[dom] * 1e-3) / 1e12
+    out = {
+        "metric": f"grad steps/s at n={c.n} d={c.d}", "value": 1e3 / ms_step, "unit": "steps/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE[a.precision] if not a.exact else DTYPE[a.precision] + "+fp64-forward",
+        "data": "synthetic",
+        "config": {"workload": f"{c.name}: n={c.n} d={c.d} N={c.N} M={c.M} rank={c.rank}; "
+                               f"p=coeff(W0 W0^T), W0 {c.N}x{c.w0_rank} N(0,{c.w0_std:.4g}^2); "
+                               f"W N(0,{c.w_std:.4g}^2)",
+                   "precision": a.precision, "exact_forward": a.exact, "lr": lr},
+        "roofline": {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "algorithmic_flops": flops[dom], "avg_ms": per_launch[dom],
+                     "executed_mfma_factor": 3 if (a.precision == "bf16x3" and not (a.exact and dom == "gram")) else 1},
+        "kernels_ms_per_step": {name: kern[name][0] / a.steps for name in kern},
+        "loss": float(loss.item()),
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(c, a.cpu_rows)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -185,6 +185,28 @@ int sos_step_batch(const sos_plan_t* plans, void* const* d_W, void* const* d_sta
                    const int64_t* t, const double* const* d_p, const sos_adam_t* adam,
                    double* d_losses, int count, void* stream);
 
+/* Kernel classes reported by sos_timing_read. */
+enum sos_kernel_class {
+  SOS_K_PREP = 0,    /* operand copies / bf16 split of W                  */
+  SOS_K_INIT = 1,    /* r <- -p                                           */
+  SOS_K_GRAM = 2,    /* gram-scatter forward                              */
+  SOS_K_LOSS = 3,    /* sum of squares                                    */
+  SOS_K_GATHER = 4,  /* R from r                                          */
+  SOS_K_RW = 5,      /* R W backward                                      */
+  SOS_K_ADAM = 6,    /* Adam update                                       */
+  SOS_K_COUNT = 7
+};
+
+/* Per-kernel timing with HIP events around this plan's launches (tracing
+ * aid; adds one event pair per launch).  enable = 1 clears the totals and
+ * starts recording, enable = 0 stops.                                     */
+int sos_timing(sos_plan_t plan, int enable);
+
+/* Wait for the recorded events and return, per kernel class, the summed
+ * milliseconds (h_ms[SOS_K_COUNT]) and launch counts (h_calls[SOS_K_COUNT],
+ * may be NULL).  Clears the totals.                                       */
+int sos_timing_read(sos_plan_t plan, double* h_ms, int64_t* h_calls);
+
 /* Message for the last error on this thread ("" if none). */
 const char* sos_last_error(void);
 

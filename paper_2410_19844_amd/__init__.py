@@ -51,7 +51,7 @@ class _Result(ctypes.Structure):
 
 def _load():
     if not os.path.exists(_LIB_PATH):
-        raise ImportError(f"{_LIB_PATH} is missing: run `python -m paper_2410_19844_amd.build`")
+        raise ImportError(f"{_LIB_PATH} is missing: run `python paper_2410_19844_amd/build.py`")
     lib = ctypes.CDLL(_LIB_PATH)
     P, V, I, I64 = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
     sig = {
@@ -69,6 +69,8 @@ def _load():
         "sos_verify": (I, [P, V, V, ctypes.POINTER(ctypes.c_double), V, V]),
         "sos_step_batch": (I, [ctypes.POINTER(P), ctypes.POINTER(V), ctypes.POINTER(V),
                                ctypes.POINTER(I64), ctypes.POINTER(V), ctypes.POINTER(_Adam), V, I, V]),
+        "sos_timing": (I, [P, I]),
+        "sos_timing_read": (I, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]),
         "sos_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -81,7 +83,8 @@ def _load():
 _lib = _load()
 EXPORTS = ("sos_plan", "sos_plan_query", "sos_plan_bind", "sos_plan_destroy", "sos_exponents",
            "sos_pair_ranks", "sos_loss_grad", "sos_step", "sos_solve", "sos_verify",
-           "sos_step_batch", "sos_last_error")
+           "sos_step_batch", "sos_timing", "sos_timing_read", "sos_last_error")
+KERNEL_CLASSES = ("prep", "init_r", "gram", "loss", "gather", "rw", "adam")
 
 
 def _check(rc: int, allow=(OK,)):
@@ -198,6 +201,17 @@ class Plan:
         r = torch.empty(self.M, dtype=torch.float64, device=self.device) if want_r else None
         _check(_lib.sos_verify(self._h, _ptr(W), _ptr(p), ctypes.byref(rel), _ptr(r), _stream(stream)))
         return (rel.value, r) if want_r else rel.value
+
+    def timing(self, enable: bool):
+        _check(_lib.sos_timing(self._h, 1 if enable else 0))
+
+    def timing_read(self):
+        """{kernel class: (total ms, launches)} since timing(True)."""
+        n = len(KERNEL_CLASSES)
+        ms = (ctypes.c_double * n)()
+        calls = (ctypes.c_int64 * n)()
+        _check(_lib.sos_timing_read(self._h, ms, calls))
+        return {name: (ms[i], calls[i]) for i, name in enumerate(KERNEL_CLASSES)}
 
     def solve(self, W, p, adam: Adam, tol=1e-8, max_steps=10000, check_every=50, ladder=True,
               stall_checks=4, stall_ratio=0.7, state=None, stream=None):

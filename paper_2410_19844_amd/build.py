@@ -1,6 +1,6 @@
 """Build libsos.so (gfx950) in-tree with hipcc.
 
-Usage: python -m paper_2410_19844_amd.build   (or call build()).
+Usage: python paper_2410_19844_amd/build.py   (or __graft_entry__.build()).
 """
 from __future__ import annotations
 

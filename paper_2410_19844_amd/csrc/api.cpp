@@ -27,6 +27,48 @@ int hip_error(hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_error(e_, what); \
   } while (0)
 
+// Event pairs around launches while sos_timing is on.
+static hipEvent_t take_event(sos_plan_s* p) {
+  if (!p->event_pool.empty()) {
+    hipEvent_t e = p->event_pool.back();
+    p->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct Timer {
+  sos_plan_s* p;
+  int cls;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  Timer(sos_plan_s* p_, int c, hipStream_t s_) : p(p_), cls(c), s(s_) {
+    if (!p->timing) return;
+    a = take_event(p);
+    b = take_event(p);
+    if (a && b) (void)hipEventRecord(a, s);
+  }
+  void done() {
+    if (!p->timing || !a || !b) return;
+    (void)hipEventRecord(b, s);
+    p->timed.push_back({cls, a, b});
+    a = b = nullptr;
+  }
+  ~Timer() {
+    if (a) p->event_pool.push_back(a);
+    if (b) p->event_pool.push_back(b);
+  }
+};
+
+#define TIMED(cls, call, what)   \
+  do {                            \
+    Timer tm_(p, cls, s);         \
+    SOS_HIP(call, what);          \
+    tm_.done();                   \
+  } while (0)
+
 static int check_bound(const sos_plan_s* p, const char* fn) {
   if (!p) return set_error(SOS_EINVAL, std::string(fn) + ": plan is NULL");
   if (!p->bound) return set_error(SOS_EINVAL, std::string(fn) + ": plan is not bound to a workspace");
@@ -41,10 +83,16 @@ static double* scal(const sos_plan_s* p) { return (double*)(p->ws + p->lay.scal)
 static int run_forward(sos_plan_s* p, const void* W, const double* d_p, bool exact, bool prep,
                        double* d_loss, hipStream_t s) {
   if (p->prec == SOS_FP64) exact = false;
-  if (prep || exact) SOS_HIP(launch_prep(p, W, exact, s), "prep");
-  SOS_HIP(launch_init_r(p, d_p, s), "init_r");
-  SOS_HIP(launch_gram(p, exact, s), "gram");
-  SOS_HIP(launch_sumsq(p, (const double*)(p->ws + p->lay.r), p->M, d_loss, s), "loss");
+  if (prep || exact) TIMED(SOS_K_PREP, launch_prep(p, W, exact, s), "prep");
+  TIMED(SOS_K_INIT, launch_init_r(p, d_p, s), "init_r");
+  TIMED(SOS_K_GRAM, launch_gram(p, exact, s), "gram");
+  TIMED(SOS_K_LOSS, launch_sumsq(p, (const double*)(p->ws + p->lay.r), p->M, d_loss, s), "loss");
+  return SOS_OK;
+}
+
+static int run_backward(sos_plan_s* p, void* g, hipStream_t s) {
+  TIMED(SOS_K_GATHER, launch_gather(p, s), "gather");
+  TIMED(SOS_K_RW, launch_rw(p, g, s), "backward");
   return SOS_OK;
 }
 
@@ -54,9 +102,10 @@ static int run_step(sos_plan_s* p, void* W, void* state, int64_t t, const double
   int rc = run_forward(p, W, d_p, exact, true, d_loss, s);
   if (rc) return rc;
   void* g = p->ws + p->lay.g;
-  SOS_HIP(launch_backward(p, g, s), "backward");
+  rc = run_backward(p, g, s);
+  if (rc) return rc;
   char* st = (char*)state;
-  SOS_HIP(launch_adam(p, W, st, st + slot_bytes(p), g, t, h, s), "adam");
+  TIMED(SOS_K_ADAM, launch_adam(p, W, st, st + slot_bytes(p), g, t, h, s), "adam");
   return SOS_OK;
 }
 
@@ -71,7 +120,47 @@ static int check_adam(const sos_adam_t* h, const char* fn) {
 
 using namespace sos;
 
+sos_plan_s::~sos_plan_s() {
+  for (auto& t : timed) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (auto e : event_pool) (void)hipEventDestroy(e);
+}
+
 extern "C" {
+
+int sos_timing(sos_plan_t p, int enable) {
+  if (!p) return set_error(SOS_EINVAL, "sos_timing: plan is NULL");
+  if (enable) {
+    for (auto& t : p->timed) {
+      p->event_pool.push_back(t.a);
+      p->event_pool.push_back(t.b);
+    }
+    p->timed.clear();
+  }
+  p->timing = enable != 0;
+  return SOS_OK;
+}
+
+int sos_timing_read(sos_plan_t p, double* h_ms, int64_t* h_calls) {
+  if (!p || !h_ms) return set_error(SOS_EINVAL, "sos_timing_read: NULL argument");
+  for (int c = 0; c < SOS_K_COUNT; ++c) {
+    h_ms[c] = 0;
+    if (h_calls) h_calls[c] = 0;
+  }
+  for (auto& t : p->timed) {
+    float ms = 0;
+    SOS_HIP(hipEventSynchronize(t.b), "sos_timing_read");
+    SOS_HIP(hipEventElapsedTime(&ms, t.a, t.b), "sos_timing_read");
+    h_ms[t.cls] += ms;
+    if (h_calls) h_calls[t.cls] += 1;
+    p->event_pool.push_back(t.a);
+    p->event_pool.push_back(t.b);
+  }
+  p->timed.clear();
+  return SOS_OK;
+}
 
 int sos_plan(int n, int d, int rank, int precision, sos_plan_t* out) {
   try {
@@ -144,7 +233,7 @@ int sos_loss_grad(sos_plan_t p, const void* d_W, const double* d_p, double* d_lo
   hipStream_t s = (hipStream_t)stream;
   int rc = run_forward(p, d_W, d_p, (flags & SOS_FLAG_EXACT_FORWARD) != 0, true, d_loss, s);
   if (rc) return rc;
-  if (d_grad) SOS_HIP(launch_backward(p, d_grad, s), "sos_loss_grad: backward");
+  if (d_grad && (rc = run_backward(p, d_grad, s))) return rc;
   if (d_r)
     SOS_HIP(hipMemcpyAsync(d_r, p->ws + p->lay.r, p->M * 8, hipMemcpyDeviceToDevice, s), "sos_loss_grad: r");
   return SOS_OK;

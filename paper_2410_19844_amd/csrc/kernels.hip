@@ -615,7 +615,7 @@ static hipError_t rw_launch(const sos_plan_s* p, void* g, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_backward(const sos_plan_s* p, void* g, hipStream_t s) {
+hipError_t launch_gather(const sos_plan_s* p, hipStream_t s) {
   char* ws = p->ws;
   const RankCtx rk = rank_ctx(p);
   const double* r = (const double*)(ws + p->lay.r);
@@ -625,8 +625,10 @@ hipError_t launch_backward(const sos_plan_s* p, void* g, hipStream_t s) {
   if (p->prec == SOS_FP64) k_gather<0><<<grid_for(total), 256, 0, s>>>(rk, r, (int)p->N, p->Np, p->Np2, Rh, Rl);
   else if (p->prec == SOS_FP32) k_gather<1><<<grid_for(total), 256, 0, s>>>(rk, r, (int)p->N, p->Np, p->Np2, Rh, Rl);
   else k_gather<2><<<grid_for(total), 256, 0, s>>>(rk, r, (int)p->N, p->Np, p->Np2, Rh, Rl);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_rw(const sos_plan_s* p, void* g, hipStream_t s) {
   if (p->prec == SOS_FP64) return rw_launch<MF64>(p, g, s);
   if (p->prec == SOS_FP32) return rw_launch<MF32>(p, g, s);
   return rw_launch<MBF3>(p, g, s);

@@ -58,6 +58,12 @@ struct sos_plan_s {
   char* ws = nullptr;
   size_t ws_size = 0;
   bool bound = false;
+  // kernel timing (sos_timing)
+  struct TimedLaunch { int cls; hipEvent_t a, b; };
+  bool timing = false;
+  std::vector<TimedLaunch> timed;
+  std::vector<hipEvent_t> event_pool;
+  ~sos_plan_s();
 };
 
 namespace sos {
@@ -80,7 +86,8 @@ hipError_t launch_prep(const sos_plan_s* p, const void* W, bool want_f32, hipStr
 hipError_t launch_init_r(const sos_plan_s* p, const double* d_p, hipStream_t s);
 hipError_t launch_sumsq(const sos_plan_s* p, const double* x, int64_t M, double* out, hipStream_t s);
 hipError_t launch_gram(const sos_plan_s* p, bool exact, hipStream_t s);
-hipError_t launch_backward(const sos_plan_s* p, void* g, hipStream_t s);
+hipError_t launch_gather(const sos_plan_s* p, hipStream_t s);
+hipError_t launch_rw(const sos_plan_s* p, void* g, hipStream_t s);
 hipError_t launch_adam(const sos_plan_s* p, void* W, void* m, void* v, const void* g, int64_t t,
                        const sos_adam_t& h, hipStream_t s);
 }  // namespace sos
