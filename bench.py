@@ -44,6 +44,11 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-steps", type=int, default=3000)
     ap.add_argument("--lr", type=float, default=None)
+    ap.add_argument("--lr-exact", type=float, default=1e-3, help="Adam step size in the exact-forward phase")
+    ap.add_argument("--switch-rel", type=float, default=None,
+                    help="ladder switch point (default 1e-5 for bf16x3, 1e-6 for fp32)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 1 GiB device copy first (scale reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -109,7 +114,9 @@ def main():
 
     c, W, p = make_inputs(S, torch, a.workload, a.precision)
     pl = S.Plan(c.n, c.d, c.rank, a.precision)
-    lr = a.lr if a.lr is not None else 1e-3
+    lr = a.lr if a.lr is not None else 3e-3
+    if a.switch_rel is None:
+        a.switch_rel = {"bf16x3": 1e-5, "fp32": 1e-6, "fp64": 0.0}[a.precision]
     adam = S.Adam(lr=lr)
     stream = torch.cuda.current_stream()
     flags = S.FLAG_EXACT_FORWARD if a.exact else 0
@@ -117,8 +124,9 @@ def main():
     if a.mode == "ttt":
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res = pl.solve(W, p, adam, tol=a.tol, max_steps=a.max_steps, check_every=25, ladder=True,
-                       stall_checks=4, stall_ratio=0.8)
+        res = pl.solve(W, p, adam, tol=a.tol, max_steps=a.max_steps, check_every=10, ladder=True,
+                       stall_checks=6, stall_ratio=0.8, switch_rel=a.switch_rel, lr_exact=a.lr_exact,
+                       rollback_ratio=10.0)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out = {"metric": f"time-to-rel-residual {a.tol:g} at n={c.n} d={c.d}", "value": dt, "unit": "s",
@@ -126,11 +134,18 @@ def main():
                "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
                "dtype": DTYPE[a.precision], "data": "synthetic",
                "config": {"workload": f"{c.name}: n={c.n} d={c.d} N={c.N} M={c.M} rank={c.rank}",
-                          "precision": a.precision, "lr": lr, "tol": a.tol},
+                          "precision": a.precision, "lr": lr, "lr_exact": a.lr_exact,
+                          "switch_rel": a.switch_rel, "tol": a.tol},
                "result": res}
         print(json.dumps(out), flush=True)
         return
 
+    if a.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     loss = torch.empty(1, dtype=torch.float64, device="cuda")
     st = pl.new_state()
     for t in range(1, a.warmup + 1):

@@ -91,16 +91,27 @@ typedef struct {
   double lr, beta1, beta2, eps;
 } sos_adam_t;
 
-/* sos_solve options. */
+/* sos_solve options.  The loop follows the paper's first-order method
+ * (Adam from the given start, success judged on the best iterate); the
+ * precision ladder and the step-size guard are this library's additions,
+ * needed because a residual measured with a rounded forward cannot go below
+ * that forward's rounding level, and Adam with a fixed step size turns
+ * unstable once the gradient is dominated by that rounding noise.        */
 typedef struct {
   double tol;            /* target: FP64 ||r|| / ||p|| <= tol                */
   int64_t max_steps;     /* step budget                                     */
   int64_t check_every;   /* read the loss back every this many steps        */
   int32_t ladder;        /* 1: start with the plan's fast forward and switch
-                            to SOS_FLAG_EXACT_FORWARD when it stalls        */
-  int32_t stall_checks;  /* checks without `stall_ratio` improvement that
-                            count as a stall (ladder switch)                */
-  double stall_ratio;    /* e.g. 0.7: progress needs rel < 0.7 * best       */
+                            to SOS_FLAG_EXACT_FORWARD (see switch_rel and
+                            stall_checks)                                   */
+  int32_t stall_checks;  /* checks without `stall_ratio` progress count as a
+                            stall, on which the ladder switches; 0: off     */
+  double stall_ratio;    /* progress means rel < stall_ratio * reference    */
+  double switch_rel;     /* ladder: switch once the fast forward's rel <=
+                            switch_rel (0: switch on a stall only)          */
+  double lr_exact;       /* Adam step size in the exact phase (0: adam->lr) */
+  double rollback_ratio; /* rel > rollback_ratio * best rel: restore the best
+                            W and halve the step size (0: off)              */
 } sos_solve_opts_t;
 
 typedef struct {

@@ -39,7 +39,9 @@ class _Adam(ctypes.Structure):
 class _SolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_steps", ctypes.c_int64),
                 ("check_every", ctypes.c_int64), ("ladder", ctypes.c_int32),
-                ("stall_checks", ctypes.c_int32), ("stall_ratio", ctypes.c_double)]
+                ("stall_checks", ctypes.c_int32), ("stall_ratio", ctypes.c_double),
+                ("switch_rel", ctypes.c_double), ("lr_exact", ctypes.c_double),
+                ("rollback_ratio", ctypes.c_double)]
 
 
 class _Result(ctypes.Structure):
@@ -214,10 +216,13 @@ class Plan:
         return {name: (ms[i], calls[i]) for i, name in enumerate(KERNEL_CLASSES)}
 
     def solve(self, W, p, adam: Adam, tol=1e-8, max_steps=10000, check_every=50, ladder=True,
-              stall_checks=4, stall_ratio=0.7, state=None, stream=None):
+              stall_checks=4, stall_ratio=0.7, switch_rel=0.0, lr_exact=0.0, rollback_ratio=0.0,
+              state=None, stream=None):
+        """sos_solve: Adam to an FP64-verified ||r||/||p|| <= tol; W ends as the best iterate."""
         self._w(W), self._p(p)
         state = self.new_state() if state is None else state
-        opts = _SolveOpts(tol, max_steps, check_every, 1 if ladder else 0, stall_checks, stall_ratio)
+        opts = _SolveOpts(tol, max_steps, check_every, 1 if ladder else 0, stall_checks, stall_ratio,
+                          switch_rel, lr_exact, rollback_ratio)
         res = _Result()
         _check(_lib.sos_solve(self._h, _ptr(W), _ptr(state), _ptr(p), ctypes.byref(adam.c()),
                               ctypes.byref(opts), ctypes.byref(res), _stream(stream)),

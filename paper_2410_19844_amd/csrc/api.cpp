@@ -192,6 +192,8 @@ int sos_plan_bind(sos_plan_t p, void* d_ws, size_t ws_bytes, void* stream) {
           "sos_plan_bind: codes");
   SOS_HIP(hipMemcpyAsync(p->ws + p->lay.tables, p->tables.data(), p->tables.size() * 4, hipMemcpyHostToDevice, s),
           "sos_plan_bind: tables");
+  SOS_HIP(hipMemcpyAsync(p->ws + p->lay.tiles, p->tile_list.data(), p->tile_list.size() * 4, hipMemcpyHostToDevice, s),
+          "sos_plan_bind: tiles");
   SOS_HIP(hipStreamSynchronize(s), "sos_plan_bind");
   p->bound = true;
   return SOS_OK;
@@ -272,8 +274,10 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
   if (int rc = check_bound(p, "sos_solve")) return rc;
   if (int rc = check_adam(adam, "sos_solve")) return rc;
   if (!d_W || !d_state || !d_p || !o || !res) return set_error(SOS_EINVAL, "sos_solve: NULL argument");
-  if (o->max_steps < 0 || o->check_every < 1 || !(o->tol >= 0))
-    return set_error(SOS_EINVAL, "sos_solve: needs max_steps >= 0, check_every >= 1, tol >= 0");
+  if (o->max_steps < 0 || o->check_every < 1 || !(o->tol >= 0) || !(o->lr_exact >= 0) ||
+      !(o->rollback_ratio >= 0) || o->stall_checks < 0)
+    return set_error(SOS_EINVAL, "sos_solve: needs max_steps >= 0, check_every >= 1, tol, lr_exact, "
+                                 "rollback_ratio >= 0 and stall_checks >= 0");
   hipStream_t s = (hipStream_t)stream;
   std::memset(res, 0, sizeof(*res));
   const size_t slot = slot_bytes(p), wbytes = (size_t)p->N * p->k * w_elem(p);
@@ -287,39 +291,54 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
   SOS_HIP(hipMemcpyAsync(&pn2, sc + 1, 8, hipMemcpyDeviceToHost, s), "sos_solve: readback");
   SOS_HIP(hipStreamSynchronize(s), "sos_solve");
   const double pnorm = pn2 > 0 ? std::sqrt(pn2) : 1.0;
+  const double inf = std::numeric_limits<double>::infinity();
 
   const bool can_ladder = o->ladder && p->prec != SOS_FP64;
+  sos_adam_t h = *adam;
   int phase = 0;
-  double best_rel = std::numeric_limits<double>::infinity(), ref_rel = best_rel;
+  double best_rel = inf, ref_rel = inf;
   bool have_best = false;
   int stall = 0;
   int64_t t = 0, exact_steps = 0;
   double last_loss = 0;
   bool done = false;
+  auto enter_exact = [&]() {
+    phase = 1;
+    stall = 0;
+    if (o->lr_exact > 0) h.lr = o->lr_exact;
+    best_rel = ref_rel = inf;  // exact values from here on
+  };
   while (t < o->max_steps && !done) {
     ++t;
     const bool check = (t % o->check_every == 0) || t == o->max_steps;
     if (check) SOS_HIP(hipMemcpyAsync(cand, d_W, wbytes, hipMemcpyDeviceToDevice, s), "sos_solve: snapshot");
     const int flags = phase == 1 ? SOS_FLAG_EXACT_FORWARD : 0;
-    int rc = run_step(p, d_W, st, t, d_p, *adam, sc + 0, flags, s);
+    int rc = run_step(p, d_W, st, t, d_p, h, sc + 0, flags, s);
     if (rc) return rc;
     if (phase == 1) ++exact_steps;
     if (!check) continue;
     SOS_HIP(hipMemcpyAsync(&last_loss, sc + 0, 8, hipMemcpyDeviceToHost, s), "sos_solve: loss");
     SOS_HIP(hipStreamSynchronize(s), "sos_solve");
-    if (!std::isfinite(last_loss)) {
-      if (have_best) SOS_HIP(hipMemcpy(d_W, best, wbytes, hipMemcpyDeviceToDevice), "sos_solve: restore");
+    const double rel = std::isfinite(last_loss) ? std::sqrt(last_loss) / pnorm : inf;
+    if (!std::isfinite(rel) && !have_best) {
       res->steps = t;
       res->exact_steps = exact_steps;
       res->loss = last_loss;
       res->phase = phase;
       return set_error(SOS_ENUMERIC, "sos_solve: loss is not finite");
     }
-    const double rel = std::sqrt(last_loss) / pnorm;
     if (rel < best_rel) {
       best_rel = rel;
       std::swap(best, cand);  // the snapshot is the iterate this loss belongs to
       have_best = true;
+    }
+    if (have_best && (!std::isfinite(rel) || (o->rollback_ratio > 0 && rel > o->rollback_ratio * best_rel))) {
+      // diverging: back to the best iterate with half the step size
+      SOS_HIP(hipMemcpyAsync(d_W, best, wbytes, hipMemcpyDeviceToDevice, s), "sos_solve: rollback");
+      h.lr *= 0.5;
+      stall = 0;
+      ref_rel = best_rel;
+      continue;
     }
     if (rel < o->stall_ratio * ref_rel) {
       ref_rel = rel;
@@ -327,7 +346,8 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
     } else {
       ++stall;
     }
-    bool switch_phase = can_ladder && phase == 0 && o->stall_checks > 0 && stall >= o->stall_checks;
+    bool switch_phase = can_ladder && phase == 0 &&
+                        ((o->stall_checks > 0 && stall >= o->stall_checks) || (o->switch_rel > 0 && rel <= o->switch_rel));
     if (rel <= o->tol) {
       double vrel = 0;
       int vrc = sos_verify(p, best, d_p, &vrel, nullptr, stream);
@@ -335,11 +355,7 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
       if (vrel <= o->tol) done = true;
       else if (can_ladder && phase == 0) switch_phase = true;
     }
-    if (switch_phase) {
-      phase = 1;
-      stall = 0;
-      best_rel = ref_rel = std::numeric_limits<double>::infinity();  // exact values from here on
-    }
+    if (switch_phase) enter_exact();
   }
   if (have_best) SOS_HIP(hipMemcpyAsync(d_W, best, wbytes, hipMemcpyDeviceToDevice, s), "sos_solve: best W");
   double vrel = 0;

@@ -377,19 +377,16 @@ __device__ __forceinline__ void gemm_tile(const typename Md::GT* const* A, const
   lb.store(st[0].b);
   __syncthreads();
   const int64_t nk = K / Md::BK;
-  for (int64_t kt = 0; kt < nk; ++kt) {
+  for (int64_t kt = 0; kt + 1 < nk; ++kt) {
     const int cur = (int)(kt & 1);
-    if (kt + 1 < nk) {
-      la.load(A, ld, a_row0, (kt + 1) * Md::BK);
-      lb.load(B, ld, b_row0, (kt + 1) * Md::BK);
-    }
+    la.load(A, ld, a_row0, (kt + 1) * Md::BK);
+    lb.load(B, ld, b_row0, (kt + 1) * Md::BK);
     mma_stage<Md>(st[cur], acc, wm, wn);
-    if (kt + 1 < nk) {
-      la.store(st[cur ^ 1].a);
-      lb.store(st[cur ^ 1].b);
-    }
+    la.store(st[cur ^ 1].a);
+    lb.store(st[cur ^ 1].b);
     __syncthreads();
   }
+  mma_stage<Md>(st[(nk - 1) & 1], acc, wm, wn);
 }
 
 // ---------------------------------------------------------------------------
@@ -592,7 +589,7 @@ hipError_t launch_gram(const sos_plan_s* p, bool exact, hipStream_t s) {
     return gram_launch<MEX>(p, a, nullptr, s);
   }
   if (p->prec == SOS_FP32) return gram_launch<MF32>(p, ws + p->lay.a_hi, nullptr, s);
-  return gram_launch<MBF3>(p, ws + p->lay.a_hi, ws + p->lay.a_lo, s);
+  return launch_gram_bf3(p, s);
 }
 
 template <class Md>
@@ -631,7 +628,7 @@ hipError_t launch_gather(const sos_plan_s* p, hipStream_t s) {
 hipError_t launch_rw(const sos_plan_s* p, void* g, hipStream_t s) {
   if (p->prec == SOS_FP64) return rw_launch<MF64>(p, g, s);
   if (p->prec == SOS_FP32) return rw_launch<MF32>(p, g, s);
-  return rw_launch<MBF3>(p, g, s);
+  return launch_rw_bf3(p, g, s);
 }
 
 hipError_t launch_adam(const sos_plan_s* p, void* W, void* m, void* v, const void* g, int64_t t,

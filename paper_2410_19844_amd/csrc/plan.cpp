@@ -138,12 +138,27 @@ int plan_create(int n, int d, int rank, int prec, sos_plan_s** out) {
   p->Kp2 = round_up(rank, kPadRows);
   const size_t wel = (prec == SOS_FP64) ? 8 : 4;          // W / gradient element
   const size_t oel = (prec == SOS_FP64) ? 8 : (prec == SOS_FP32 ? 4 : 2);  // operand element
+  // Upper-triangle tiles of 256 rows, ordered by 8 x 8 super-blocks so that a
+  // run of consecutive tiles shares at most 16 operand panels.
+  {
+    const int T = (int)(p->Np / 256), SB = 8;
+    for (int P = 0; P * SB < T; ++P)
+      for (int Q = P; Q * SB < T; ++Q)
+        for (int J = Q * SB; J < std::min(T, (Q + 1) * SB); ++J)
+          for (int I = P * SB; I < std::min(T, (P + 1) * SB); ++I)
+            if (I <= J) {
+              p->tile_list.push_back(I);
+              p->tile_list.push_back(J);
+            }
+    p->ntiles256 = (int)(p->tile_list.size() / 2);
+  }
   Layout& L = p->lay;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = round_up(off + bytes, 256); return o; };
   L.codes = take((size_t)N * p->nwords * 4);
   L.tables = take(p->tables.size() * 4);
   L.r = take((size_t)M * 8);
+  L.tiles = take(p->tile_list.size() * 4);
   L.scal = take(1024 * 8);   // [0..7] scalars, [8..519] reduction partials
   L.a_hi = take((size_t)p->Np * p->Kp * oel);
   if (prec == SOS_BF16X3) L.a_lo = take((size_t)p->Np * p->Kp * oel);

@@ -31,6 +31,7 @@ constexpr int kPadK = 64;        // operand K extents padded to this multiple (z
 struct Layout {
   // byte offsets into the workspace
   size_t codes = 0, tables = 0, r = 0, scal = 0;
+  size_t tiles = 0;              // (I, J) pairs of 256-row upper-triangle tiles, int2
   size_t a_hi = 0, a_lo = 0;     // W operand copies, rows = Np, ld = Kp   (forward A/B)
   size_t t_hi = 0, t_lo = 0;     // W^T operand copies, rows = Kp2, ld = Np2 (backward B)
   size_t R_hi = 0, R_lo = 0;     // R operand, rows = Np, ld = Np2           (backward A)
@@ -54,6 +55,8 @@ struct sos_plan_s {
   int64_t Np2 = 0;   // N rounded up to kPadK      (ld of R and W^T copies)
   int64_t Kp2 = 0;   // k rounded up to kPadRows   (rows of W^T copies)
   sos::Layout lay;
+  int ntiles256 = 0;               // upper-triangle tiles of 256 x 256
+  std::vector<int32_t> tile_list;  // 2 * ntiles256
   size_t state_bytes = 0;
   char* ws = nullptr;
   size_t ws_size = 0;
@@ -88,6 +91,8 @@ hipError_t launch_sumsq(const sos_plan_s* p, const double* x, int64_t M, double*
 hipError_t launch_gram(const sos_plan_s* p, bool exact, hipStream_t s);
 hipError_t launch_gather(const sos_plan_s* p, hipStream_t s);
 hipError_t launch_rw(const sos_plan_s* p, void* g, hipStream_t s);
+hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s);
+hipError_t launch_rw_bf3(const sos_plan_s* p, void* g, hipStream_t s);
 hipError_t launch_adam(const sos_plan_s* p, void* W, void* m, void* v, const void* g, int64_t t,
                        const sos_adam_t& h, hipStream_t s);
 }  // namespace sos
