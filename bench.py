@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--lr-exact", type=float, default=1e-3, help="Adam step size in the exact-forward phase")
     ap.add_argument("--switch-rel", type=float, default=None,
                     help="ladder switch point (default 1e-5 for bf16x3, 1e-6 for fp32)")
+    ap.add_argument("--split-backward", action="store_true",
+                    help="bf16x3: three bf16 products (hi/lo split) in the R W backward instead of one")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (scale reference for HBM byte counters)")
     return ap.parse_args()
@@ -119,14 +121,15 @@ def main():
         a.switch_rel = {"bf16x3": 1e-5, "fp32": 1e-6, "fp64": 0.0}[a.precision]
     adam = S.Adam(lr=lr)
     stream = torch.cuda.current_stream()
-    flags = S.FLAG_EXACT_FORWARD if a.exact else 0
+    a.single_backward = a.precision == "bf16x3" and not a.split_backward
+    flags = (S.FLAG_EXACT_FORWARD if a.exact else 0) | (S.FLAG_SINGLE_BACKWARD if a.single_backward else 0)
 
     if a.mode == "ttt":
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = pl.solve(W, p, adam, tol=a.tol, max_steps=a.max_steps, check_every=10, ladder=True,
                        stall_checks=6, stall_ratio=0.8, switch_rel=a.switch_rel, lr_exact=a.lr_exact,
-                       rollback_ratio=10.0)
+                       rollback_ratio=10.0, single_backward=a.single_backward)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out = {"metric": f"time-to-rel-residual {a.tol:g} at n={c.n} d={c.d}", "value": dt, "unit": "s",
@@ -135,7 +138,7 @@ def main():
                "dtype": DTYPE[a.precision], "data": "synthetic",
                "config": {"workload": f"{c.name}: n={c.n} d={c.d} N={c.N} M={c.M} rank={c.rank}",
                           "precision": a.precision, "lr": lr, "lr_exact": a.lr_exact,
-                          "switch_rel": a.switch_rel, "tol": a.tol},
+                          "switch_rel": a.switch_rel, "tol": a.tol, "single_backward": a.single_backward},
                "result": res}
         print(json.dumps(out), flush=True)
         return
@@ -181,11 +184,13 @@ def main():
         "config": {"workload": f"{c.name}: n={c.n} d={c.d} N={c.N} M={c.M} rank={c.rank}; "
                                f"p=coeff(W0 W0^T), W0 {c.N}x{c.w0_rank} N(0,{c.w0_std:.4g}^2); "
                                f"W N(0,{c.w_std:.4g}^2)",
-                   "precision": a.precision, "exact_forward": a.exact, "lr": lr},
+                   "precision": a.precision, "exact_forward": a.exact, "lr": lr,
+                   "single_backward": a.single_backward},
         "roofline": {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
                      "algorithmic_flops": flops[dom], "avg_ms": per_launch[dom],
-                     "executed_mfma_factor": 3 if (a.precision == "bf16x3" and not (a.exact and dom == "gram")) else 1},
+                     "executed_mfma_factor": (1 if (dom == "rw" and a.single_backward) else 3)
+                     if (a.precision == "bf16x3" and not (a.exact and dom == "gram")) else 1},
         "kernels_ms_per_step": {name: kern[name][0] / a.steps for name in kern},
         "loss": float(loss.item()),
     }

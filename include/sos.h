@@ -84,6 +84,11 @@ enum sos_flags {
    * transposed copies) were written by the previous sos_step of this plan
    * on this same W, so the split pass is skipped.                         */
   SOS_FLAG_COPIES_VALID = 2,
+  /* SOS_BF16X3 only: the backward takes one bf16 product per element pair
+   * (hi * hi) instead of three.  The gradient 4 R W then carries a relative
+   * error of about 2^-8 per term; it still vanishes where R does (at an
+   * exact fit), so the fixed point is unchanged.  Ignored for other modes. */
+  SOS_FLAG_SINGLE_BACKWARD = 4,
 };
 
 /* Adam hyper-parameters (Kingma and Ba; the paper's optimiser, Section 3). */
@@ -112,6 +117,8 @@ typedef struct {
   double lr_exact;       /* Adam step size in the exact phase (0: adam->lr) */
   double rollback_ratio; /* rel > rollback_ratio * best rel: restore the best
                             W and halve the step size (0: off)              */
+  int32_t single_backward; /* 1: steps use SOS_FLAG_SINGLE_BACKWARD         */
+  int32_t reserved;
 } sos_solve_opts_t;
 
 typedef struct {

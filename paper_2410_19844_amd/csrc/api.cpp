@@ -90,9 +90,9 @@ static int run_forward(sos_plan_s* p, const void* W, const double* d_p, bool exa
   return SOS_OK;
 }
 
-static int run_backward(sos_plan_s* p, void* g, hipStream_t s) {
-  TIMED(SOS_K_GATHER, launch_gather(p, s), "gather");
-  TIMED(SOS_K_RW, launch_rw(p, g, s), "backward");
+static int run_backward(sos_plan_s* p, void* g, bool split, hipStream_t s) {
+  TIMED(SOS_K_GATHER, launch_gather(p, split, s), "gather");
+  TIMED(SOS_K_RW, launch_rw(p, g, split, s), "backward");
   return SOS_OK;
 }
 
@@ -102,7 +102,7 @@ static int run_step(sos_plan_s* p, void* W, void* state, int64_t t, const double
   int rc = run_forward(p, W, d_p, exact, true, d_loss, s);
   if (rc) return rc;
   void* g = p->ws + p->lay.g;
-  rc = run_backward(p, g, s);
+  rc = run_backward(p, g, (flags & SOS_FLAG_SINGLE_BACKWARD) == 0, s);
   if (rc) return rc;
   char* st = (char*)state;
   TIMED(SOS_K_ADAM, launch_adam(p, W, st, st + slot_bytes(p), g, t, h, s), "adam");
@@ -231,11 +231,12 @@ int sos_loss_grad(sos_plan_t p, const void* d_W, const double* d_p, double* d_lo
                   double* d_r, int flags, void* stream) {
   if (int rc = check_bound(p, "sos_loss_grad")) return rc;
   if (!d_W || !d_p || !d_loss) return set_error(SOS_EINVAL, "sos_loss_grad: d_W, d_p and d_loss are required");
-  if (flags & ~(int)SOS_FLAG_EXACT_FORWARD) return set_error(SOS_EINVAL, "sos_loss_grad: unknown flags");
+  if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_SINGLE_BACKWARD))
+    return set_error(SOS_EINVAL, "sos_loss_grad: unknown flags");
   hipStream_t s = (hipStream_t)stream;
   int rc = run_forward(p, d_W, d_p, (flags & SOS_FLAG_EXACT_FORWARD) != 0, true, d_loss, s);
   if (rc) return rc;
-  if (d_grad && (rc = run_backward(p, d_grad, s))) return rc;
+  if (d_grad && (rc = run_backward(p, d_grad, (flags & SOS_FLAG_SINGLE_BACKWARD) == 0, s))) return rc;
   if (d_r)
     SOS_HIP(hipMemcpyAsync(d_r, p->ws + p->lay.r, p->M * 8, hipMemcpyDeviceToDevice, s), "sos_loss_grad: r");
   return SOS_OK;
@@ -247,7 +248,7 @@ int sos_step(sos_plan_t p, void* d_W, void* d_state, int64_t t, const double* d_
   if (int rc = check_adam(adam, "sos_step")) return rc;
   if (!d_W || !d_state || !d_p || !d_loss) return set_error(SOS_EINVAL, "sos_step: NULL device pointer");
   if (t < 1) return set_error(SOS_EINVAL, "sos_step: t is 1-based");
-  if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_COPIES_VALID))
+  if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_COPIES_VALID | SOS_FLAG_SINGLE_BACKWARD))
     return set_error(SOS_EINVAL, "sos_step: unknown flags");
   return run_step(p, d_W, d_state, t, d_p, *adam, d_loss, flags, (hipStream_t)stream);
 }
@@ -312,7 +313,7 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
     ++t;
     const bool check = (t % o->check_every == 0) || t == o->max_steps;
     if (check) SOS_HIP(hipMemcpyAsync(cand, d_W, wbytes, hipMemcpyDeviceToDevice, s), "sos_solve: snapshot");
-    const int flags = phase == 1 ? SOS_FLAG_EXACT_FORWARD : 0;
+    const int flags = (phase == 1 ? SOS_FLAG_EXACT_FORWARD : 0) | (o->single_backward ? SOS_FLAG_SINGLE_BACKWARD : 0);
     int rc = run_step(p, d_W, st, t, d_p, h, sc + 0, flags, s);
     if (rc) return rc;
     if (phase == 1) ++exact_steps;

@@ -4,8 +4,8 @@
 // lo = bf16(w - hi); a product w w' is taken as lo*hi' + hi*lo' + hi*hi' on
 // v_mfma_f32_32x32x16_bf16 with FP32 accumulation (lo*lo' is dropped).
 //
-// Tile: 256 x 256 outputs per 512-thread workgroup; 8 waves in a 4 x 2 grid,
-// each wave 64 x 128 (2 x 4 MFMA blocks of 32 x 32).  K advances in stages
+// Tile: 256 x 256 outputs per workgroup; each wave owns WM x WN of it
+// (WM / 32 x WN / 32 MFMA blocks of 32 x 32).  K advances in stages
 // of 16 through a 4-deep ring of LDS stages (4 arrays x 256 rows x 32 B =
 // 32 KB each) filled by direct global->LDS loads issued three stages ahead,
 // so an L2 miss has about three stages of MFMA work to hide behind.
@@ -27,7 +27,13 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int TM = 256;
 constexpr int BK = 16;            // K per pipeline stage (one MFMA k-step)
-constexpr int NT = 512;
+constexpr int WM = 128;           // rows of the output tile per wave
+constexpr int WN = 128;           // columns of the output tile per wave
+constexpr int BI = WM / 32, BJ = WN / 32;     // 32 x 32 MFMA blocks per wave
+constexpr int WGN = TM / WN;                  // waves along the column direction
+constexpr int NWAVES = (TM / WM) * WGN;
+constexpr int NT = 64 * NWAVES;
+constexpr int ROWS_PER_WAVE = TM / NWAVES;    // rows each wave loads per array
 constexpr int NSTAGE = 4;         // LDS stages; loads run NSTAGE - 1 stages ahead
 constexpr int ROWB = BK * 2;      // bytes per row per array (32)
 constexpr int ARR = TM * ROWB;    // bytes per array tile (8 KB)
@@ -48,7 +54,7 @@ struct Operands {
   const __bf16* a_lo;
   const __bf16* b_hi;
   const __bf16* b_lo;
-  int64_t ld;  // shared leading dimension (= K extent, padded)
+  int64_t nkb;  // K blocks of 16 per panel (panel-blocked layout, see blk_off)
 };
 
 // Wait until at most n of this wave's vector-memory operations are pending
@@ -70,103 +76,170 @@ __device__ __forceinline__ void wait_vm_barrier() {
 // cannot tell the pipeline's LDS buffers apart across the loop back-edge,
 // does not drain the whole pipeline before each stage; the waits for these
 // loads are explicit (wait_vm_barrier).  The asm has no outputs: the data
-// goes to LDS, and the address registers are read when it issues.
-__device__ __forceinline__ void dma16(const void* gaddr, char* lds_base) {
-  const unsigned off = (unsigned)(uintptr_t)(lds_t)lds_base;
-  asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+// goes to LDS, and the registers are read when it issues.
+//
+// Hazards the compiler cannot see inside the asm, handled here: the global
+// address is a per-lane 64-bit VGPR pair (a VALU-written VGPR read by a
+// vector-memory instruction is interlocked, whereas an SGPR base written by
+// a VALU instruction would need 5 wait states before the load), and the
+// SALU write of m0 is followed by s_nop before the load that reads it.
+__device__ __forceinline__ void dma16(const void* base, unsigned voff, char* lds_base) {
+  const unsigned m0 = (unsigned)(uintptr_t)(lds_t)lds_base;
+  const char* gaddr = (const char*)base + voff;
+  asm volatile("s_mov_b32 m0, %0\n\ts_nop 1\n\tglobal_load_lds_dwordx4 %1, off"
                :
-               : "s"(__builtin_amdgcn_readfirstlane(off)), "v"(gaddr)
+               : "s"(__builtin_amdgcn_readfirstlane(m0)), "v"(gaddr)
                : "memory", "m0");
 }
 
 // Issue the direct-to-LDS loads of one stage: wave w moves rows
-// [32w, 32w + 32) of each of the four arrays, lane l one 16-byte chunk.
+// [ROWS_PER_WAVE w, ROWS_PER_WAVE (w + 1)) of each array, 32 rows (1 KB)
+// per instruction, lane l one 16-byte chunk.  With the panel-blocked layout
+// the stage is one contiguous 8 KB block per array, so the 1 KB of one
+// instruction is 8 whole 128-byte lines.
+template <bool SPLIT>
 __device__ __forceinline__ void issue_stage(char* st, const Operands& o, int64_t arow0, int64_t brow0, int64_t k0) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int r = w * 32 + (l >> 1);
-  const int c = (l & 1) ^ ((r >> 3) & 1);
-  const int64_t ea = (arow0 + r) * o.ld + k0 + c * 8;
-  const int64_t eb = (brow0 + r) * o.ld + k0 + c * 8;
-  char* base = st + w * 1024;
-  dma16(o.a_hi + ea, base + 0 * ARR);
-  dma16(o.a_lo + ea, base + 1 * ARR);
-  dma16(o.b_hi + eb, base + 2 * ARR);
-  dma16(o.b_lo + eb, base + 3 * ARR);
+  const int64_t ablk = ((arow0 / TM) * o.nkb + k0 / BK) * (TM * BK);  // element offset of the block
+  const int64_t bblk = ((brow0 / TM) * o.nkb + k0 / BK) * (TM * BK);
+#pragma unroll
+  for (int h = 0; h < ROWS_PER_WAVE / 32; ++h) {
+    const int r = w * ROWS_PER_WAVE + h * 32 + (l >> 1);
+    const int c = (l & 1) ^ ((r >> 3) & 1);
+    const unsigned voff = (unsigned)((r * BK + c * 8) * 2);  // bytes inside the block
+    char* base = st + (w * ROWS_PER_WAVE + h * 32) * ROWB;
+    dma16(o.a_hi + ablk, voff, base + 0 * ARR);
+    if (SPLIT) dma16(o.a_lo + ablk, voff, base + 1 * ARR);
+    dma16(o.b_hi + bblk, voff, base + 2 * ARR);
+    if (SPLIT) dma16(o.b_lo + bblk, voff, base + 3 * ARR);
+  }
 }
 
-__device__ __forceinline__ void mma_stage(const char* st, f32x16 (&acc)[2][4], int wm, int wn) {
+// MFMA operand fragments of one stage for this wave: per 32-row block of A
+// (and of B) one 16-byte chunk per lane of hi (and lo).
+struct Frag {
+  bf16x8 ah[BI], al[BI], bh[BJ], bl[BJ];
+};
+
+// Fragment reads: row = (block base, a multiple of 32) + (lane & 31), so the
+// swizzle depends on the lane only and every read is one lane-constant base
+// plus a compile-time offset.
+template <bool SPLIT>
+__device__ __forceinline__ void load_frag(Frag& f, const char* st, int wm, int wn) {
   const int l = threadIdx.x & 63;
-  const int c = l >> 5;
-  bf16x8 ah[2], al[2], bh[4], bl[4];
+  const int lane_off = slot_off(l & 31, l >> 5);
+  const char* a = st + wm * WM * ROWB + lane_off;
+  const char* b = st + 2 * ARR + wn * WN * ROWB + lane_off;
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi) {
-    const int off = slot_off(wm * 64 + bi * 32 + (l & 31), c);
-    ah[bi] = *(const bf16x8*)(st + 0 * ARR + off);
-    al[bi] = *(const bf16x8*)(st + 1 * ARR + off);
+  for (int bi = 0; bi < BI; ++bi) {
+    f.ah[bi] = *(const bf16x8*)(a + bi * 32 * ROWB);
+    if (SPLIT) f.al[bi] = *(const bf16x8*)(a + ARR + bi * 32 * ROWB);
   }
 #pragma unroll
-  for (int bj = 0; bj < 4; ++bj) {
-    const int off = slot_off(wn * 128 + bj * 32 + (l & 31), c);
-    bh[bj] = *(const bf16x8*)(st + 2 * ARR + off);
-    bl[bj] = *(const bf16x8*)(st + 3 * ARR + off);
+  for (int bj = 0; bj < BJ; ++bj) {
+    f.bh[bj] = *(const bf16x8*)(b + bj * 32 * ROWB);
+    if (SPLIT) f.bl[bj] = *(const bf16x8*)(b + ARR + bj * 32 * ROWB);
   }
+}
+
+// MFMAs of A-blocks [b0, b1) against all B-blocks.
+template <bool SPLIT, int b0, int b1>
+__device__ __forceinline__ void mma_rows(const Frag& f, f32x16 (&acc)[BI][BJ]) {
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bi = b0; bi < b1; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) {
-      acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[bi], bh[bj], acc[bi][bj], 0, 0, 0);
-      acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bl[bj], acc[bi][bj], 0, 0, 0);
-      acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bi], bh[bj], acc[bi][bj], 0, 0, 0);
+    for (int bj = 0; bj < BJ; ++bj) {
+      if (SPLIT) {
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.al[bi], f.bh[bj], acc[bi][bj], 0, 0, 0);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.ah[bi], f.bl[bj], acc[bi][bj], 0, 0, 0);
+      }
+      acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.ah[bi], f.bh[bj], acc[bi][bj], 0, 0, 0);
     }
 }
 
-// Pipeline slot of stage kt: its own LDS buffer is bufs[B] (B = kt % 4),
-// and it refills bufs[(B + 3) % 4], last read by stage kt - 1.  Distinct
-// __shared__ arrays per buffer (and B known at compile time) let the
-// compiler see that these loads never alias the reads of this stage.
-// One pipeline step on stage kt: wait for its buffer (rd), refill the buffer
-// of stage kt - 1 (wr) with stage kt + 3, then run the MFMAs on rd.  rd and
-// wr are restrict-qualified so that, once inlined, the compiler knows the
-// refill cannot alias this step's LDS reads and does not wait for it.
-__device__ __forceinline__ void pipe_step(const char* __restrict__ rd, char* __restrict__ wr, const Operands& o,
+// One step of the software pipeline.  On entry `cur` holds the fragments of
+// stage kt.  The first half of its MFMAs is issued; then, while they run,
+// the wave waits for stage kt+1 to land, joins the barrier (after which the
+// buffer of stage kt is free: every wave has its fragments in registers),
+// issues the loads of stage kt+4 into that buffer and reads the fragments of
+// stage kt+1 into `nxt`; the second half of the MFMAs of stage kt covers the
+// latency of those reads.
+template <bool SPLIT>
+__device__ __forceinline__ void pipe_step(Frag& cur, Frag& nxt, char* ring, const Operands& o,
                                           int64_t kt, int64_t nk, int64_t arow0, int64_t brow0,
-                                          f32x16 (&acc)[2][4], int wm, int wn) {
-  const int64_t ahead = nk - 1 - kt;
-  if (ahead >= 2) wait_vm_barrier<8>();
-  else if (ahead == 1) wait_vm_barrier<4>();
-  else wait_vm_barrier<0>();
-  if (kt + NSTAGE - 1 < nk) issue_stage(wr, o, arow0, brow0, (kt + NSTAGE - 1) * BK);
-  mma_stage(rd, acc, wm, wn);
+                                          f32x16 (&acc)[BI][BJ], int wm, int wn) {
+  constexpr int per = (SPLIT ? 4 : 2) * (ROWS_PER_WAVE / 32);  // loads per thread per stage
+  mma_rows<SPLIT, 0, BI / 2>(cur, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  if (kt + 1 < nk) {
+    // stages issued so far: up to kt + 3; stage kt + 1 must have landed
+    const int64_t later = (nk - 1) - (kt + 1) < 2 ? (nk - 1) - (kt + 1) : 2;
+    if (later == 2) wait_vm_barrier<2 * per>();
+    else if (later == 1) wait_vm_barrier<per>();
+    else wait_vm_barrier<0>();
+    if (kt + NSTAGE < nk) issue_stage<SPLIT>(ring + (kt % NSTAGE) * STAGE, o, arow0, brow0, (kt + NSTAGE) * BK);
+    load_frag<SPLIT>(nxt, ring + ((kt + 1) % NSTAGE) * STAGE, wm, wn);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  mma_rows<SPLIT, BI / 2, BI>(cur, acc);
+}
+
+// The same step in the steady state (kt + 4 < nk): stage kt+1 has two
+// stages behind it in flight and the refill always happens, so the step has
+// no branches.
+template <bool SPLIT>
+__device__ __forceinline__ void pipe_step_steady(Frag& cur, Frag& nxt, char* ring, const Operands& o, int64_t kt,
+                                                 int64_t arow0, int64_t brow0, f32x16 (&acc)[BI][BJ], int wm,
+                                                 int wn) {
+  constexpr int per = (SPLIT ? 4 : 2) * (ROWS_PER_WAVE / 32);
+  mma_rows<SPLIT, 0, BI / 2>(cur, acc);
+  __builtin_amdgcn_sched_barrier(0);
+  wait_vm_barrier<2 * per>();
+  issue_stage<SPLIT>(ring + (kt % NSTAGE) * STAGE, o, arow0, brow0, (kt + NSTAGE) * BK);
+  load_frag<SPLIT>(nxt, ring + ((kt + 1) % NSTAGE) * STAGE, wm, wn);
+  __builtin_amdgcn_sched_barrier(0);
+  mma_rows<SPLIT, BI / 2, BI>(cur, acc);
 }
 
 // C(256 x 256) = A[arow0 .. +256) x B[brow0 .. +256)^T over K (K % BK == 0).
+template <bool SPLIT>
 __device__ __forceinline__ void tile_gemm(const Operands& o, int64_t K, int64_t arow0, int64_t brow0,
-                                          char* const (&bufs)[NSTAGE], f32x16 (&acc)[2][4]) {
+                                          char* ring, f32x16 (&acc)[BI][BJ]) {
   const int wave = threadIdx.x >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WGN, wn = wave % WGN;
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = f32x16{};
+    for (int bj = 0; bj < BJ; ++bj) acc[bi][bj] = f32x16{};
+  constexpr int per = (SPLIT ? 4 : 2) * (ROWS_PER_WAVE / 32);
   const int64_t nk = K / BK;
-  if (0 < nk) issue_stage(bufs[0], o, arow0, brow0, 0);
-  if (1 < nk) issue_stage(bufs[1], o, arow0, brow0, BK);
-  if (2 < nk) issue_stage(bufs[2], o, arow0, brow0, 2 * BK);
-  for (int64_t kt = 0; kt < nk; kt += NSTAGE) {
-    pipe_step(bufs[0], bufs[3], o, kt, nk, arow0, brow0, acc, wm, wn);
-    if (kt + 1 < nk) pipe_step(bufs[1], bufs[0], o, kt + 1, nk, arow0, brow0, acc, wm, wn);
-    if (kt + 2 < nk) pipe_step(bufs[2], bufs[1], o, kt + 2, nk, arow0, brow0, acc, wm, wn);
-    if (kt + 3 < nk) pipe_step(bufs[3], bufs[2], o, kt + 3, nk, arow0, brow0, acc, wm, wn);
+  for (int s = 0; s < NSTAGE - 1; ++s)
+    if (s < nk) issue_stage<SPLIT>(ring + s * STAGE, o, arow0, brow0, (int64_t)s * BK);
+  // stage 0 must have landed; stages 1 and 2 may be in flight
+  if (nk >= 3) wait_vm_barrier<2 * per>();
+  else if (nk == 2) wait_vm_barrier<per>();
+  else wait_vm_barrier<0>();
+  if (NSTAGE - 1 < nk) issue_stage<SPLIT>(ring + (NSTAGE - 1) * STAGE, o, arow0, brow0, (int64_t)(NSTAGE - 1) * BK);
+  Frag f0, f1;
+  load_frag<SPLIT>(f0, ring, wm, wn);
+  int64_t kt = 0;
+  for (; kt + 1 + NSTAGE < nk; kt += 2) {
+    pipe_step_steady<SPLIT>(f0, f1, ring, o, kt, arow0, brow0, acc, wm, wn);
+    pipe_step_steady<SPLIT>(f1, f0, ring, o, kt + 1, arow0, brow0, acc, wm, wn);
+  }
+  for (; kt < nk; kt += 2) {
+    pipe_step<SPLIT>(f0, f1, ring, o, kt, nk, arow0, brow0, acc, wm, wn);
+    if (kt + 1 < nk) pipe_step<SPLIT>(f1, f0, ring, o, kt + 1, nk, arow0, brow0, acc, wm, wn);
   }
 }
 
 // (row, col) of accumulator (bi, bj, q) inside the 256 x 256 tile.
 __device__ __forceinline__ int acc_row(int wm, int bi, int q) {
   const int l = threadIdx.x & 63;
-  return wm * 64 + bi * 32 + (q >> 2) * 8 + (l >> 5) * 4 + (q & 3);
+  return wm * WM + bi * 32 + (q >> 2) * 8 + (l >> 5) * 4 + (q & 3);
 }
 __device__ __forceinline__ int acc_col(int wn, int bj) {
-  return wn * 128 + bj * 32 + (threadIdx.x & 31);
+  return wn * WN + bj * 32 + (threadIdx.x & 31);
 }
 
 // Block id -> position in a per-XCD-contiguous order (bijective on [0, nb)).
@@ -204,44 +277,59 @@ struct GramArgs {
   double* r;
 };
 
-#define SOS_BF3_BUFFERS                                         \
-  __shared__ __attribute__((aligned(16))) char lds0[STAGE];    \
-  __shared__ __attribute__((aligned(16))) char lds1[STAGE];    \
-  __shared__ __attribute__((aligned(16))) char lds2[STAGE];    \
-  __shared__ __attribute__((aligned(16))) char lds3[STAGE];    \
-  char* const bufs[NSTAGE] = {lds0, lds1, lds2, lds3}
+#define SOS_BF3_BUFFERS \
+  __shared__ __attribute__((aligned(16))) char lds[NSTAGE * STAGE]
 
+// Epilogue through LDS: the accumulator tile (fp32, 256 KB) goes out in
+// row-halves of 128 x 256 (128 KB, the pipeline buffers being free by now);
+// then every thread takes consecutive elements of the half, ranks each
+// (row, col) pair and adds it into r.  Copying out with compile-time indices
+// keeps the accumulators in registers; the scatter loop indexes LDS instead.
 __global__ __launch_bounds__(NT) void k_gram_bf3(GramArgs g) {
   SOS_BF3_BUFFERS;
   const int v = xcd_order(blockIdx.x, g.ntiles);
   const int2 t = g.tiles[v];
-  f32x16 acc[2][4];
-  tile_gemm(g.o, g.K, (int64_t)t.x * TM, (int64_t)t.y * TM, bufs, acc);
+  f32x16 acc[BI][BJ];
+  tile_gemm<true>(g.o, g.K, (int64_t)t.x * TM, (int64_t)t.y * TM, lds, acc);
   const int wave = threadIdx.x >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WGN, wn = wave % WGN;
+  float* half = (float*)lds;  // the whole pipeline ring: 128 KB
+  constexpr int HROWS = 128;
+  static_assert(4 * STAGE == HROWS * TM * 4, "half tile must fill the pipeline buffers");
+  static_assert(TM == kBlkRows && BK == kBlkK, "stage = one block of the panel-blocked layout");
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int hh = 0; hh < TM / HROWS; ++hh) {
+    __syncthreads();
+    if (wm * WM / HROWS == hh) {
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) {
-      const int j = t.y * TM + acc_col(wn, bj);
+      for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int i = t.x * TM + acc_row(wm, bi, q);
-        if (i < g.N && j < g.N && i <= j) {
-          const double w = (i == j) ? 1.0 : 2.0;
-          unsafeAtomicAdd(g.r + rank_sum(g.rk, i, j), w * (double)acc[bi][bj][q]);
-        }
+        for (int bj = 0; bj < BJ; ++bj)
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            const int row = acc_row(wm, bi, q) - hh * HROWS, col = acc_col(wn, bj);
+            half[row * TM + col] = acc[bi][bj][q];
+          }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < HROWS * TM; e += NT) {
+      const int i = t.x * TM + hh * HROWS + e / TM, j = t.y * TM + e % TM;
+      if (i < g.N && j < g.N && i <= j) {
+        const double w = (i == j) ? 1.0 : 2.0;
+        unsafeAtomicAdd(g.r + rank_sum(g.rk, i, j), w * (double)half[e]);
       }
     }
+  }
 }
 
 struct RwArgs {
-  Operands o;  // A = R (rows Np), B = W^T copies (rows Kp2); ld = Np2
+  Operands o;  // A = R (rows Np), B = W^T copies (rows Kp2); K extent Np2
   int64_t K;
   int TI, TL, N, k;
   float* g;    // N x k
 };
 
+template <bool SPLIT>
 __global__ __launch_bounds__(NT) void k_rw_bf3(RwArgs a) {
   SOS_BF3_BUFFERS;
   const int nb = a.TI * a.TL;
@@ -253,21 +341,32 @@ __global__ __launch_bounds__(NT) void k_rw_bf3(RwArgs a) {
   const int rows = min(GROUP, a.TI - first);
   const int in = v % per_group;
   const int I = first + in % rows, L = in / rows;
-  f32x16 acc[2][4];
-  tile_gemm(a.o, a.K, (int64_t)I * TM, (int64_t)L * TM, bufs, acc);
+  f32x16 acc[BI][BJ];
+  tile_gemm<SPLIT>(a.o, a.K, (int64_t)I * TM, (int64_t)L * TM, lds, acc);
+  // epilogue through LDS in row-halves (as in k_gram_bf3), then coalesced
+  // row-major stores of 4 * acc into g
   const int wave = threadIdx.x >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WGN, wn = wave % WGN;
+  float* half = (float*)lds;
+  constexpr int HROWS = 128;
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int hh = 0; hh < TM / HROWS; ++hh) {
+    __syncthreads();
+    if (wm * WM / HROWS == hh) {
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) {
-      const int l = L * TM + acc_col(wn, bj);
+      for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int i = I * TM + acc_row(wm, bi, q);
-        if (i < a.N && l < a.k) a.g[(int64_t)i * a.k + l] = 4.0f * acc[bi][bj][q];
-      }
+        for (int bj = 0; bj < BJ; ++bj)
+#pragma unroll
+          for (int q = 0; q < 16; ++q)
+            half[(acc_row(wm, bi, q) - hh * HROWS) * TM + acc_col(wn, bj)] = acc[bi][bj][q];
     }
+    __syncthreads();
+    for (int e = threadIdx.x; e < HROWS * TM; e += NT) {
+      const int i = I * TM + hh * HROWS + e / TM, l = L * TM + e % TM;
+      if (i < a.N && l < a.k) a.g[(int64_t)i * a.k + l] = 4.0f * half[e];
+    }
+  }
 }
 
 }  // namespace bf3
@@ -279,7 +378,7 @@ hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s) {
   const char* ws = p->ws;
   g.o.a_hi = g.o.b_hi = (const __bf16*)(ws + p->lay.a_hi);
   g.o.a_lo = g.o.b_lo = (const __bf16*)(ws + p->lay.a_lo);
-  g.o.ld = p->Kp;
+  g.o.nkb = p->Kp / kBlkK;
   g.K = p->Kp;
   g.tiles = (const int2*)(ws + p->lay.tiles);
   g.ntiles = p->ntiles256;
@@ -293,21 +392,22 @@ hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_rw_bf3(const sos_plan_s* p, void* g, hipStream_t s) {
+hipError_t launch_rw_bf3(const sos_plan_s* p, void* g, bool split, hipStream_t s) {
   bf3::RwArgs a;
   const char* ws = p->ws;
   a.o.a_hi = (const __bf16*)(ws + p->lay.R_hi);
   a.o.a_lo = (const __bf16*)(ws + p->lay.R_lo);
   a.o.b_hi = (const __bf16*)(ws + p->lay.t_hi);
   a.o.b_lo = (const __bf16*)(ws + p->lay.t_lo);
-  a.o.ld = p->Np2;
+  a.o.nkb = p->Np2 / kBlkK;
   a.K = p->Np2;
   a.TI = (int)(p->Np / bf3::TM);
   a.TL = (int)(p->Kp2 / bf3::TM);
   a.N = (int)p->N;
   a.k = p->k;
   a.g = (float*)g;
-  bf3::k_rw_bf3<<<a.TI * a.TL, bf3::NT, 0, s>>>(a);
+  if (split) bf3::k_rw_bf3<true><<<a.TI * a.TL, bf3::NT, 0, s>>>(a);
+  else bf3::k_rw_bf3<false><<<a.TI * a.TL, bf3::NT, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -90,8 +90,9 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
       else if (MODE == 1) ((float*)a.a_hi)[o] = (float)v;
       else {
         const __bf16 h = (__bf16)(float)v;
-        ((__bf16*)a.a_hi)[o] = h;
-        ((__bf16*)a.a_lo)[o] = (__bf16)((float)v - (float)h);
+        const int64_t ob = blk_off(i, l, a.Kp / kBlkK);
+        ((__bf16*)a.a_hi)[ob] = h;
+        ((__bf16*)a.a_lo)[ob] = (__bf16)((float)v - (float)h);
         if (a.a_f32) a.a_f32[o] = (float)v;
       }
     }
@@ -106,8 +107,9 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
       else if (MODE == 1) ((float*)a.t_hi)[o] = (float)v;
       else {
         const __bf16 h = (__bf16)(float)v;
-        ((__bf16*)a.t_hi)[o] = h;
-        ((__bf16*)a.t_lo)[o] = (__bf16)((float)v - (float)h);
+        const int64_t ob = blk_off(l, i, a.Np2 / kBlkK);
+        ((__bf16*)a.t_hi)[ob] = h;
+        ((__bf16*)a.t_lo)[ob] = (__bf16)((float)v - (float)h);
       }
     }
   }
@@ -435,13 +437,22 @@ __global__ __launch_bounds__(kThreads) void k_gram(GramArgs g) {
 // ---------------------------------------------------------------------------
 // Backward: R from r, then g = 4 R W.
 // ---------------------------------------------------------------------------
-template <int MODE>  // 0 FP64, 1 FP32, 2 bf16 hi/lo
+template <int MODE>  // 0 FP64, 1 FP32, 2 bf16 hi/lo, 3 bf16 hi only
 __global__ __launch_bounds__(256) void k_gather(RankCtx rk, const double* __restrict__ r, int N,
                                                 int64_t Np, int64_t ld, void* R_hi, void* R_lo) {
   const int64_t total = Np * ld;
+  const int64_t nkb = ld / kBlkK;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e / ld), j = (int)(e % ld);
+    int i, j;
+    if (MODE >= 2) {  // e walks the panel-blocked layout (see blk_off)
+      const int64_t blk = e / (kBlkRows * kBlkK), in = e % (kBlkRows * kBlkK);
+      i = (int)((blk / nkb) * kBlkRows + in / kBlkK);
+      j = (int)((blk % nkb) * kBlkK + in % kBlkK);
+    } else {
+      i = (int)(e / ld);
+      j = (int)(e % ld);
+    }
     double v = 0.0;
     if (i < N && j < N) v = r[rank_of_sum(rk, i, j)];
     if (MODE == 0) ((double*)R_hi)[e] = v;
@@ -450,7 +461,7 @@ __global__ __launch_bounds__(256) void k_gather(RankCtx rk, const double* __rest
       const float f = (float)v;
       const __bf16 h = (__bf16)f;
       ((__bf16*)R_hi)[e] = h;
-      ((__bf16*)R_lo)[e] = (__bf16)(f - (float)h);
+      if (MODE == 2) ((__bf16*)R_lo)[e] = (__bf16)(f - (float)h);
     }
   }
 }
@@ -612,7 +623,7 @@ static hipError_t rw_launch(const sos_plan_s* p, void* g, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_gather(const sos_plan_s* p, hipStream_t s) {
+hipError_t launch_gather(const sos_plan_s* p, bool split, hipStream_t s) {
   char* ws = p->ws;
   const RankCtx rk = rank_ctx(p);
   const double* r = (const double*)(ws + p->lay.r);
@@ -621,14 +632,15 @@ hipError_t launch_gather(const sos_plan_s* p, hipStream_t s) {
   void* Rl = p->prec == SOS_BF16X3 ? ws + p->lay.R_lo : nullptr;
   if (p->prec == SOS_FP64) k_gather<0><<<grid_for(total), 256, 0, s>>>(rk, r, (int)p->N, p->Np, p->Np2, Rh, Rl);
   else if (p->prec == SOS_FP32) k_gather<1><<<grid_for(total), 256, 0, s>>>(rk, r, (int)p->N, p->Np, p->Np2, Rh, Rl);
-  else k_gather<2><<<grid_for(total), 256, 0, s>>>(rk, r, (int)p->N, p->Np, p->Np2, Rh, Rl);
+  else if (split) k_gather<2><<<grid_for(total), 256, 0, s>>>(rk, r, (int)p->N, p->Np, p->Np2, Rh, Rl);
+  else k_gather<3><<<grid_for(total), 256, 0, s>>>(rk, r, (int)p->N, p->Np, p->Np2, Rh, Rl);
   return hipGetLastError();
 }
 
-hipError_t launch_rw(const sos_plan_s* p, void* g, hipStream_t s) {
+hipError_t launch_rw(const sos_plan_s* p, void* g, bool split, hipStream_t s) {
   if (p->prec == SOS_FP64) return rw_launch<MF64>(p, g, s);
   if (p->prec == SOS_FP32) return rw_launch<MF32>(p, g, s);
-  return launch_rw_bf3(p, g, s);
+  return launch_rw_bf3(p, g, split, s);
 }
 
 hipError_t launch_adam(const sos_plan_s* p, void* W, void* m, void* v, const void* g, int64_t t,

@@ -28,6 +28,16 @@ constexpr int kMaxWords = 3;     // n <= 16  ->  at most 6 groups
 constexpr int kPadRows = 256;    // operand rows padded to this multiple (zero rows)
 constexpr int kPadK = 64;        // operand K extents padded to this multiple (zero columns)
 
+// Panel-blocked layout of the split-bf16 operands: rows in panels of 256,
+// K in blocks of 16; block (panel, kb) is 256 rows x 16 elements stored
+// contiguously (8 KB of bf16), blocks of one panel consecutive in kb.  A
+// GEMM stage then reads one contiguous 8 KB block per array.
+constexpr int kBlkRows = 256;
+constexpr int kBlkK = 16;
+__host__ __device__ inline int64_t blk_off(int64_t row, int64_t k, int64_t nkb) {
+  return (((row / kBlkRows) * nkb + k / kBlkK) * kBlkRows + row % kBlkRows) * kBlkK + k % kBlkK;
+}
+
 struct Layout {
   // byte offsets into the workspace
   size_t codes = 0, tables = 0, r = 0, scal = 0;
@@ -89,10 +99,10 @@ hipError_t launch_prep(const sos_plan_s* p, const void* W, bool want_f32, hipStr
 hipError_t launch_init_r(const sos_plan_s* p, const double* d_p, hipStream_t s);
 hipError_t launch_sumsq(const sos_plan_s* p, const double* x, int64_t M, double* out, hipStream_t s);
 hipError_t launch_gram(const sos_plan_s* p, bool exact, hipStream_t s);
-hipError_t launch_gather(const sos_plan_s* p, hipStream_t s);
-hipError_t launch_rw(const sos_plan_s* p, void* g, hipStream_t s);
+hipError_t launch_gather(const sos_plan_s* p, bool split, hipStream_t s);
+hipError_t launch_rw(const sos_plan_s* p, void* g, bool split, hipStream_t s);
 hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s);
-hipError_t launch_rw_bf3(const sos_plan_s* p, void* g, hipStream_t s);
+hipError_t launch_rw_bf3(const sos_plan_s* p, void* g, bool split, hipStream_t s);
 hipError_t launch_adam(const sos_plan_s* p, void* W, void* m, void* v, const void* g, int64_t t,
                        const sos_adam_t& h, hipStream_t s);
 }  // namespace sos

@@ -38,6 +38,8 @@ def tol_for(prec, K):
         return 1e-10
     if prec == "fp32":
         return gamma(K + 1) + U32
+    if prec == "bf16x1":   # one bf16 product: both operands rounded to 8 significant bits
+        return 2.0 ** -7 + 2.0 ** -16 + gamma(K) + U32
     return 3.1 * 2.0 ** -16 + gamma(3 * K) + U32
 
 
@@ -122,6 +124,25 @@ def test_loss_grad_parity(prec, n, d, k):
     gabs_fwd = 4.0 * ((tf * cabs + 0.0)[pr] @ np.abs(W64))
     err = np.abs(g.double().cpu().numpy() - g_o)
     assert np.all(err <= tb * gabs + gabs_fwd + 1e-300), f"gradient: max ratio {np.max(err / (tb * gabs + gabs_fwd + 1e-300)):.3g}"
+
+
+@pytest.mark.parametrize("n,d,k", [(3, 2, 20), (6, 4, 420), (10, 5, 300)])
+def test_single_product_backward(n, d, k):
+    """SOS_FLAG_SINGLE_BACKWARD: split-bf16 forward, one bf16 product in R W."""
+    W64, Wd, p, pd = make_case(n, d, k, "bf16x3", seed=n + d)
+    pl = S.Plan(n, d, k, "bf16x3")
+    loss, g, r = pl.loss_grad(Wd, pd, grad=True, want_r=True, single_backward=True)
+    pr = O.pair_ranks(n, d)
+    L_o, g_o, r_o = O.loss_grad(W64, p, n, d, pr)
+    cabs = O.coefficients_abs(W64, n, d, pr)
+    tf = tol_for("bf16x3", k)
+    assert_close_scaled(r.cpu().numpy() + p, r_o + p, cabs, tf, "coefficients")
+    N = W64.shape[0]
+    tb = tol_for("bf16x1", N)
+    gabs = 4.0 * (np.abs(r_o)[pr] @ np.abs(W64))
+    gabs_fwd = 4.0 * ((tf * cabs)[pr] @ np.abs(W64))
+    err = np.abs(g.double().cpu().numpy() - g_o)
+    assert np.all(err <= tb * gabs + gabs_fwd + 1e-300)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
