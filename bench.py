@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--lr-exact", type=float, default=1e-3, help="Adam step size in the exact-forward phase")
     ap.add_argument("--switch-rel", type=float, default=None,
                     help="ladder switch point (default 1e-5 for bf16x3, 1e-6 for fp32)")
+    ap.add_argument("--mid-rel", type=float, default=None,
+                    help="bf16x3 ladder: FP32-forward rung until rel <= mid_rel before the FP64 forward (0: none)")
     ap.add_argument("--split-backward", action="store_true",
                     help="bf16x3: three bf16 products (hi/lo split) in the R W backward instead of one")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -118,7 +120,7 @@ def main():
     pl = S.Plan(c.n, c.d, c.rank, a.precision)
     lr = a.lr if a.lr is not None else 3e-3
     if a.switch_rel is None:
-        a.switch_rel = {"bf16x3": 1e-5, "fp32": 1e-6, "fp64": 0.0}[a.precision]
+        a.switch_rel = {"bf16x3": 3e-6, "fp32": 1e-6, "fp64": 0.0}[a.precision]
     adam = S.Adam(lr=lr)
     stream = torch.cuda.current_stream()
     a.single_backward = a.precision == "bf16x3" and not a.split_backward
@@ -129,7 +131,8 @@ def main():
         t0 = time.perf_counter()
         res = pl.solve(W, p, adam, tol=a.tol, max_steps=a.max_steps, check_every=10, ladder=True,
                        stall_checks=6, stall_ratio=0.8, switch_rel=a.switch_rel, lr_exact=a.lr_exact,
-                       rollback_ratio=10.0, single_backward=a.single_backward)
+                       rollback_ratio=10.0, single_backward=a.single_backward,
+                       mid_rel=a.mid_rel if a.mid_rel is not None else 0.0)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out = {"metric": f"time-to-rel-residual {a.tol:g} at n={c.n} d={c.d}", "value": dt, "unit": "s",
@@ -138,7 +141,8 @@ def main():
                "dtype": DTYPE[a.precision], "data": "synthetic",
                "config": {"workload": f"{c.name}: n={c.n} d={c.d} N={c.N} M={c.M} rank={c.rank}",
                           "precision": a.precision, "lr": lr, "lr_exact": a.lr_exact,
-                          "switch_rel": a.switch_rel, "tol": a.tol, "single_backward": a.single_backward},
+                          "switch_rel": a.switch_rel, "mid_rel": a.mid_rel, "tol": a.tol,
+                          "single_backward": a.single_backward},
                "result": res}
         print(json.dumps(out), flush=True)
         return

@@ -89,6 +89,10 @@ enum sos_flags {
    * error of about 2^-8 per term; it still vanishes where R does (at an
    * exact fit), so the fixed point is unchanged.  Ignored for other modes. */
   SOS_FLAG_SINGLE_BACKWARD = 4,
+  /* SOS_BF16X3 only: forward with FP32 MFMA on the FP32 master W (between
+   * the split-bf16 forward and the FP64 one in accuracy and cost).
+   * SOS_FLAG_EXACT_FORWARD takes precedence.                              */
+  SOS_FLAG_FP32_FORWARD = 8,
 };
 
 /* Adam hyper-parameters (Kingma and Ba; the paper's optimiser, Section 3). */
@@ -119,6 +123,10 @@ typedef struct {
                             W and halve the step size (0: off)              */
   int32_t single_backward; /* 1: steps use SOS_FLAG_SINGLE_BACKWARD         */
   int32_t reserved;
+  double mid_rel;        /* SOS_BF16X3 ladder with a middle rung: after the
+                            fast phase, steps use SOS_FLAG_FP32_FORWARD until
+                            rel <= mid_rel (or a stall), then the exact
+                            forward (0: no middle rung)                     */
 } sos_solve_opts_t;
 
 typedef struct {
@@ -128,7 +136,8 @@ typedef struct {
   double rel;            /* FP64-verified ||r||/||p|| of the returned W     */
   double best_rel;       /* best relative residual seen at any check        */
   int32_t status;        /* SOS_OK or SOS_NOT_CONVERGED                     */
-  int32_t phase;         /* 0: fast forward, 1: exact forward at the end    */
+  int32_t phase;         /* forward at the end: 0 fast, 1 FP32 (middle rung),
+                            2 exact                                         */
 } sos_result_t;
 
 /* Plan a problem (host only; enumerates the bases of Section 1.1, builds

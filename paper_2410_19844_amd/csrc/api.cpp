@@ -80,12 +80,19 @@ static size_t w_elem(const sos_plan_s* p) { return p->prec == SOS_FP64 ? 8 : 4; 
 static double* scal(const sos_plan_s* p) { return (double*)(p->ws + p->lay.scal); }
 
 // r <- coeff(W W^T) - p in the workspace, L = ||r||^2 -> d_loss.
-static int run_forward(sos_plan_s* p, const void* W, const double* d_p, bool exact, bool prep,
-                       double* d_loss, hipStream_t s) {
-  if (p->prec == SOS_FP64) exact = false;
-  if (prep || exact) TIMED(SOS_K_PREP, launch_prep(p, W, exact, s), "prep");
+static int fwd_mode(const sos_plan_s* p, int flags) {
+  if (p->prec == SOS_FP64) return kFwdFast;
+  if (flags & SOS_FLAG_EXACT_FORWARD) return kFwdExact;
+  if ((flags & SOS_FLAG_FP32_FORWARD) && p->prec == SOS_BF16X3) return kFwdF32;
+  return kFwdFast;
+}
+
+static int run_forward(sos_plan_s* p, const void* W, const double* d_p, int flags, double* d_loss,
+                       hipStream_t s) {
+  const int mode = fwd_mode(p, flags);
+  TIMED(SOS_K_PREP, launch_prep(p, W, mode != kFwdFast, s), "prep");
   TIMED(SOS_K_INIT, launch_init_r(p, d_p, s), "init_r");
-  TIMED(SOS_K_GRAM, launch_gram(p, exact, s), "gram");
+  TIMED(SOS_K_GRAM, launch_gram(p, mode, s), "gram");
   TIMED(SOS_K_LOSS, launch_sumsq(p, (const double*)(p->ws + p->lay.r), p->M, d_loss, s), "loss");
   return SOS_OK;
 }
@@ -98,8 +105,7 @@ static int run_backward(sos_plan_s* p, void* g, bool split, hipStream_t s) {
 
 static int run_step(sos_plan_s* p, void* W, void* state, int64_t t, const double* d_p,
                     const sos_adam_t& h, double* d_loss, int flags, hipStream_t s) {
-  const bool exact = (flags & SOS_FLAG_EXACT_FORWARD) != 0;
-  int rc = run_forward(p, W, d_p, exact, true, d_loss, s);
+  int rc = run_forward(p, W, d_p, flags, d_loss, s);
   if (rc) return rc;
   void* g = p->ws + p->lay.g;
   rc = run_backward(p, g, (flags & SOS_FLAG_SINGLE_BACKWARD) == 0, s);
@@ -231,10 +237,10 @@ int sos_loss_grad(sos_plan_t p, const void* d_W, const double* d_p, double* d_lo
                   double* d_r, int flags, void* stream) {
   if (int rc = check_bound(p, "sos_loss_grad")) return rc;
   if (!d_W || !d_p || !d_loss) return set_error(SOS_EINVAL, "sos_loss_grad: d_W, d_p and d_loss are required");
-  if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_SINGLE_BACKWARD))
+  if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_SINGLE_BACKWARD | SOS_FLAG_FP32_FORWARD))
     return set_error(SOS_EINVAL, "sos_loss_grad: unknown flags");
   hipStream_t s = (hipStream_t)stream;
-  int rc = run_forward(p, d_W, d_p, (flags & SOS_FLAG_EXACT_FORWARD) != 0, true, d_loss, s);
+  int rc = run_forward(p, d_W, d_p, flags, d_loss, s);
   if (rc) return rc;
   if (d_grad && (rc = run_backward(p, d_grad, (flags & SOS_FLAG_SINGLE_BACKWARD) == 0, s))) return rc;
   if (d_r)
@@ -248,7 +254,8 @@ int sos_step(sos_plan_t p, void* d_W, void* d_state, int64_t t, const double* d_
   if (int rc = check_adam(adam, "sos_step")) return rc;
   if (!d_W || !d_state || !d_p || !d_loss) return set_error(SOS_EINVAL, "sos_step: NULL device pointer");
   if (t < 1) return set_error(SOS_EINVAL, "sos_step: t is 1-based");
-  if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_COPIES_VALID | SOS_FLAG_SINGLE_BACKWARD))
+  if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_COPIES_VALID | SOS_FLAG_SINGLE_BACKWARD |
+                     SOS_FLAG_FP32_FORWARD))
     return set_error(SOS_EINVAL, "sos_step: unknown flags");
   return run_step(p, d_W, d_state, t, d_p, *adam, d_loss, flags, (hipStream_t)stream);
 }
@@ -258,7 +265,7 @@ int sos_verify(sos_plan_t p, const void* d_W, const double* d_p, double* h_rel, 
   if (!d_W || !d_p || !h_rel) return set_error(SOS_EINVAL, "sos_verify: NULL argument");
   hipStream_t s = (hipStream_t)stream;
   double* sc = scal(p);
-  int rc = run_forward(p, d_W, d_p, true, true, sc + 0, s);
+  int rc = run_forward(p, d_W, d_p, SOS_FLAG_EXACT_FORWARD, sc + 0, s);
   if (rc) return rc;
   SOS_HIP(launch_sumsq(p, d_p, p->M, sc + 1, s), "sos_verify: ||p||");
   double h[2];
@@ -303,20 +310,22 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
   int64_t t = 0, exact_steps = 0;
   double last_loss = 0;
   bool done = false;
-  auto enter_exact = [&]() {
-    phase = 1;
+  const bool has_mid = can_ladder && p->prec == SOS_BF16X3 && o->mid_rel > 0;
+  auto next_phase = [&]() {
+    phase = (phase == 0 && has_mid) ? 1 : 2;
     stall = 0;
     if (o->lr_exact > 0) h.lr = o->lr_exact;
-    best_rel = ref_rel = inf;  // exact values from here on
+    best_rel = ref_rel = inf;  // values of the more accurate forward from here on
   };
   while (t < o->max_steps && !done) {
     ++t;
     const bool check = (t % o->check_every == 0) || t == o->max_steps;
     if (check) SOS_HIP(hipMemcpyAsync(cand, d_W, wbytes, hipMemcpyDeviceToDevice, s), "sos_solve: snapshot");
-    const int flags = (phase == 1 ? SOS_FLAG_EXACT_FORWARD : 0) | (o->single_backward ? SOS_FLAG_SINGLE_BACKWARD : 0);
+    const int flags = (phase == 2 ? SOS_FLAG_EXACT_FORWARD : phase == 1 ? SOS_FLAG_FP32_FORWARD : 0) |
+                      (o->single_backward ? SOS_FLAG_SINGLE_BACKWARD : 0);
     int rc = run_step(p, d_W, st, t, d_p, h, sc + 0, flags, s);
     if (rc) return rc;
-    if (phase == 1) ++exact_steps;
+    if (phase == 2) ++exact_steps;
     if (!check) continue;
     SOS_HIP(hipMemcpyAsync(&last_loss, sc + 0, 8, hipMemcpyDeviceToHost, s), "sos_solve: loss");
     SOS_HIP(hipStreamSynchronize(s), "sos_solve");
@@ -347,16 +356,17 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
     } else {
       ++stall;
     }
-    bool switch_phase = can_ladder && phase == 0 &&
-                        ((o->stall_checks > 0 && stall >= o->stall_checks) || (o->switch_rel > 0 && rel <= o->switch_rel));
+    const double target = phase == 0 ? o->switch_rel : o->mid_rel;
+    bool switch_phase = can_ladder && phase < 2 &&
+                        ((o->stall_checks > 0 && stall >= o->stall_checks) || (target > 0 && rel <= target));
     if (rel <= o->tol) {
       double vrel = 0;
       int vrc = sos_verify(p, best, d_p, &vrel, nullptr, stream);
       if (vrc) return vrc;
       if (vrel <= o->tol) done = true;
-      else if (can_ladder && phase == 0) switch_phase = true;
+      else if (can_ladder && phase < 2) switch_phase = true;
     }
-    if (switch_phase) enter_exact();
+    if (switch_phase && !done) next_phase();
   }
   if (have_best) SOS_HIP(hipMemcpyAsync(d_W, best, wbytes, hipMemcpyDeviceToDevice, s), "sos_solve: best W");
   double vrel = 0;

@@ -65,7 +65,7 @@ struct PrepArgs {
   int N, k;
   int64_t Np, Kp;      // forward copies: rows Np, ld Kp
   int64_t Kp2, Np2;    // transposed copies: rows Kp2, ld Np2
-  void* a_hi; void* a_lo; float* a_f32;
+  void* a_hi; void* a_lo; float* a_f32; float* x_f32;
   void* t_hi; void* t_lo;
 };
 
@@ -86,6 +86,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
     tile[r][tx] = v;
     if (i < a.Np && l < a.Kp) {
       const int64_t o = i * a.Kp + l;
+      if (MODE != 0 && a.x_f32) a.x_f32[blk_off(i, l, a.Kp / kBlkK)] = (float)v;
       if (MODE == 0) ((double*)a.a_hi)[o] = (double)v;
       else if (MODE == 1) ((float*)a.a_hi)[o] = (float)v;
       else {
@@ -548,6 +549,7 @@ hipError_t launch_prep(const sos_plan_s* p, const void* W, bool want_f32, hipStr
   a.a_hi = p->ws + p->lay.a_hi;
   a.a_lo = p->prec == SOS_BF16X3 ? p->ws + p->lay.a_lo : nullptr;
   a.a_f32 = (p->prec == SOS_BF16X3 && want_f32) ? (float*)(p->ws + p->lay.a_f32) : nullptr;
+  a.x_f32 = (p->prec != SOS_FP64 && want_f32) ? (float*)(p->ws + p->lay.x_f32) : nullptr;
   a.t_hi = p->ws + p->lay.t_hi;
   a.t_lo = p->prec == SOS_BF16X3 ? p->ws + p->lay.t_lo : nullptr;
   const int64_t rows = p->Np > p->Np2 ? p->Np : p->Np2;
@@ -592,14 +594,13 @@ static hipError_t gram_launch(const sos_plan_s* p, const void* a0, const void* a
   return hipGetLastError();
 }
 
-hipError_t launch_gram(const sos_plan_s* p, bool exact, hipStream_t s) {
+hipError_t launch_gram(const sos_plan_s* p, int mode, hipStream_t s) {
   const char* ws = p->ws;
   if (p->prec == SOS_FP64) return gram_launch<MF64>(p, ws + p->lay.a_hi, nullptr, s);
-  if (exact) {
-    const void* a = (p->prec == SOS_FP32) ? ws + p->lay.a_hi : ws + p->lay.a_f32;
-    return gram_launch<MEX>(p, a, nullptr, s);
-  }
-  if (p->prec == SOS_FP32) return gram_launch<MF32>(p, ws + p->lay.a_hi, nullptr, s);
+  // FP32 padded row-major copy of W: a_hi in FP32 plans, a_f32 in split plans
+  const void* w32 = (p->prec == SOS_FP32) ? ws + p->lay.a_hi : ws + p->lay.a_f32;
+  if (mode == kFwdExact) return launch_gram_x64(p, s);
+  if (mode == kFwdF32 || p->prec == SOS_FP32) return gram_launch<MF32>(p, w32, nullptr, s);
   return launch_gram_bf3(p, s);
 }
 

@@ -169,6 +169,7 @@ int plan_create(int n, int d, int rank, int prec, sos_plan_s** out) {
   // split-precision plans keep an FP32 padded copy of W for the exact FP64 forward
   // (FP32 plans use a_hi, which already is that copy)
   if (prec == SOS_BF16X3) L.a_f32 = take((size_t)p->Np * p->Kp * 4);
+  if (prec != SOS_FP64) L.x_f32 = take((size_t)p->Np * p->Kp * 4);
   L.g = take((size_t)N * rank * wel);
   L.bytes = off;
   p->state_bytes = round_up((size_t)N * rank * wel, 256) * 4;  // m, v, best W, candidate W

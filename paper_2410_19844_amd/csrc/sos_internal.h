@@ -46,6 +46,7 @@ struct Layout {
   size_t t_hi = 0, t_lo = 0;     // W^T operand copies, rows = Kp2, ld = Np2 (backward B)
   size_t R_hi = 0, R_lo = 0;     // R operand, rows = Np, ld = Np2           (backward A)
   size_t a_f32 = 0;              // FP32 padded W (split-precision plans), rows = Np, ld = Kp
+  size_t x_f32 = 0;              // FP32 W, panel-blocked (exact forward), rows = Np, K extent Kp
   size_t g = 0;                  // gradient scratch, N x k in W's type
   size_t bytes = 0;
 };
@@ -98,10 +99,12 @@ hipError_t launch_pair_ranks(const sos_plan_s* p, int32_t* out, hipStream_t s);
 hipError_t launch_prep(const sos_plan_s* p, const void* W, bool want_f32, hipStream_t s);
 hipError_t launch_init_r(const sos_plan_s* p, const double* d_p, hipStream_t s);
 hipError_t launch_sumsq(const sos_plan_s* p, const double* x, int64_t M, double* out, hipStream_t s);
-hipError_t launch_gram(const sos_plan_s* p, bool exact, hipStream_t s);
+enum { kFwdFast = 0, kFwdF32 = 1, kFwdExact = 2 };
+hipError_t launch_gram(const sos_plan_s* p, int mode, hipStream_t s);
 hipError_t launch_gather(const sos_plan_s* p, bool split, hipStream_t s);
 hipError_t launch_rw(const sos_plan_s* p, void* g, bool split, hipStream_t s);
 hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s);
+hipError_t launch_gram_x64(const sos_plan_s* p, hipStream_t s);
 hipError_t launch_rw_bf3(const sos_plan_s* p, void* g, bool split, hipStream_t s);
 hipError_t launch_adam(const sos_plan_s* p, void* W, void* m, void* v, const void* g, int64_t t,
                        const sos_adam_t& h, hipStream_t s);

@@ -145,6 +145,32 @@ def test_single_product_backward(n, d, k):
     assert np.all(err <= tb * gabs + gabs_fwd + 1e-300)
 
 
+def test_fp32_forward_rung_in_split_plan():
+    """SOS_FLAG_FP32_FORWARD in a split-bf16 plan: FP32 MFMA on the FP32 master."""
+    n, d, k = 6, 4, 420
+    W64, Wd, p, pd = make_case(n, d, k, "bf16x3", seed=8)
+    pl = S.Plan(n, d, k, "bf16x3")
+    loss, _, r = pl.loss_grad(Wd, pd, grad=False, want_r=True, fp32_forward=True)
+    pr = O.pair_ranks(n, d)
+    L_o, _, r_o = O.loss_grad(W64, p, n, d, pr)
+    cabs = O.coefficients_abs(W64, n, d, pr)
+    assert_close_scaled(r.cpu().numpy() + p, r_o + p, cabs, tol_for("fp32", k), "fp32-rung coefficients")
+
+
+def test_solve_three_rung_ladder():
+    n, d = 4, 3
+    N = comb(n + d, d)
+    p = O.coefficients(gaussian((N, N // 2), 0), n, d)
+    pl = S.Plan(n, d, 2 * N, "bf16x3")
+    Wd = to_dev(gaussian((N, 2 * N), 1, 1 / math.sqrt(2 * N)), torch.float32)
+    res = pl.solve(Wd, to_dev(p, torch.float64), S.Adam(lr=3e-3), tol=1e-8, max_steps=30000, check_every=20,
+                   ladder=True, stall_checks=8, stall_ratio=0.8, switch_rel=1e-5, mid_rel=3e-7,
+                   lr_exact=1e-3, rollback_ratio=10.0, single_backward=True)
+    assert res["status"] == S.OK and res["phase"] == 2, res
+    L_o, _, _ = O.loss_grad(Wd.double().cpu().numpy(), p, n, d)
+    assert math.sqrt(L_o) / np.linalg.norm(p) <= 1e-8
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_exact_forward_is_fp64(prec):
     n, d, k = 6, 4, 420
