@@ -54,7 +54,7 @@ struct Operands {
   const __bf16* a_lo;
   const __bf16* b_hi;
   const __bf16* b_lo;
-  int64_t nkb;  // K blocks of 16 per panel (panel-blocked layout, see blk_off)
+  int64_t pstride;  // elements per (padded) panel of the panel-blocked layout, see blk_off
 };
 
 // Wait until at most n of this wave's vector-memory operations are pending
@@ -83,35 +83,50 @@ __device__ __forceinline__ void wait_vm_barrier() {
 // vector-memory instruction is interlocked, whereas an SGPR base written by
 // a VALU instruction would need 5 wait states before the load), and the
 // SALU write of m0 is followed by s_nop before the load that reads it.
-__device__ __forceinline__ void dma16(const void* base, unsigned voff, char* lds_base) {
-  const unsigned m0 = (unsigned)(uintptr_t)(lds_t)lds_base;
-  const char* gaddr = (const char*)base + voff;
+__device__ __forceinline__ void dma16(const char* gaddr, unsigned m0) {
   asm volatile("s_mov_b32 m0, %0\n\ts_nop 1\n\tglobal_load_lds_dwordx4 %1, off"
                :
-               : "s"(__builtin_amdgcn_readfirstlane(m0)), "v"(gaddr)
+               : "s"(m0), "v"(gaddr)
                : "memory", "m0");
 }
 
-// Issue the direct-to-LDS loads of one stage: wave w moves rows
-// [ROWS_PER_WAVE w, ROWS_PER_WAVE (w + 1)) of each array, 32 rows (1 KB)
-// per instruction, lane l one 16-byte chunk.  With the panel-blocked layout
-// the stage is one contiguous 8 KB block per array, so the 1 KB of one
-// instruction is 8 whole 128-byte lines.
+// LDS byte address of the ring and of this wave's rows in a stage, computed
+// once per tile as wave-uniform values (scalar registers), so that each load
+// costs one 64-bit address add and the m0 write.
+struct RingAddr {
+  unsigned ring;   // LDS address of stage buffer 0
+  unsigned wrow;   // offset of this wave's first row within an array tile
+};
+
+__device__ __forceinline__ RingAddr ring_addr(char* ring) {
+  RingAddr a;
+  a.ring = __builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)(lds_t)ring);
+  a.wrow = __builtin_amdgcn_readfirstlane((unsigned)((threadIdx.x >> 6) * ROWS_PER_WAVE * ROWB));
+  return a;
+}
+
+// Issue the direct-to-LDS loads of one stage into ring buffer `buf`: wave w
+// moves rows [ROWS_PER_WAVE w, ROWS_PER_WAVE (w + 1)) of each array, 32 rows
+// (1 KB) per instruction, lane l one 16-byte chunk.  With the panel-blocked
+// layout the stage is one contiguous 8 KB block per array, so the 1 KB of
+// one instruction is 8 whole 128-byte lines.
 template <bool SPLIT>
-__device__ __forceinline__ void issue_stage(char* st, const Operands& o, int64_t arow0, int64_t brow0, int64_t k0) {
+__device__ __forceinline__ void issue_stage(const RingAddr& ra, int buf, const Operands& o, int64_t arow0,
+                                            int64_t brow0, int64_t k0) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int64_t ablk = ((arow0 / TM) * o.nkb + k0 / BK) * (TM * BK);  // element offset of the block
-  const int64_t bblk = ((brow0 / TM) * o.nkb + k0 / BK) * (TM * BK);
+  const int64_t ablk = (arow0 / TM) * o.pstride + (k0 / BK) * (TM * BK);  // element offset of the block
+  const int64_t bblk = (brow0 / TM) * o.pstride + (k0 / BK) * (TM * BK);
+  const unsigned m = ra.ring + (unsigned)buf * STAGE + ra.wrow;
 #pragma unroll
   for (int h = 0; h < ROWS_PER_WAVE / 32; ++h) {
     const int r = w * ROWS_PER_WAVE + h * 32 + (l >> 1);
     const int c = (l & 1) ^ ((r >> 3) & 1);
-    const unsigned voff = (unsigned)((r * BK + c * 8) * 2);  // bytes inside the block
-    char* base = st + (w * ROWS_PER_WAVE + h * 32) * ROWB;
-    dma16(o.a_hi + ablk, voff, base + 0 * ARR);
-    if (SPLIT) dma16(o.a_lo + ablk, voff, base + 1 * ARR);
-    dma16(o.b_hi + bblk, voff, base + 2 * ARR);
-    if (SPLIT) dma16(o.b_lo + bblk, voff, base + 3 * ARR);
+    const int e = r * BK + c * 8;  // element offset inside the block
+    const unsigned mh = m + h * 32 * ROWB;
+    dma16((const char*)(o.a_hi + ablk + e), mh + 0 * ARR);
+    if (SPLIT) dma16((const char*)(o.a_lo + ablk + e), mh + 1 * ARR);
+    dma16((const char*)(o.b_hi + bblk + e), mh + 2 * ARR);
+    if (SPLIT) dma16((const char*)(o.b_lo + bblk + e), mh + 3 * ARR);
   }
 }
 
@@ -165,7 +180,7 @@ __device__ __forceinline__ void mma_rows(const Frag& f, f32x16 (&acc)[BI][BJ]) {
 // stage kt+1 into `nxt`; the second half of the MFMAs of stage kt covers the
 // latency of those reads.
 template <bool SPLIT>
-__device__ __forceinline__ void pipe_step(Frag& cur, Frag& nxt, char* ring, const Operands& o,
+__device__ __forceinline__ void pipe_step(Frag& cur, Frag& nxt, char* ring, const RingAddr& ra, const Operands& o,
                                           int64_t kt, int64_t nk, int64_t arow0, int64_t brow0,
                                           f32x16 (&acc)[BI][BJ], int wm, int wn) {
   constexpr int per = (SPLIT ? 4 : 2) * (ROWS_PER_WAVE / 32);  // loads per thread per stage
@@ -177,7 +192,7 @@ __device__ __forceinline__ void pipe_step(Frag& cur, Frag& nxt, char* ring, cons
     if (later == 2) wait_vm_barrier<2 * per>();
     else if (later == 1) wait_vm_barrier<per>();
     else wait_vm_barrier<0>();
-    if (kt + NSTAGE < nk) issue_stage<SPLIT>(ring + (kt % NSTAGE) * STAGE, o, arow0, brow0, (kt + NSTAGE) * BK);
+    if (kt + NSTAGE < nk) issue_stage<SPLIT>(ra, (int)(kt % NSTAGE), o, arow0, brow0, (kt + NSTAGE) * BK);
     load_frag<SPLIT>(nxt, ring + ((kt + 1) % NSTAGE) * STAGE, wm, wn);
   }
   __builtin_amdgcn_sched_barrier(0);
@@ -188,14 +203,15 @@ __device__ __forceinline__ void pipe_step(Frag& cur, Frag& nxt, char* ring, cons
 // stages behind it in flight and the refill always happens, so the step has
 // no branches.
 template <bool SPLIT>
-__device__ __forceinline__ void pipe_step_steady(Frag& cur, Frag& nxt, char* ring, const Operands& o, int64_t kt,
+__device__ __forceinline__ void pipe_step_steady(Frag& cur, Frag& nxt, char* ring, const RingAddr& ra, const Operands& o,
+                                                 int64_t kt,
                                                  int64_t arow0, int64_t brow0, f32x16 (&acc)[BI][BJ], int wm,
                                                  int wn) {
   constexpr int per = (SPLIT ? 4 : 2) * (ROWS_PER_WAVE / 32);
   mma_rows<SPLIT, 0, BI / 2>(cur, acc);
   __builtin_amdgcn_sched_barrier(0);
   wait_vm_barrier<2 * per>();
-  issue_stage<SPLIT>(ring + (kt % NSTAGE) * STAGE, o, arow0, brow0, (kt + NSTAGE) * BK);
+  issue_stage<SPLIT>(ra, (int)(kt % NSTAGE), o, arow0, brow0, (kt + NSTAGE) * BK);
   load_frag<SPLIT>(nxt, ring + ((kt + 1) % NSTAGE) * STAGE, wm, wn);
   __builtin_amdgcn_sched_barrier(0);
   mma_rows<SPLIT, BI / 2, BI>(cur, acc);
@@ -213,23 +229,24 @@ __device__ __forceinline__ void tile_gemm(const Operands& o, int64_t K, int64_t 
     for (int bj = 0; bj < BJ; ++bj) acc[bi][bj] = f32x16{};
   constexpr int per = (SPLIT ? 4 : 2) * (ROWS_PER_WAVE / 32);
   const int64_t nk = K / BK;
+  const RingAddr ra = ring_addr(ring);
   for (int s = 0; s < NSTAGE - 1; ++s)
-    if (s < nk) issue_stage<SPLIT>(ring + s * STAGE, o, arow0, brow0, (int64_t)s * BK);
+    if (s < nk) issue_stage<SPLIT>(ra, s, o, arow0, brow0, (int64_t)s * BK);
   // stage 0 must have landed; stages 1 and 2 may be in flight
   if (nk >= 3) wait_vm_barrier<2 * per>();
   else if (nk == 2) wait_vm_barrier<per>();
   else wait_vm_barrier<0>();
-  if (NSTAGE - 1 < nk) issue_stage<SPLIT>(ring + (NSTAGE - 1) * STAGE, o, arow0, brow0, (int64_t)(NSTAGE - 1) * BK);
+  if (NSTAGE - 1 < nk) issue_stage<SPLIT>(ra, NSTAGE - 1, o, arow0, brow0, (int64_t)(NSTAGE - 1) * BK);
   Frag f0, f1;
   load_frag<SPLIT>(f0, ring, wm, wn);
   int64_t kt = 0;
   for (; kt + 1 + NSTAGE < nk; kt += 2) {
-    pipe_step_steady<SPLIT>(f0, f1, ring, o, kt, arow0, brow0, acc, wm, wn);
-    pipe_step_steady<SPLIT>(f1, f0, ring, o, kt + 1, arow0, brow0, acc, wm, wn);
+    pipe_step_steady<SPLIT>(f0, f1, ring, ra, o, kt, arow0, brow0, acc, wm, wn);
+    pipe_step_steady<SPLIT>(f1, f0, ring, ra, o, kt + 1, arow0, brow0, acc, wm, wn);
   }
   for (; kt < nk; kt += 2) {
-    pipe_step<SPLIT>(f0, f1, ring, o, kt, nk, arow0, brow0, acc, wm, wn);
-    if (kt + 1 < nk) pipe_step<SPLIT>(f1, f0, ring, o, kt + 1, nk, arow0, brow0, acc, wm, wn);
+    pipe_step<SPLIT>(f0, f1, ring, ra, o, kt, nk, arow0, brow0, acc, wm, wn);
+    if (kt + 1 < nk) pipe_step<SPLIT>(f1, f0, ring, ra, o, kt + 1, nk, arow0, brow0, acc, wm, wn);
   }
 }
 
@@ -378,7 +395,7 @@ hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s) {
   const char* ws = p->ws;
   g.o.a_hi = g.o.b_hi = (const __bf16*)(ws + p->lay.a_hi);
   g.o.a_lo = g.o.b_lo = (const __bf16*)(ws + p->lay.a_lo);
-  g.o.nkb = p->Kp / kBlkK;
+  g.o.pstride = panel_stride(p->Kp / kBlkK, 2);
   g.K = p->Kp;
   g.tiles = (const int2*)(ws + p->lay.tiles);
   g.ntiles = p->ntiles256;
@@ -399,7 +416,7 @@ hipError_t launch_rw_bf3(const sos_plan_s* p, void* g, bool split, hipStream_t s
   a.o.a_lo = (const __bf16*)(ws + p->lay.R_lo);
   a.o.b_hi = (const __bf16*)(ws + p->lay.t_hi);
   a.o.b_lo = (const __bf16*)(ws + p->lay.t_lo);
-  a.o.nkb = p->Np2 / kBlkK;
+  a.o.pstride = panel_stride(p->Np2 / kBlkK, 2);
   a.K = p->Np2;
   a.TI = (int)(p->Np / bf3::TM);
   a.TL = (int)(p->Kp2 / bf3::TM);

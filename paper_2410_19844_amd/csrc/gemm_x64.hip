@@ -49,11 +49,10 @@ __device__ __forceinline__ int xcd_order(int b, int nb) {
 
 // Direct global->LDS load of 16 bytes per lane; see gemm_bf3.hip for why it
 // is asm and which hazards it covers (VGPR address, s_nop after m0).
-__device__ __forceinline__ void dma16(const char* gaddr, char* lds_base) {
-  const unsigned m0 = (unsigned)(uintptr_t)(lds_t)lds_base;
+__device__ __forceinline__ void dma16(const char* gaddr, unsigned m0) {
   asm volatile("s_mov_b32 m0, %0\n\ts_nop 1\n\tglobal_load_lds_dwordx4 %1, off"
                :
-               : "s"(__builtin_amdgcn_readfirstlane(m0)), "v"(gaddr)
+               : "s"(m0), "v"(gaddr)
                : "memory", "m0");
 }
 
@@ -71,24 +70,27 @@ __device__ __forceinline__ void wait_vm_barrier() {
 constexpr int LOADS = 3;
 
 // Global byte address of row r (within the tile's operand) at stage ks.
-__device__ __forceinline__ const char* row_addr(const float* w, int64_t nkb, int64_t row0, int r, int64_t ks) {
+__device__ __forceinline__ const char* row_addr(const float* w, int64_t pstride, int64_t row0, int r, int64_t ks) {
   const int64_t row = row0 + r;
-  return (const char*)(w + (((row / PANEL) * nkb + ks) * PANEL + row % PANEL) * BK);
+  return (const char*)(w + (row / PANEL) * pstride + (ks * PANEL + row % PANEL) * BK);
 }
 
-__device__ __forceinline__ void issue_stage(char* st, const float* w, int64_t nkb, int64_t arow0, int64_t brow0,
-                                            int64_t ks) {
+// st_lds: wave-uniform LDS address of the stage buffer (scalar register).
+__device__ __forceinline__ void issue_stage(unsigned st_lds, const float* w, int64_t pstride, int64_t arow0,
+                                            int64_t brow0, int64_t ks) {
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const unsigned wave_u = __builtin_amdgcn_readfirstlane((unsigned)wave);
 #pragma unroll
   for (int q = 0; q < LOADS; ++q) {
     const int ins = wave * LOADS + q;  // 0..23: 0..7 A, 8..23 B; 16 rows of 64 B each
+    const unsigned ins_u = wave_u * LOADS + q;
     const int r = (ins < 8 ? ins : ins - 8) * 16 + (l >> 2);
     // LDS slot l & 3 of row r holds chunk (l & 3) ^ ((r >> 2) & 3): 16 consecutive
     // rows read at one chunk then fall in 16 distinct 16-byte bank groups
     const int chunk = (l & 3) ^ ((r >> 2) & 3);
-    const char* g = (ins < 8) ? row_addr(w, nkb, arow0, r, ks) : row_addr(w, nkb, brow0, r, ks);
-    char* base = st + (ins < 8 ? 0 : ABYTES) + (ins < 8 ? ins : ins - 8) * 1024;
-    dma16(g + chunk * 16, base);
+    const char* g = (ins < 8) ? row_addr(w, pstride, arow0, r, ks) : row_addr(w, pstride, brow0, r, ks);
+    const unsigned m0 = st_lds + (ins_u < 8 ? 0u : (unsigned)ABYTES) + (ins_u < 8 ? ins_u : ins_u - 8) * 1024u;
+    dma16(g + chunk * 16, m0);
   }
 }
 
@@ -148,7 +150,8 @@ __device__ __forceinline__ int rank_sum(const RankTab& c, int i, int j) {
 
 struct Args {
   const float* w;     // panel-blocked FP32 W: rows Np, K extent Kp
-  int64_t nkb;        // Kp / 16
+  int64_t nkb;        // Kp / 16: stages
+  int64_t pstride;    // elements per padded panel (see blk_off)
   const int2* tiles;  // 256 x 256 upper-triangle tile list
   int ntiles, N;
   RankTab rk;
@@ -169,8 +172,9 @@ __global__ __launch_bounds__(NT) void k_gram_x64(Args g) {
 #pragma unroll
     for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = f64x4{};
   const int64_t nk = g.nkb;
+  const unsigned ring_lds = __builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)(lds_t)ring);
   for (int s = 0; s < NSTAGE - 1; ++s)
-    if (s < nk) issue_stage(ring + s * STAGE, g.w, g.nkb, arow0, brow0, s);
+    if (s < nk) issue_stage(ring_lds + s * STAGE, g.w, g.pstride, arow0, brow0, s);
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int64_t ahead = nk - 1 - kt;  // stages after kt that have been issued (at most 2)
     if (ahead >= 2) wait_vm_barrier<2 * LOADS>();
@@ -178,7 +182,8 @@ __global__ __launch_bounds__(NT) void k_gram_x64(Args g) {
     else wait_vm_barrier<0>();
     // all waves are past their reads of stage kt-1: refill its buffer
     if (kt + NSTAGE - 1 < nk)
-      issue_stage(ring + ((kt + NSTAGE - 1) % NSTAGE) * STAGE, g.w, g.nkb, arow0, brow0, kt + NSTAGE - 1);
+      issue_stage(ring_lds + (unsigned)((kt + NSTAGE - 1) % NSTAGE) * STAGE, g.w, g.pstride, arow0, brow0,
+                  kt + NSTAGE - 1);
     Frag f;
     load_frag(f, ring + (kt % NSTAGE) * STAGE, wm, wn);
     mma_stage(f, acc);
@@ -208,6 +213,7 @@ hipError_t launch_gram_x64(const sos_plan_s* p, hipStream_t s) {
   const char* ws = p->ws;
   g.w = (const float*)(ws + p->lay.x_f32);
   g.nkb = p->Kp / kBlkK;
+  g.pstride = panel_stride(g.nkb, 4);
   g.tiles = (const int2*)(ws + p->lay.tiles);
   g.ntiles = p->ntiles256;
   g.N = (int)p->N;

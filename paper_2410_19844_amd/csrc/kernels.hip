@@ -86,12 +86,12 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
     tile[r][tx] = v;
     if (i < a.Np && l < a.Kp) {
       const int64_t o = i * a.Kp + l;
-      if (MODE != 0 && a.x_f32) a.x_f32[blk_off(i, l, a.Kp / kBlkK)] = (float)v;
+      if (MODE != 0 && a.x_f32) a.x_f32[blk_off(i, l, panel_stride(a.Kp / kBlkK, 4))] = (float)v;
       if (MODE == 0) ((double*)a.a_hi)[o] = (double)v;
       else if (MODE == 1) ((float*)a.a_hi)[o] = (float)v;
       else {
         const __bf16 h = (__bf16)(float)v;
-        const int64_t ob = blk_off(i, l, a.Kp / kBlkK);
+        const int64_t ob = blk_off(i, l, panel_stride(a.Kp / kBlkK, 2));
         ((__bf16*)a.a_hi)[ob] = h;
         ((__bf16*)a.a_lo)[ob] = (__bf16)((float)v - (float)h);
         if (a.a_f32) a.a_f32[o] = (float)v;
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
       else if (MODE == 1) ((float*)a.t_hi)[o] = (float)v;
       else {
         const __bf16 h = (__bf16)(float)v;
-        const int64_t ob = blk_off(l, i, a.Np2 / kBlkK);
+        const int64_t ob = blk_off(l, i, panel_stride(a.Np2 / kBlkK, 2));
         ((__bf16*)a.t_hi)[ob] = h;
         ((__bf16*)a.t_lo)[ob] = (__bf16)((float)v - (float)h);
       }
@@ -443,26 +443,29 @@ __global__ __launch_bounds__(256) void k_gather(RankCtx rk, const double* __rest
                                                 int64_t Np, int64_t ld, void* R_hi, void* R_lo) {
   const int64_t total = Np * ld;
   const int64_t nkb = ld / kBlkK;
+  const int64_t ps = panel_stride(nkb, 2);
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     int i, j;
-    if (MODE >= 2) {  // e walks the panel-blocked layout (see blk_off)
+    int64_t o = e;
+    if (MODE >= 2) {  // e walks the blocks of the panel-blocked layout in order (see blk_off)
       const int64_t blk = e / (kBlkRows * kBlkK), in = e % (kBlkRows * kBlkK);
       i = (int)((blk / nkb) * kBlkRows + in / kBlkK);
       j = (int)((blk % nkb) * kBlkK + in % kBlkK);
+      o = blk_off(i, j, ps);
     } else {
       i = (int)(e / ld);
       j = (int)(e % ld);
     }
     double v = 0.0;
     if (i < N && j < N) v = r[rank_of_sum(rk, i, j)];
-    if (MODE == 0) ((double*)R_hi)[e] = v;
-    else if (MODE == 1) ((float*)R_hi)[e] = (float)v;
+    if (MODE == 0) ((double*)R_hi)[o] = v;
+    else if (MODE == 1) ((float*)R_hi)[o] = (float)v;
     else {
       const float f = (float)v;
       const __bf16 h = (__bf16)f;
-      ((__bf16*)R_hi)[e] = h;
-      if (MODE == 2) ((__bf16*)R_lo)[e] = (__bf16)(f - (float)h);
+      ((__bf16*)R_hi)[o] = h;
+      if (MODE == 2) ((__bf16*)R_lo)[o] = (__bf16)(f - (float)h);
     }
   }
 }

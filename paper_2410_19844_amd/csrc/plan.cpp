@@ -160,16 +160,21 @@ int plan_create(int n, int d, int rank, int prec, sos_plan_s** out) {
   L.r = take((size_t)M * 8);
   L.tiles = take(p->tile_list.size() * 4);
   L.scal = take(1024 * 8);   // [0..7] scalars, [8..519] reduction partials
-  L.a_hi = take((size_t)p->Np * p->Kp * oel);
-  if (prec == SOS_BF16X3) L.a_lo = take((size_t)p->Np * p->Kp * oel);
-  L.t_hi = take((size_t)p->Kp2 * p->Np2 * oel);
-  if (prec == SOS_BF16X3) L.t_lo = take((size_t)p->Kp2 * p->Np2 * oel);
-  L.R_hi = take((size_t)p->Np * p->Np2 * oel);
-  if (prec == SOS_BF16X3) L.R_lo = take((size_t)p->Np * p->Np2 * oel);
+  // split-bf16 operands are panel-blocked with padded panels (see blk_off)
+  const bool blk = prec == SOS_BF16X3;
+  const size_t a_el = blk ? (size_t)(p->Np / kBlkRows) * panel_stride(p->Kp / kBlkK, 2) : (size_t)p->Np * p->Kp;
+  const size_t t_el = blk ? (size_t)(p->Kp2 / kBlkRows) * panel_stride(p->Np2 / kBlkK, 2) : (size_t)p->Kp2 * p->Np2;
+  const size_t R_el = blk ? (size_t)(p->Np / kBlkRows) * panel_stride(p->Np2 / kBlkK, 2) : (size_t)p->Np * p->Np2;
+  L.a_hi = take(a_el * oel);
+  if (blk) L.a_lo = take(a_el * oel);
+  L.t_hi = take(t_el * oel);
+  if (blk) L.t_lo = take(t_el * oel);
+  L.R_hi = take(R_el * oel);
+  if (blk) L.R_lo = take(R_el * oel);
   // split-precision plans keep an FP32 padded copy of W for the exact FP64 forward
   // (FP32 plans use a_hi, which already is that copy)
   if (prec == SOS_BF16X3) L.a_f32 = take((size_t)p->Np * p->Kp * 4);
-  if (prec != SOS_FP64) L.x_f32 = take((size_t)p->Np * p->Kp * 4);
+  if (prec != SOS_FP64) L.x_f32 = take((size_t)(p->Np / kBlkRows) * panel_stride(p->Kp / kBlkK, 4) * 4);
   L.g = take((size_t)N * rank * wel);
   L.bytes = off;
   p->state_bytes = round_up((size_t)N * rank * wel, 256) * 4;  // m, v, best W, candidate W

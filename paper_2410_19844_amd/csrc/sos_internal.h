@@ -32,10 +32,17 @@ constexpr int kPadK = 64;        // operand K extents padded to this multiple (z
 // K in blocks of 16; block (panel, kb) is 256 rows x 16 elements stored
 // contiguously (8 KB of bf16), blocks of one panel consecutive in kb.  A
 // GEMM stage then reads one contiguous 8 KB block per array.
+// Consecutive panels are kPanelPadBytes further apart than their data, so
+// the blocks that concurrent tiles read at one K (one per panel) do not all
+// sit at the same offset modulo the L2 channel interleave.
 constexpr int kBlkRows = 256;
 constexpr int kBlkK = 16;
-__host__ __device__ inline int64_t blk_off(int64_t row, int64_t k, int64_t nkb) {
-  return (((row / kBlkRows) * nkb + k / kBlkK) * kBlkRows + row % kBlkRows) * kBlkK + k % kBlkK;
+constexpr int kPanelPadBytes = 4096;
+__host__ __device__ inline int64_t panel_stride(int64_t nkb, int elem_bytes) {
+  return nkb * kBlkRows * kBlkK + kPanelPadBytes / elem_bytes;
+}
+__host__ __device__ inline int64_t blk_off(int64_t row, int64_t k, int64_t pstride) {
+  return (row / kBlkRows) * pstride + ((k / kBlkK) * kBlkRows + row % kBlkRows) * kBlkK + k % kBlkK;
 }
 
 struct Layout {
