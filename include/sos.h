@@ -204,12 +204,36 @@ int sos_solve(sos_plan_t plan, void* d_W, void* d_state, const double* d_p,
 int sos_verify(sos_plan_t plan, const void* d_W, const double* d_p, double* h_rel,
                double* d_r, void* stream);
 
-/* Serving: one Adam step for `count` independent problems in one set of
- * launches.  plans[q] (bound, distinct workspaces), W[q], state[q], t[q],
- * p[q] as in sos_step; d_losses[q] receives problem q's loss.  All plans
- * must share the precision.                                               */
+/* Largest basis size N for which a plan supports the grouped (serving)
+ * calls below.                                                            */
+#define SOS_BATCH_MAX_N 1024
+
+/* Serving: one Adam step (Section 3 loop body) for `count` independent small
+ * problems in one set of grouped launches.  plans[q] must be bound SOS_FP32
+ * plans with N <= SOS_BATCH_MAX_N and distinct workspaces; d_W[q] (N x k
+ * FP32, row-major), d_state[q] (sos_plan_query's state_bytes; m and v as in
+ * sos_step), t[q] (1-based Adam step count) and d_p[q] (M FP64) as in
+ * sos_step.  d_losses[q] (device) receives L of problem q at the W before
+ * the update.  Any count >= 0 is accepted; the library launches in groups.
+ *
+ * Numerics: the forward forms every Gram entry from exact FP64 products of
+ * the FP32 entries, summed in FP64, then each coefficient sums its (i <= j)
+ * pairs in one fixed order (eq. basicsos, no atomics); the backward 4 R W
+ * is FP32; Adam is FP32.  Every problem's arithmetic is independent of the
+ * others in the call, and the order of every sum is fixed, so a problem's
+ * results are bitwise the same alone and in any mix.  Asynchronous on
+ * `stream`.  Errors: SOS_EINVAL for NULL arrays, unbound or non-FP32 plans,
+ * t < 1; SOS_ERANGE for a plan with N > SOS_BATCH_MAX_N.                  */
 int sos_step_batch(const sos_plan_t* plans, void* const* d_W, void* const* d_state,
                    const int64_t* t, const double* const* d_p, const sos_adam_t* adam,
+                   double* d_losses, int count, void* stream);
+
+/* Serving certificate: the grouped forward of sos_step_batch alone.
+ * d_losses[q] = ||coeff(W_q W_q^T) - p_q||^2 in FP64 (exact FP64 products of
+ * the FP32 entries, fixed summation order), so sqrt(d_losses[q]) / ||p_q||
+ * is the FP64-verified relative residual of W_q.  Same plan requirements
+ * and errors as sos_step_batch; asynchronous on `stream`.               */
+int sos_loss_batch(const sos_plan_t* plans, const void* const* d_W, const double* const* d_p,
                    double* d_losses, int count, void* stream);
 
 /* Kernel classes reported by sos_timing_read. */

@@ -25,6 +25,7 @@ FLAG_COPIES_VALID = 2
 FLAG_SINGLE_BACKWARD = 4
 FLAG_FP32_FORWARD = 8
 OK, NOT_CONVERGED = 0, 1
+EINVAL, ERANGE, ENOMEM, EHIP, ENUMERIC = -1, -2, -3, -4, -5
 
 
 class SosError(RuntimeError):
@@ -74,6 +75,7 @@ def _load():
         "sos_verify": (I, [P, V, V, ctypes.POINTER(ctypes.c_double), V, V]),
         "sos_step_batch": (I, [ctypes.POINTER(P), ctypes.POINTER(V), ctypes.POINTER(V),
                                ctypes.POINTER(I64), ctypes.POINTER(V), ctypes.POINTER(_Adam), V, I, V]),
+        "sos_loss_batch": (I, [ctypes.POINTER(P), ctypes.POINTER(V), ctypes.POINTER(V), V, I, V]),
         "sos_timing": (I, [P, I]),
         "sos_timing_read": (I, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]),
         "sos_last_error": (ctypes.c_char_p, []),
@@ -88,7 +90,7 @@ def _load():
 _lib = _load()
 EXPORTS = ("sos_plan", "sos_plan_query", "sos_plan_bind", "sos_plan_destroy", "sos_exponents",
            "sos_pair_ranks", "sos_loss_grad", "sos_step", "sos_solve", "sos_verify",
-           "sos_step_batch", "sos_timing", "sos_timing_read", "sos_last_error")
+           "sos_step_batch", "sos_loss_batch", "sos_timing", "sos_timing_read", "sos_last_error")
 KERNEL_CLASSES = ("prep", "init_r", "gram", "loss", "gather", "rw", "adam")
 
 
@@ -236,15 +238,36 @@ class Plan:
         return {f: getattr(res, f) for f, _ in _Result._fields_}
 
 
+BATCH_MAX_N = 1024   # largest basis size N of a plan the grouped calls take
+
+
 def step_batch(plans, Ws, states, ts, ps, adam: Adam, losses, stream=None):
-    """One Adam step for several independent problems (serving)."""
+    """sos_step_batch: one Adam step for several independent problems (serving).
+
+    FP32 plans with N <= BATCH_MAX_N; losses[q] gets problem q's loss at the
+    W before the update.  A problem's results do not depend on the others.
+    """
     n = len(plans)
+    for pl, W, p in zip(plans, Ws, ps):
+        pl._w(W), pl._p(p)
     P = (ctypes.c_void_p * n)(*[pl._h for pl in plans])
     Wv = (ctypes.c_void_p * n)(*[W.data_ptr() for W in Ws])
     Sv = (ctypes.c_void_p * n)(*[s.data_ptr() for s in states])
     Tv = (ctypes.c_int64 * n)(*[int(t) for t in ts])
     Pv = (ctypes.c_void_p * n)(*[p.data_ptr() for p in ps])
     _check(_lib.sos_step_batch(P, Wv, Sv, Tv, Pv, ctypes.byref(adam.c()), _ptr(losses), n, _stream(stream)))
+    return losses
+
+
+def loss_batch(plans, Ws, ps, losses, stream=None):
+    """sos_loss_batch: FP64 loss of each W_q (the serving certificate)."""
+    n = len(plans)
+    for pl, W, p in zip(plans, Ws, ps):
+        pl._w(W), pl._p(p)
+    P = (ctypes.c_void_p * n)(*[pl._h for pl in plans])
+    Wv = (ctypes.c_void_p * n)(*[W.data_ptr() for W in Ws])
+    Pv = (ctypes.c_void_p * n)(*[p.data_ptr() for p in ps])
+    _check(_lib.sos_loss_batch(P, Wv, Pv, _ptr(losses), n, _stream(stream)))
     return losses
 
 

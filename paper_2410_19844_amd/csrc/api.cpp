@@ -1,5 +1,6 @@
 // C ABI of libsos (declared in include/sos.h): argument checks, call
 // sequencing on the caller's stream, and the host side of the solve loop.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -200,6 +201,12 @@ int sos_plan_bind(sos_plan_t p, void* d_ws, size_t ws_bytes, void* stream) {
           "sos_plan_bind: tables");
   SOS_HIP(hipMemcpyAsync(p->ws + p->lay.tiles, p->tile_list.data(), p->tile_list.size() * 4, hipMemcpyHostToDevice, s),
           "sos_plan_bind: tiles");
+  if (p->batchable) {
+    SOS_HIP(hipMemcpyAsync(p->ws + p->lay.pair_off, p->pair_off.data(), p->pair_off.size() * 4,
+                           hipMemcpyHostToDevice, s), "sos_plan_bind: pair offsets");
+    SOS_HIP(hipMemcpyAsync(p->ws + p->lay.pair_idx, p->pair_idx.data(), p->pair_idx.size() * 4,
+                           hipMemcpyHostToDevice, s), "sos_plan_bind: pair lists");
+  }
   SOS_HIP(hipStreamSynchronize(s), "sos_plan_bind");
   p->bound = true;
   return SOS_OK;
@@ -382,21 +389,49 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
   return res->status;
 }
 
+static int check_batch(const sos_plan_t* plans, const void* const* W, const double* const* d_p, double* losses,
+                       int count, const char* what) {
+  if (count < 0) return set_error(SOS_EINVAL, std::string(what) + ": count < 0");
+  if (count > 0 && (!plans || !W || !d_p || !losses)) return set_error(SOS_EINVAL, std::string(what) + ": NULL array");
+  for (int q = 0; q < count; ++q) {
+    if (int rc = check_bound(plans[q], what)) return rc;
+    if (plans[q]->prec != SOS_FP32)
+      return set_error(SOS_EINVAL, std::string(what) + ": grouped calls take SOS_FP32 plans");
+    if (!plans[q]->batchable)
+      return set_error(SOS_ERANGE, std::string(what) + ": plan has N > SOS_BATCH_MAX_N");
+    if (!W[q] || !d_p[q]) return set_error(SOS_EINVAL, std::string(what) + ": NULL W or p");
+  }
+  return SOS_OK;
+}
+
 int sos_step_batch(const sos_plan_t* plans, void* const* d_W, void* const* d_state, const int64_t* t,
                    const double* const* d_p, const sos_adam_t* adam, double* d_losses, int count,
                    void* stream) {
-  if (count < 0 || (count > 0 && (!plans || !d_W || !d_state || !t || !d_p || !d_losses)))
-    return set_error(SOS_EINVAL, "sos_step_batch: NULL argument");
+  if (int rc = check_batch(plans, (const void* const*)d_W, d_p, d_losses, count, "sos_step_batch")) return rc;
+  if (count == 0) return SOS_OK;
+  if (!d_state || !t) return set_error(SOS_EINVAL, "sos_step_batch: NULL state or t");
   if (int rc = check_adam(adam, "sos_step_batch")) return rc;
   for (int q = 0; q < count; ++q) {
-    if (int rc = check_bound(plans[q], "sos_step_batch")) return rc;
-    if (q > 0 && plans[q]->prec != plans[0]->prec)
-      return set_error(SOS_EINVAL, "sos_step_batch: all plans must share the precision");
+    if (!d_state[q]) return set_error(SOS_EINVAL, "sos_step_batch: NULL state");
     if (t[q] < 1) return set_error(SOS_EINVAL, "sos_step_batch: t is 1-based");
   }
-  for (int q = 0; q < count; ++q) {
-    int rc = run_step(plans[q], d_W[q], d_state[q], t[q], d_p[q], *adam, d_losses + q, 0, (hipStream_t)stream);
-    if (rc) return rc;
+  const int cap = batch_capacity();
+  for (int q0 = 0; q0 < count; q0 += cap) {
+    const int c = std::min(cap, count - q0);
+    SOS_HIP(launch_step_group(plans + q0, d_W + q0, d_state + q0, t + q0, d_p + q0, adam, d_losses + q0, c,
+                              (hipStream_t)stream), "sos_step_batch");
+  }
+  return SOS_OK;
+}
+
+int sos_loss_batch(const sos_plan_t* plans, const void* const* d_W, const double* const* d_p, double* d_losses,
+                   int count, void* stream) {
+  if (int rc = check_batch(plans, d_W, d_p, d_losses, count, "sos_loss_batch")) return rc;
+  const int cap = batch_capacity();
+  for (int q0 = 0; q0 < count; q0 += cap) {
+    const int c = std::min(cap, count - q0);
+    SOS_HIP(launch_step_group(plans + q0, (void* const*)(d_W + q0), nullptr, nullptr, d_p + q0, nullptr,
+                              d_losses + q0, c, (hipStream_t)stream), "sos_loss_batch");
   }
   return SOS_OK;
 }

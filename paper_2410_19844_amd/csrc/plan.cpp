@@ -176,6 +176,34 @@ int plan_create(int n, int d, int rank, int prec, sos_plan_s** out) {
   if (prec == SOS_BF16X3) L.a_f32 = take((size_t)p->Np * p->Kp * 4);
   if (prec != SOS_FP64) L.x_f32 = take((size_t)(p->Np / kBlkRows) * panel_stride(p->Kp / kBlkK, 4) * 4);
   L.g = take((size_t)N * rank * wel);
+  // Grouped serving path: the coefficient of monomial m sums the Gram entries
+  // of its pairs (i <= j, alpha_i + alpha_j = m) in one fixed order (i, then
+  // j, ascending), so a problem's forward is deterministic.  The pair lists
+  // are the inverse of the ranking map, built here once (counting sort).
+  if (prec == SOS_FP32 && N <= SOS_BATCH_MAX_N) {
+    p->batchable = true;
+    auto rank_of = [&](int64_t i, int64_t j) {
+      int64_t r = 0;
+      for (int w = 0; w < p->nwords; ++w) {
+        const uint32_t s = p->codes[i * p->nwords + w] + p->codes[j * p->nwords + w];
+        r += p->tables[(size_t)(2 * w) * kGroupEntries + (s & 0xFFFu)];
+        if (2 * w + 1 < p->ngroups) r += p->tables[(size_t)(2 * w + 1) * kGroupEntries + ((s >> 16) & 0xFFFu)];
+      }
+      return r;
+    };
+    p->pair_off.assign(M + 1, 0);
+    for (int64_t i = 0; i < N; ++i)
+      for (int64_t j = i; j < N; ++j) ++p->pair_off[rank_of(i, j) + 1];
+    for (int64_t m = 0; m < M; ++m) p->pair_off[m + 1] += p->pair_off[m];
+    p->pair_idx.assign(N * (N + 1) / 2, 0);
+    std::vector<int32_t> fill(p->pair_off.begin(), p->pair_off.end() - 1);
+    for (int64_t i = 0; i < N; ++i)
+      for (int64_t j = i; j < N; ++j)
+        p->pair_idx[fill[rank_of(i, j)]++] = (int32_t)((uint32_t)(i * N + j) | (i < j ? 0x80000000u : 0u));
+    L.bG = take((size_t)N * N * 8);
+    L.pair_off = take(p->pair_off.size() * 4);
+    L.pair_idx = take(p->pair_idx.size() * 4);
+  }
   L.bytes = off;
   p->state_bytes = round_up((size_t)N * rank * wel, 256) * 4;  // m, v, best W, candidate W
   *out = p;

@@ -55,6 +55,10 @@ struct Layout {
   size_t a_f32 = 0;              // FP32 padded W (split-precision plans), rows = Np, ld = Kp
   size_t x_f32 = 0;              // FP32 W, panel-blocked (exact forward), rows = Np, K extent Kp
   size_t g = 0;                  // gradient scratch, N x k in W's type
+  // grouped (serving) path, FP32 plans with N <= SOS_BATCH_MAX_N only
+  size_t bG = 0;                 // FP64 Gram, N x N row-major (upper triangle used)
+  size_t pair_off = 0;           // M + 1 int32: pairs of coefficient m are pair_idx[off[m] .. off[m+1])
+  size_t pair_idx = 0;           // N (N + 1) / 2 int32: i * N + j (i <= j), bit 31 set when i < j
   size_t bytes = 0;
 };
 
@@ -75,6 +79,8 @@ struct sos_plan_s {
   sos::Layout lay;
   int ntiles256 = 0;               // upper-triangle tiles of 256 x 256
   std::vector<int32_t> tile_list;  // 2 * ntiles256
+  bool batchable = false;          // grouped (serving) calls supported
+  std::vector<int32_t> pair_off, pair_idx;
   size_t state_bytes = 0;
   char* ws = nullptr;
   size_t ws_size = 0;
@@ -115,4 +121,9 @@ hipError_t launch_gram_x64(const sos_plan_s* p, hipStream_t s);
 hipError_t launch_rw_bf3(const sos_plan_s* p, void* g, bool split, hipStream_t s);
 hipError_t launch_adam(const sos_plan_s* p, void* W, void* m, void* v, const void* g, int64_t t,
                        const sos_adam_t& h, hipStream_t s);
+// grouped serving kernels (batch.hip); at most batch_capacity() problems per call
+int batch_capacity();
+hipError_t launch_step_group(sos_plan_s* const* plans, void* const* W, void* const* state, const int64_t* t,
+                             const double* const* p, const sos_adam_t* h, double* losses, int count,
+                             hipStream_t s);
 }  // namespace sos

@@ -325,30 +325,3 @@ def test_sosloss_autograd_matches_fd_and_oracle():
         assert abs(g[i, j] - g_o[i, j]) <= tb * gabs[i, j] + gabs_fwd[i, j]
 
 
-# ---------------------------------------------------------------------------
-# Serving batch = the same steps one by one
-# ---------------------------------------------------------------------------
-
-def test_step_batch_matches_single_steps():
-    shapes = [(3, 2, 20), (4, 3, 70), (5, 2, 42)]
-    adam = S.Adam(lr=1e-2)
-    plans, Ws, sts, ps, refs = [], [], [], [], []
-    for q, (n, d, k) in enumerate(shapes):
-        W64, Wd, p, pd = make_case(n, d, k, "fp32", seed=q)
-        plans.append(S.Plan(n, d, k, "fp32"))
-        Ws.append(Wd)
-        sts.append(plans[-1].new_state())
-        ps.append(pd)
-        solo = S.Plan(n, d, k, "fp32")
-        Wsolo, st_solo = Wd.clone(), solo.new_state()
-        ls = []
-        for t in range(1, 4):
-            ls.append(solo.step(Wsolo, st_solo, t, pd, adam).item())
-        refs.append((Wsolo, ls))
-    losses = torch.empty(len(shapes), dtype=torch.float64, device=dev())
-    for t in range(1, 4):
-        S.step_batch(plans, Ws, sts, [t] * len(shapes), ps, adam, losses)
-        for q in range(len(shapes)):
-            assert abs(losses[q].item() - refs[q][1][t - 1]) <= 1e-6 * refs[q][1][t - 1]
-    for q in range(len(shapes)):
-        assert torch.allclose(Ws[q], refs[q][0], rtol=1e-5, atol=1e-6)

@@ -1,0 +1,258 @@
+"""Serving: the grouped kernels (sos_step_batch, sos_loss_batch) against the
+FP64 oracle, and the continuous-batching server (determinism alone vs in
+the mix, HBM admission, verdicts checked by the oracle).
+
+Tolerances: the grouped forward forms FP64 sums of exact products of FP32
+entries, so coefficients (and the loss) take the FP64 bound 1e-10 relative
+to cabs = coeff(|W||W|^T); the grouped backward is FP32, bound
+gamma(N+1) + 2^-24 relative to gabs = 4 |R| |W| (a dot product of N terms
+plus the FP64 -> FP32 rounding of R).
+"""
+import math
+from math import comb
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import gaussian, motzkin_terms
+
+torch = pytest.importorskip("torch")
+S = pytest.importorskip("paper_2410_19844_amd")
+from paper_2410_19844_amd import serve  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+TOL64 = 1e-10
+
+
+def gamma(n):
+    return n * U32 / (1 - n * U32)
+
+
+def dev():
+    return torch.device("cuda")
+
+
+# (n, d, k): ragged tiles (N and k off the 32 / 64 grid), one-tile, multi-tile
+# and the largest basis the grouped path takes (n=10, d=4: N = 1001)
+MIX = [(1, 1, 3), (3, 2, 20), (4, 3, 37), (2, 5, 7), (6, 3, 168), (5, 6, 50), (8, 4, 990), (10, 4, 70)]
+
+
+def make_mix(shapes, seed0=0):
+    plans, Ws, W64s, ps, p64s = [], [], [], [], []
+    for q, (n, d, k) in enumerate(shapes):
+        N, M = comb(n + d, d), comb(n + 2 * d, 2 * d)
+        W = gaussian((N, k), 300 + seed0 + q, 1.0 / math.sqrt(k))
+        Wd = torch.tensor(W, dtype=torch.float32, device=dev())
+        p = gaussian(M, 400 + seed0 + q)
+        plans.append(S.Plan(n, d, k, "fp32"))
+        Ws.append(Wd)
+        W64s.append(Wd.double().cpu().numpy())
+        ps.append(torch.tensor(p, dtype=torch.float64, device=dev()))
+        p64s.append(p)
+    return plans, Ws, W64s, ps, p64s
+
+
+def test_loss_batch_matches_oracle():
+    plans, Ws, W64s, ps, p64s = make_mix(MIX)
+    losses = torch.empty(len(MIX), dtype=torch.float64, device=dev())
+    S.loss_batch(plans, Ws, ps, losses)
+    L = losses.cpu().numpy()
+    for q, (n, d, k) in enumerate(MIX):
+        pr = O.pair_ranks(n, d)
+        Lo, _, r = O.loss_grad(W64s[q], p64s[q], n, d, pr)
+        cabs = O.coefficients_abs(W64s[q], n, d, pr)
+        dc = TOL64 * cabs
+        bound = 2 * np.sum(np.abs(r) * dc) + np.sum(dc * dc)
+        assert abs(L[q] - Lo) <= bound, (n, d, k, L[q], Lo, bound)
+
+
+def test_step_batch_gradient_matches_oracle():
+    """With beta1 = 0 the first moment after one step is the gradient itself."""
+    shapes = MIX + [(3, 3, 40)] * 20          # 28 problems: more than one group of launches
+    plans, Ws, W64s, ps, p64s = make_mix(shapes, seed0=50)
+    states = [pl.new_state() for pl in plans]
+    losses = torch.empty(len(shapes), dtype=torch.float64, device=dev())
+    adam = S.Adam(lr=1e-3, beta1=0.0, beta2=0.999, eps=1e-8)
+    W_before = [W.clone() for W in Ws]
+    S.step_batch(plans, Ws, states, [1] * len(shapes), ps, adam, losses)
+    L = losses.cpu().numpy()
+    for q, (n, d, k) in enumerate(shapes):
+        N = plans[q].N
+        pr = O.pair_ranks(n, d)
+        Lo, go, r = O.loss_grad(W64s[q], p64s[q], n, d, pr)
+        cabs = O.coefficients_abs(W64s[q], n, d, pr)
+        dc = TOL64 * cabs
+        assert abs(L[q] - Lo) <= 2 * np.sum(np.abs(r) * dc) + np.sum(dc * dc), (q, L[q], Lo)
+        m = states[q][: N * k * 4].view(torch.float32).reshape(N, k).double().cpu().numpy()
+        gabs = 4.0 * np.abs(r[pr]) @ np.abs(W64s[q])
+        err = np.abs(m - go)
+        bound = (gamma(N + 1) + U32) * gabs + 1e-9 * np.abs(go).max() + 1e-300
+        assert np.max(err / bound) <= 1.0, (q, n, d, k, float(np.max(err / bound)))
+        # the update of that step: W - lr * g / (|g| + eps) at t = 1, up to the
+        # FP32 rounding of Adam's own arithmetic (beta2 = 0.999 is not exact in FP32)
+        g64 = torch.tensor(m, dtype=torch.float64, device=dev())
+        want = W_before[q].double() - 1e-3 * g64 / (g64.abs() + 1e-8)
+        slack = 2e-5 * 1e-3 + 2.0 ** -23 * want.abs()
+        assert bool(((Ws[q].double() - want).abs() <= slack).all()), q
+
+
+def test_step_batch_matches_single_exact_steps():
+    """Three grouped steps = three sos_step calls with the exact forward (FP64
+    sums of FP32 products in both); the backward differs in FP32 rounding only."""
+    shapes = [(3, 2, 20), (4, 3, 70), (5, 2, 42), (8, 4, 990)]
+    adam = S.Adam(lr=1e-2)
+    plans, Ws, W64s, ps, _ = make_mix(shapes, seed0=80)
+    sts = [pl.new_state() for pl in plans]
+    refs = []
+    for q, (n, d, k) in enumerate(shapes):
+        solo = S.Plan(n, d, k, "fp32")
+        Wsolo, st_solo = Ws[q].clone(), solo.new_state()
+        ls = [solo.step(Wsolo, st_solo, t, ps[q], adam, flags=S.FLAG_EXACT_FORWARD).item() for t in range(1, 4)]
+        refs.append((Wsolo, ls))
+    losses = torch.empty(len(shapes), dtype=torch.float64, device=dev())
+    for t in range(1, 4):
+        S.step_batch(plans, Ws, sts, [t] * len(shapes), ps, adam, losses)
+        for q in range(len(shapes)):
+            want = refs[q][1][t - 1]
+            assert abs(losses[q].item() - want) <= (1e-12 if t == 1 else 1e-5) * want, (q, t)
+    for q in range(len(shapes)):
+        assert torch.allclose(Ws[q], refs[q][0], rtol=1e-5, atol=1e-6), q
+
+
+def test_batch_errors():
+    pl64 = S.Plan(3, 2, 5, "fp64")
+    W = torch.zeros((pl64.N, 5), dtype=torch.float64, device=dev())
+    p = torch.zeros(pl64.M, dtype=torch.float64, device=dev())
+    losses = torch.empty(1, dtype=torch.float64, device=dev())
+    with pytest.raises(S.SosError) as e:
+        S.loss_batch([pl64], [W], [p], losses)
+    assert e.value.code == S.EINVAL
+    big = S.Plan(10, 5, 3, "fp32")                      # N = 3003 > 1024
+    Wb = torch.zeros((big.N, 3), dtype=torch.float32, device=dev())
+    pb = torch.zeros(big.M, dtype=torch.float64, device=dev())
+    with pytest.raises(S.SosError) as e:
+        S.loss_batch([big], [Wb], [pb], losses)
+    assert e.value.code == S.ERANGE
+    S.loss_batch([], [], [], losses)                    # empty batch: nothing to do
+
+
+# ---------------------------------------------------------------------------
+# The server
+# ---------------------------------------------------------------------------
+
+def build_requests(specs):
+    """specs: (id, n, d, kind, arrival).  W0 rank ceil(N/4), W init N(0, 1/k)
+    with k = 2N, seeds 2 id and 2 id + 1 (as in the serving workload)."""
+    reqs = []
+    for rid, n, d, kind, arrival in specs:
+        N = comb(n + d, d)
+        k = 2 * N
+        W0 = gaussian((N, -(-N // 4)), 2 * rid)
+        Wi = gaussian((N, k), 2 * rid + 1, 1.0 / math.sqrt(k))
+        if kind == "sos":
+            reqs.append(serve.sos_request(rid, n, d, k, W0, Wi, arrival=arrival))
+        else:
+            reqs.append(serve.motzkin_request(rid, n, d, k, motzkin_terms(n), W0, Wi, arrival=arrival))
+    return reqs
+
+
+SPECS = [(0, 5, 3, "sos", 0.0), (1, 8, 4, "sos", 0.0), (2, 4, 2, "sos", 0.0), (3, 3, 3, "non", 0.0),
+         (4, 3, 4, "sos", 0.01), (5, 6, 2, "sos", 0.02), (6, 4, 4, "non", 0.02), (7, 7, 3, "sos", 0.05),
+         (8, 3, 3, "sos", 0.05), (9, 8, 2, "sos", 0.1)]
+
+
+@pytest.fixture(scope="module")
+def mixed_run():
+    reqs = build_requests(SPECS)
+    srv = serve.Server(max_active=6, check_every=50, tol=1e-6, max_steps=3000, keep_W=True)
+    res = srv.run(reqs)
+    return reqs, srv, res
+
+
+def test_server_alone_vs_mix_bitwise(mixed_run):
+    reqs, srv, res = mixed_run
+    assert [r.id for r in res] == [s[0] for s in SPECS]
+    assert srv.peak_active > 1            # the mix really ran problems together
+    for req, r in zip(reqs, res):
+        alone = serve.Server(max_active=1, check_every=50, tol=1e-6, max_steps=3000, keep_W=True)
+        solo = req.__class__(**{**req.__dict__, "arrival": 0.0})
+        (a,) = alone.run([solo])
+        assert (a.verdict, a.reason, a.steps) == (r.verdict, r.reason, r.steps), req.id
+        assert a.rel == r.rel, req.id
+        assert torch.equal(a.W, r.W), req.id
+
+
+def oracle_p(rid, n, d, kind):
+    """The request's p from the oracle alone (W0 rounded to FP32, as the server's is)."""
+    N = comb(n + d, d)
+    W0 = gaussian((N, -(-N // 4)), 2 * rid).astype(np.float32).astype(np.float64)
+    c = O.coefficients(W0, n, d)
+    if kind == "sos":
+        return c
+    return O.poly_vector(motzkin_terms(n), n, d) + 1e-3 * c / np.linalg.norm(c)
+
+
+def oracle_run(rid, n, d, p, lr, tol, budget, check_every):
+    """The oracle's Adam from the request's starting W, checked like the server
+    checks (the loss of the W before the last update, every check_every
+    steps).  Returns (first step that met tol or None, best rel seen)."""
+    N = comb(n + d, d)
+    k = 2 * N
+    W = gaussian((N, k), 2 * rid + 1, 1.0 / math.sqrt(k)).astype(np.float32).astype(np.float64)
+    st = O.AdamState(np.zeros_like(W), np.zeros_like(W))
+    pr = O.pair_ranks(n, d)
+    pn = np.linalg.norm(p)
+    best = math.inf
+    for t in range(1, budget + 1):
+        L, g, _ = O.loss_grad(W, p, n, d, pr)
+        W = O.adam_step(W, g, st, lr)
+        if t % check_every == 0:
+            rel = math.sqrt(L) / pn
+            best = min(best, rel)
+            if rel <= tol:
+                return t, rel
+    return None, best
+
+
+def test_server_verdicts_vs_oracle(mixed_run):
+    reqs, srv, res = mixed_run
+    decided = 0
+    for (rid, n, d, kind, _), req, r in zip(SPECS, reqs, res):
+        assert r.steps <= 3000 and r.steps % 50 == 0
+        p = oracle_p(rid, n, d, kind)
+        # the server's p (built on the GPU) is the oracle's up to FP64 rounding
+        assert np.allclose(req.p.cpu().numpy(), p, rtol=1e-12, atol=1e-12 * np.abs(p).max()), rid
+        if r.verdict == "sos":
+            # the certificate holds in the oracle's own FP64 arithmetic
+            W64 = r.W.double().cpu().numpy()
+            rel_o = np.linalg.norm(O.residual(W64, p, n, d)) / np.linalg.norm(p)
+            assert rel_o <= 1e-6, (rid, rel_o)
+            assert abs(rel_o - r.rel) <= 1e-6 * rel_o + 1e-13, (rid, rel_o, r.rel)
+        if kind == "non":
+            # a Motzkin-based p is not SOS: nothing certifies it, here or in the oracle
+            assert r.verdict == "not certified" and r.rel > 1e-3, (rid, r.rel)
+            continue
+        hit, best = oracle_run(rid, n, d, p, 3e-2, 1e-6, 3000, 50)
+        if hit is not None and hit <= 1500:
+            assert r.verdict == "sos", (rid, hit)
+            decided += 1
+        elif hit is None and best > 1e-5:
+            assert r.verdict == "not certified", (rid, best)
+            decided += 1
+    assert decided >= 5
+
+
+def test_server_admission_respects_budget():
+    reqs = build_requests([(20, 8, 4, "sos", 0.0), (21, 7, 4, "sos", 0.0), (22, 8, 3, "sos", 0.0),
+                           (23, 6, 4, "sos", 0.0), (24, 3, 3, "sos", 0.0)])
+    fps = sorted(serve.footprint(q.n, q.d, q.rank) for q in reqs)
+    budget = fps[-1] + fps[-2]
+    srv = serve.Server(hbm_budget=budget, max_active=8, check_every=50, tol=1e-6, max_steps=600)
+    res = srv.run(reqs)
+    assert len(res) == len(reqs)
+    assert srv.peak_bytes <= budget
+    with pytest.raises(ValueError):
+        serve.Server(hbm_budget=fps[0] - 1).run(reqs[:1])
