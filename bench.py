@@ -11,6 +11,11 @@ master W, FP64 residual.  Prints one JSON line.
 
 --mode ttt runs sos_solve from the same start to an FP64-verified relative
 residual <= tol and reports the time to target instead of steps/s.
+
+--mode serve runs the serving workload (SOS checks of mixed n in 3..8,
+d in 2..4, half SOS by construction, half Motzkin-based non-SOS): first all
+--requests queued at t = 0 (closed loop: saturation solves/s), then the same
+requests as a Poisson stream at 0.8 x that rate (p50 / p99 latency).
 """
 from __future__ import annotations
 
@@ -40,7 +45,10 @@ def parse():
     ap.add_argument("--exact", action="store_true", help="FP64 forward (the finishing phase)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=1024)
-    ap.add_argument("--mode", default="step", choices=["step", "ttt"])
+    ap.add_argument("--mode", default="step", choices=["step", "ttt", "serve"])
+    ap.add_argument("--requests", type=int, default=1024, help="serve: requests in the stream")
+    ap.add_argument("--slots", type=int, default=48, help="serve: requests on the device at once")
+    ap.add_argument("--hbm-budget-gib", type=float, default=32.0, help="serve: device memory for active requests")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-steps", type=int, default=3000)
     ap.add_argument("--lr", type=float, default=None)
@@ -107,6 +115,68 @@ def cpu_baseline(c, rows):
                       f"{dt:.1f} s, scaled by rows/N"}
 
 
+def serve_requests(S, torch, count):
+    """The serving stream as requests on the device (built before any timing)."""
+    from paper_2410_19844_amd import serve
+    from workloads import gaussian, motzkin_terms, serving_stream
+    out = []
+    for q in serving_stream(count):
+        W0 = gaussian((q["N"], q["w0_rank"]), q["w0_seed"])
+        Wi = gaussian((q["N"], q["rank"]), q["w_seed"], 1.0 / math.sqrt(q["rank"]))
+        if q["sos"]:
+            r = serve.sos_request(q["id"], q["n"], q["d"], q["rank"], W0, Wi, arrival=q["arrival"])
+        else:
+            r = serve.motzkin_request(q["id"], q["n"], q["d"], q["rank"], motzkin_terms(q["n"]), W0, Wi,
+                                      arrival=q["arrival"])
+        out.append(r)
+    torch.cuda.synchronize()
+    return out
+
+
+def serve_mode(a, S, torch):
+    from paper_2410_19844_amd import serve
+    import dataclasses
+    reqs = serve_requests(S, torch, a.requests)
+    mk = lambda: serve.Server(hbm_budget=int(a.hbm_budget_gib * (1 << 30)), max_active=a.slots,
+                              check_every=50, tol=1e-6, max_steps=20000, stall_checks=20, stall_ratio=0.5)
+    at0 = lambda rs: [dataclasses.replace(r, arrival=0.0) for r in rs]
+    mk().run(at0(reqs[:min(len(reqs), 2 * a.slots)]))        # warm-up: kernels loaded, pools grown
+    torch.cuda.synchronize()
+    srv = mk()
+    t0 = time.perf_counter()
+    res = srv.run(at0(reqs))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sat = len(res) / wall
+    rate = 0.8 * sat
+    base = reqs[0].arrival
+    pois = [dataclasses.replace(r, arrival=(r.arrival - base) / rate) for r in reqs]   # stream drawn at rate 1
+    srv2 = mk()
+    t0 = time.perf_counter()
+    res2 = srv2.run(pois)
+    wall2 = time.perf_counter() - t0
+    lat = np.array([r.latency for r in res2])
+    steps = np.array([r.steps for r in res])
+    verdicts = {}
+    for r in res:
+        verdicts[f"{r.verdict}/{r.reason}"] = verdicts.get(f"{r.verdict}/{r.reason}", 0) + 1
+    labels = {"sos": sum(1 for q in reqs if q.label == "sos"), "non-sos": sum(1 for q in reqs if q.label != "sos")}
+    out = {"metric": "serving solves/s (SOS checks, n 3..8, d 2..4, rank 2N, FP64-verified tol 1e-6)",
+           "value": sat, "unit": "solves/s", "n_gpus": 1, "steps": int(steps.sum()), "warmup": 1,
+           "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "fp32+fp64-forward", "data": "synthetic",
+           "config": {"workload": f"serving stream: {len(reqs)} requests (seed 12345), {labels}",
+                      "slots": a.slots, "hbm_budget_gib": a.hbm_budget_gib, "check_every": 50,
+                      "max_steps": 20000, "stall": "20 checks without halving", "lr": 3e-2},
+           "closed_loop": {"solves_per_s": sat, "wall_s": wall, "grouped_steps": srv.iterations * 50,
+                           "request_steps": int(steps.sum()), "peak_active": srv.peak_active,
+                           "peak_bytes": srv.peak_bytes, "verdicts": verdicts},
+           "poisson": {"rate_per_s": rate, "solves_per_s": len(res2) / wall2, "wall_s": wall2,
+                       "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                       "mean_ms": 1e3 * float(lat.mean()), "peak_active": srv2.peak_active}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -116,6 +186,9 @@ def main():
     import torch
     import paper_2410_19844_amd as S
 
+    if a.mode == "serve":
+        serve_mode(a, S, torch)
+        return
     c, W, p = make_inputs(S, torch, a.workload, a.precision)
     pl = S.Plan(c.n, c.d, c.rank, a.precision)
     lr = a.lr if a.lr is not None else 3e-3
