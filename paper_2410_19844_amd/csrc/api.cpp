@@ -88,13 +88,21 @@ static int fwd_mode(const sos_plan_s* p, int flags) {
   return kFwdFast;
 }
 
+// grad: a backward follows (so the transposed operand copies are needed)
 static int run_forward(sos_plan_s* p, const void* W, const double* d_p, int flags, double* d_loss,
-                       hipStream_t s) {
+                       bool grad, hipStream_t s) {
   const int mode = fwd_mode(p, flags);
-  TIMED(SOS_K_PREP, launch_prep(p, W, mode != kFwdFast, s), "prep");
+  PrepNeeds need;
+  need.a = p->prec == SOS_FP64 || mode == kFwdFast;
+  need.a_f32 = mode == kFwdF32;
+  need.x_f32 = mode == kFwdExact;
+  need.t = grad;
+  need.t_lo = grad && (flags & SOS_FLAG_SINGLE_BACKWARD) == 0;
+  TIMED(SOS_K_PREP, launch_prep(p, W, need, s), "prep");
   TIMED(SOS_K_INIT, launch_init_r(p, d_p, s), "init_r");
   TIMED(SOS_K_GRAM, launch_gram(p, mode, s), "gram");
-  TIMED(SOS_K_LOSS, launch_sumsq(p, (const double*)(p->ws + p->lay.r), p->M, d_loss, s), "loss");
+  float* r32 = (grad && p->prec != SOS_FP64) ? (float*)(p->ws + p->lay.r32) : nullptr;
+  TIMED(SOS_K_LOSS, launch_sumsq(p, (const double*)(p->ws + p->lay.r), p->M, d_loss, s, r32), "loss");
   return SOS_OK;
 }
 
@@ -106,7 +114,7 @@ static int run_backward(sos_plan_s* p, void* g, bool split, hipStream_t s) {
 
 static int run_step(sos_plan_s* p, void* W, void* state, int64_t t, const double* d_p,
                     const sos_adam_t& h, double* d_loss, int flags, hipStream_t s) {
-  int rc = run_forward(p, W, d_p, flags, d_loss, s);
+  int rc = run_forward(p, W, d_p, flags, d_loss, true, s);
   if (rc) return rc;
   void* g = p->ws + p->lay.g;
   rc = run_backward(p, g, (flags & SOS_FLAG_SINGLE_BACKWARD) == 0, s);
@@ -247,7 +255,7 @@ int sos_loss_grad(sos_plan_t p, const void* d_W, const double* d_p, double* d_lo
   if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_SINGLE_BACKWARD | SOS_FLAG_FP32_FORWARD))
     return set_error(SOS_EINVAL, "sos_loss_grad: unknown flags");
   hipStream_t s = (hipStream_t)stream;
-  int rc = run_forward(p, d_W, d_p, flags, d_loss, s);
+  int rc = run_forward(p, d_W, d_p, flags, d_loss, d_grad != nullptr, s);
   if (rc) return rc;
   if (d_grad && (rc = run_backward(p, d_grad, (flags & SOS_FLAG_SINGLE_BACKWARD) == 0, s))) return rc;
   if (d_r)
@@ -272,7 +280,7 @@ int sos_verify(sos_plan_t p, const void* d_W, const double* d_p, double* h_rel, 
   if (!d_W || !d_p || !h_rel) return set_error(SOS_EINVAL, "sos_verify: NULL argument");
   hipStream_t s = (hipStream_t)stream;
   double* sc = scal(p);
-  int rc = run_forward(p, d_W, d_p, SOS_FLAG_EXACT_FORWARD, sc + 0, s);
+  int rc = run_forward(p, d_W, d_p, SOS_FLAG_EXACT_FORWARD, sc + 0, false, s);
   if (rc) return rc;
   SOS_HIP(launch_sumsq(p, d_p, p->M, sc + 1, s), "sos_verify: ||p||");
   double h[2];

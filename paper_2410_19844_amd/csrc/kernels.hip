@@ -71,7 +71,8 @@ struct PrepArgs {
 
 // 64 x 64 tiles through LDS so that both the row-major and the transposed
 // copies are written with coalesced stores.  Mode: 0 = FP64, 1 = FP32,
-// 2 = bf16 hi/lo split (plus the FP32 copy when a_f32 != nullptr).
+// 2 = bf16 hi/lo split.  Each destination is written only when its pointer
+// is set: the caller asks for the copies its forward and backward read.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
   using WT = typename std::conditional<MODE == 0, double, float>::type;
@@ -87,17 +88,22 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
     if (i < a.Np && l < a.Kp) {
       const int64_t o = i * a.Kp + l;
       if (MODE != 0 && a.x_f32) a.x_f32[blk_off(i, l, panel_stride(a.Kp / kBlkK, 4))] = (float)v;
-      if (MODE == 0) ((double*)a.a_hi)[o] = (double)v;
-      else if (MODE == 1) ((float*)a.a_hi)[o] = (float)v;
-      else {
-        const __bf16 h = (__bf16)(float)v;
-        const int64_t ob = blk_off(i, l, panel_stride(a.Kp / kBlkK, 2));
-        ((__bf16*)a.a_hi)[ob] = h;
-        ((__bf16*)a.a_lo)[ob] = (__bf16)((float)v - (float)h);
+      if (MODE == 0) {
+        if (a.a_hi) ((double*)a.a_hi)[o] = (double)v;
+      } else if (MODE == 1) {
+        if (a.a_hi) ((float*)a.a_hi)[o] = (float)v;
+      } else {
+        if (a.a_hi) {
+          const __bf16 h = (__bf16)(float)v;
+          const int64_t ob = blk_off(i, l, panel_stride(a.Kp / kBlkK, 2));
+          ((__bf16*)a.a_hi)[ob] = h;
+          ((__bf16*)a.a_lo)[ob] = (__bf16)((float)v - (float)h);
+        }
         if (a.a_f32) a.a_f32[o] = (float)v;
       }
     }
   }
+  if (!a.t_hi) return;
   __syncthreads();
   for (int r = ty; r < 64; r += 4) {
     const int64_t l = l0 + r, i = i0 + tx;
@@ -110,7 +116,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
         const __bf16 h = (__bf16)(float)v;
         const int64_t ob = blk_off(l, i, panel_stride(a.Np2 / kBlkK, 2));
         ((__bf16*)a.t_hi)[ob] = h;
-        ((__bf16*)a.t_lo)[ob] = (__bf16)((float)v - (float)h);
+        if (a.t_lo) ((__bf16*)a.t_lo)[ob] = (__bf16)((float)v - (float)h);
       }
     }
   }
@@ -145,13 +151,15 @@ __device__ double block_sum(double v) {
   return s;
 }
 
+// x32 (optional): FP32 copy of x, written on the way (the gather of R reads it)
 __global__ __launch_bounds__(256) void k_sumsq_partial(const double* __restrict__ x, int64_t M,
-                                                       double* __restrict__ partial) {
+                                                       double* __restrict__ partial, float* __restrict__ x32) {
   double s = 0;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < M;
        e += (int64_t)gridDim.x * blockDim.x) {
     const double v = x[e];
     s += v * v;
+    if (x32) x32[e] = (float)v;
   }
   s = block_sum(s);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -470,6 +478,75 @@ __global__ __launch_bounds__(256) void k_gather(RankCtx rk, const double* __rest
   }
 }
 
+// Gather of R for FP32 and split plans, 8 consecutive columns j per thread:
+// one 16-byte store per array (bf16) or two (FP32), the row's code loaded
+// once.  r32 is the FP32 copy of r: R is rounded to FP32 first in every one
+// of these modes, so reading the copy gives the same bits as reading r.
+// Mode 1 = FP32 row-major, 2 = bf16 hi and lo (blocked), 3 = bf16 hi only.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_gather8(RankCtx rk, const float* __restrict__ r32, int N, int64_t Np,
+                                                 int64_t ld, void* R_hi, void* R_lo) {
+  const int64_t total8 = Np * ld / 8;
+  const int64_t nkb = ld / kBlkK;
+  const int64_t ps = panel_stride(nkb, 2);
+  for (int64_t e8 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e8 < total8;
+       e8 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = e8 * 8;
+    int i, j0;
+    int64_t o;
+    if (MODE >= 2) {  // e walks the blocks of the panel-blocked layout in order (see blk_off)
+      const int64_t blk = e / (kBlkRows * kBlkK), in = e % (kBlkRows * kBlkK);
+      i = (int)((blk / nkb) * kBlkRows + in / kBlkK);
+      j0 = (int)((blk % nkb) * kBlkK + in % kBlkK);
+      o = blk_off(i, j0, ps);
+    } else {
+      i = (int)(e / ld);
+      j0 = (int)(e % ld);
+      o = e;
+    }
+    float v[8];
+    if (i < N) {
+      uint32_t ci[kMaxWords];
+#pragma unroll
+      for (int w = 0; w < kMaxWords; ++w) ci[w] = (w < rk.nwords) ? rk.codes[(size_t)i * rk.nwords + w] : 0u;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int j = j0 + q;
+        v[q] = 0.f;
+        if (j < N) {
+          int rr = 0;
+#pragma unroll
+          for (int w = 0; w < kMaxWords; ++w) {
+            if (w < rk.nwords) {
+              const uint32_t sw = ci[w] + rk.codes[(size_t)j * rk.nwords + w];
+              rr += rk.tables[(2 * w) * kGroupEntries + (sw & 0xFFFu)];
+              if (2 * w + 1 < rk.ngroups) rr += rk.tables[(2 * w + 1) * kGroupEntries + ((sw >> 16) & 0xFFFu)];
+            }
+          }
+          v[q] = r32[rr];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = 0.f;
+    }
+    if (MODE == 1) {
+      float4* d = (float4*)((float*)R_hi + o);
+      d[0] = make_float4(v[0], v[1], v[2], v[3]);
+      d[1] = make_float4(v[4], v[5], v[6], v[7]);
+    } else {
+      bf16x8 h, lo;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        h[q] = (__bf16)v[q];
+        lo[q] = (__bf16)(v[q] - (float)h[q]);
+      }
+      *(bf16x8*)((__bf16*)R_hi + o) = h;
+      if (MODE == 2) *(bf16x8*)((__bf16*)R_lo + o) = lo;
+    }
+  }
+}
+
 struct RwArgs {
   const void* A[2];   // R arrays: rows Np, ld K
   const void* B[2];   // W^T arrays: rows Kp2, ld K
@@ -545,16 +622,17 @@ hipError_t launch_pair_ranks(const sos_plan_s* p, int32_t* out, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_prep(const sos_plan_s* p, const void* W, bool want_f32, hipStream_t s) {
+hipError_t launch_prep(const sos_plan_s* p, const void* W, const PrepNeeds& need, hipStream_t s) {
   PrepArgs a;
   a.W = W; a.N = (int)p->N; a.k = p->k;
   a.Np = p->Np; a.Kp = p->Kp; a.Kp2 = p->Kp2; a.Np2 = p->Np2;
-  a.a_hi = p->ws + p->lay.a_hi;
-  a.a_lo = p->prec == SOS_BF16X3 ? p->ws + p->lay.a_lo : nullptr;
-  a.a_f32 = (p->prec == SOS_BF16X3 && want_f32) ? (float*)(p->ws + p->lay.a_f32) : nullptr;
-  a.x_f32 = (p->prec != SOS_FP64 && want_f32) ? (float*)(p->ws + p->lay.x_f32) : nullptr;
-  a.t_hi = p->ws + p->lay.t_hi;
-  a.t_lo = p->prec == SOS_BF16X3 ? p->ws + p->lay.t_lo : nullptr;
+  const bool split = p->prec == SOS_BF16X3;
+  a.a_hi = need.a ? p->ws + p->lay.a_hi : nullptr;
+  a.a_lo = (need.a && split) ? p->ws + p->lay.a_lo : nullptr;
+  a.a_f32 = (split && need.a_f32) ? (float*)(p->ws + p->lay.a_f32) : nullptr;
+  a.x_f32 = (p->prec != SOS_FP64 && need.x_f32) ? (float*)(p->ws + p->lay.x_f32) : nullptr;
+  a.t_hi = need.t ? p->ws + p->lay.t_hi : nullptr;
+  a.t_lo = (need.t && need.t_lo && split) ? p->ws + p->lay.t_lo : nullptr;
   const int64_t rows = p->Np > p->Np2 ? p->Np : p->Np2;
   const int64_t cols = p->Kp2 > p->Kp ? p->Kp2 : p->Kp;
   dim3 grid((unsigned)(cols / 64), (unsigned)(rows / 64));
@@ -569,9 +647,9 @@ hipError_t launch_init_r(const sos_plan_s* p, const double* d_p, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t launch_sumsq(const sos_plan_s* p, const double* x, int64_t M, double* out, hipStream_t s) {
+hipError_t launch_sumsq(const sos_plan_s* p, const double* x, int64_t M, double* out, hipStream_t s, float* x32) {
   double* partial = (double*)(p->ws + p->lay.scal) + 8;
-  k_sumsq_partial<<<kSumBlocks, 256, 0, s>>>(x, M, partial);
+  k_sumsq_partial<<<kSumBlocks, 256, 0, s>>>(x, M, partial, x32);
   k_sumsq_final<<<1, 256, 0, s>>>(partial, out);
   return hipGetLastError();
 }
@@ -630,14 +708,19 @@ static hipError_t rw_launch(const sos_plan_s* p, void* g, hipStream_t s) {
 hipError_t launch_gather(const sos_plan_s* p, bool split, hipStream_t s) {
   char* ws = p->ws;
   const RankCtx rk = rank_ctx(p);
-  const double* r = (const double*)(ws + p->lay.r);
   const int64_t total = p->Np * p->Np2;
   void* Rh = ws + p->lay.R_hi;
   void* Rl = p->prec == SOS_BF16X3 ? ws + p->lay.R_lo : nullptr;
-  if (p->prec == SOS_FP64) k_gather<0><<<grid_for(total), 256, 0, s>>>(rk, r, (int)p->N, p->Np, p->Np2, Rh, Rl);
-  else if (p->prec == SOS_FP32) k_gather<1><<<grid_for(total), 256, 0, s>>>(rk, r, (int)p->N, p->Np, p->Np2, Rh, Rl);
-  else if (split) k_gather<2><<<grid_for(total), 256, 0, s>>>(rk, r, (int)p->N, p->Np, p->Np2, Rh, Rl);
-  else k_gather<3><<<grid_for(total), 256, 0, s>>>(rk, r, (int)p->N, p->Np, p->Np2, Rh, Rl);
+  if (p->prec == SOS_FP64) {
+    const double* r = (const double*)(ws + p->lay.r);
+    k_gather<0><<<grid_for(total), 256, 0, s>>>(rk, r, (int)p->N, p->Np, p->Np2, Rh, Rl);
+    return hipGetLastError();
+  }
+  const float* r32 = (const float*)(ws + p->lay.r32);
+  const int grid = grid_for(total / 8);
+  if (p->prec == SOS_FP32) k_gather8<1><<<grid, 256, 0, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, Rh, Rl);
+  else if (split) k_gather8<2><<<grid, 256, 0, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, Rh, Rl);
+  else k_gather8<3><<<grid, 256, 0, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, Rh, Rl);
   return hipGetLastError();
 }
 

@@ -158,6 +158,7 @@ int plan_create(int n, int d, int rank, int prec, sos_plan_s** out) {
   L.codes = take((size_t)N * p->nwords * 4);
   L.tables = take(p->tables.size() * 4);
   L.r = take((size_t)M * 8);
+  if (prec != SOS_FP64) L.r32 = take((size_t)M * 4);
   L.tiles = take(p->tile_list.size() * 4);
   L.scal = take(1024 * 8);   // [0..7] scalars, [8..519] reduction partials
   // split-bf16 operands are panel-blocked with padded panels (see blk_off)

@@ -48,6 +48,7 @@ __host__ __device__ inline int64_t blk_off(int64_t row, int64_t k, int64_t pstri
 struct Layout {
   // byte offsets into the workspace
   size_t codes = 0, tables = 0, r = 0, scal = 0;
+  size_t r32 = 0;                // FP32 copy of r (FP32 and split plans; read by the gather)
   size_t tiles = 0;              // (I, J) pairs of 256-row upper-triangle tiles, int2
   size_t a_hi = 0, a_lo = 0;     // W operand copies, rows = Np, ld = Kp   (forward A/B)
   size_t t_hi = 0, t_lo = 0;     // W^T operand copies, rows = Kp2, ld = Np2 (backward B)
@@ -109,9 +110,18 @@ int hip_error(hipError_t e, const char* what);
 namespace sos {
 // kernel launchers (kernels.hip)
 hipError_t launch_pair_ranks(const sos_plan_s* p, int32_t* out, hipStream_t s);
-hipError_t launch_prep(const sos_plan_s* p, const void* W, bool want_f32, hipStream_t s);
+// which operand copies k_prep writes (the ones the coming forward and backward read)
+struct PrepNeeds {
+  bool a = false;      // forward operands: a_hi (+ a_lo for split plans)
+  bool a_f32 = false;  // FP32 row-major copy (FP32 rung of split plans)
+  bool x_f32 = false;  // FP32 blocked copy (exact forward)
+  bool t = false;      // transposed copy for the backward (t_hi)
+  bool t_lo = false;   // its lo half (three-product backward of split plans)
+};
+hipError_t launch_prep(const sos_plan_s* p, const void* W, const PrepNeeds& need, hipStream_t s);
 hipError_t launch_init_r(const sos_plan_s* p, const double* d_p, hipStream_t s);
-hipError_t launch_sumsq(const sos_plan_s* p, const double* x, int64_t M, double* out, hipStream_t s);
+hipError_t launch_sumsq(const sos_plan_s* p, const double* x, int64_t M, double* out, hipStream_t s,
+                        float* x32 = nullptr);
 enum { kFwdFast = 0, kFwdF32 = 1, kFwdExact = 2 };
 hipError_t launch_gram(const sos_plan_s* p, int mode, hipStream_t s);
 hipError_t launch_gather(const sos_plan_s* p, bool split, hipStream_t s);
