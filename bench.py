@@ -20,6 +20,7 @@ requests as a Poisson stream at 0.8 x that rate (p50 / p99 latency).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -62,6 +63,33 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy first (scale reference for HBM byte counters)")
     return ap.parse_args()
+
+
+def kernel_sources_hash():
+    """Hash of the library's kernel sources (the HBM counters stored under
+    profiles/ are only used while it still matches)."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2410_19844_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(key):
+    """HBM bytes per launch of one kernel from the rocprofv3 FETCH_SIZE and
+    WRITE_SIZE runs summarised in profiles/ (scaled by a plain copy's counts),
+    or None when the kernels have changed since, or nothing was measured."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "n12d6_hbm_traffic.json")) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != kernel_sources_hash():
+        return None
+    v = d.get("kernels", {}).get(key)
+    return None if v is None else v["read_bytes"] + v["write_bytes"]
 
 
 def make_inputs(S, torch, wl, prec):
@@ -252,6 +280,11 @@ def main():
     else:
         peak = PEAKS_TFLOPS[a.precision]
     achieved = flops[dom] / (per_launch[dom] * 1e-3) / 1e12
+    traffic = None
+    if c.name == "n12d6" and a.precision == "bf16x3" and a.single_backward:
+        key = {("gram", False): "step:k_gram_bf3", ("gram", True): "exact:k_gram_x64",
+               ("rw", False): "step:k_rw_bf3<false>", ("rw", True): "step:k_rw_bf3<false>"}[(dom, a.exact)]
+        traffic = measured_traffic(key)
     out = {
         "metric": f"grad steps/s at n={c.n} d={c.d}", "value": 1e3 / ms_step, "unit": "steps/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_step,
@@ -264,7 +297,8 @@ def main():
                    "precision": a.precision, "exact_forward": a.exact, "lr": lr,
                    "single_backward": a.single_backward},
         "roofline": {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": traffic,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1)",
                      "algorithmic_flops": flops[dom], "avg_ms": per_launch[dom],
                      "executed_mfma_factor": (1 if (dom == "rw" and a.single_backward) else 3)
                      if (a.precision == "bf16x3" and not (a.exact and dom == "gram")) else 1},
