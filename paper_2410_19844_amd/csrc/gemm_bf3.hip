@@ -5,10 +5,13 @@
 // v_mfma_f32_32x32x16_bf16 with FP32 accumulation (lo*lo' is dropped).
 //
 // Tile: 256 x 256 outputs per workgroup; each wave owns WM x WN of it
-// (WM / 32 x WN / 32 MFMA blocks of 32 x 32).  K advances in stages
-// of 16 through a 4-deep ring of LDS stages (4 arrays x 256 rows x 32 B =
-// 32 KB each) filled by direct global->LDS loads issued three stages ahead,
-// so an L2 miss has about three stages of MFMA work to hide behind.
+// (WM / 32 x WN / 32 MFMA blocks of 32 x 32).  K advances through a 4-deep
+// ring of LDS stages (4 slots x 256 rows x 32 B = 32 KB each) filled by
+// direct global->LDS loads issued three stages ahead, so an L2 miss has
+// about three stages of MFMA work to hide behind.  A stage's four slots
+// hold A_hi, A_lo, B_hi, B_lo of one K block of 16 (split products), or,
+// for single products, A_hi and B_hi of two consecutive K blocks (32 K per
+// stage: twice the MFMA work per barrier).
 //
 // Tile order is XCD-aware: workgroups are dispatched round-robin over the 8
 // XCDs (each with its own L2), so consecutive workgroups of one XCD are
@@ -26,7 +29,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int TM = 256;
-constexpr int BK = 16;            // K per pipeline stage (one MFMA k-step)
+constexpr int BK = 16;            // K per slot (one MFMA k-step, one block of the blocked layout)
 constexpr int WM = 128;           // rows of the output tile per wave
 constexpr int WN = 128;           // columns of the output tile per wave
 constexpr int BI = WM / 32, BJ = WN / 32;     // 32 x 32 MFMA blocks per wave
@@ -37,7 +40,10 @@ constexpr int ROWS_PER_WAVE = TM / NWAVES;    // rows each wave loads per array
 constexpr int NSTAGE = 4;         // LDS stages; loads run NSTAGE - 1 stages ahead
 constexpr int ROWB = BK * 2;      // bytes per row per array (32)
 constexpr int ARR = TM * ROWB;    // bytes per array tile (8 KB)
-constexpr int STAGE = 4 * ARR;    // A_hi, A_lo, B_hi, B_lo (32 KB)
+constexpr int STAGE = 4 * ARR;    // four slots (32 KB)
+// K per stage: one block with split products, two blocks with single products
+template <bool SPLIT>
+constexpr int kstage() { return SPLIT ? BK : 2 * BK; }
 constexpr int kXcds = 8;
 
 typedef __attribute__((address_space(3))) void* lds_t;
@@ -49,6 +55,8 @@ __device__ __forceinline__ int slot_off(int row, int chunk) {
   return row * ROWB + ((chunk ^ ((row >> 3) & 1)) << 4);
 }
 
+// Slot sources.  With single products a_lo / b_lo point one K block past
+// a_hi / b_hi (the second K block of the stage), not at lo arrays.
 struct Operands {
   const __bf16* a_hi;
   const __bf16* a_lo;
@@ -105,11 +113,11 @@ __device__ __forceinline__ RingAddr ring_addr(char* ring) {
   return a;
 }
 
-// Issue the direct-to-LDS loads of one stage into ring buffer `buf`: wave w
-// moves rows [ROWS_PER_WAVE w, ROWS_PER_WAVE (w + 1)) of each array, 32 rows
-// (1 KB) per instruction, lane l one 16-byte chunk.  With the panel-blocked
-// layout the stage is one contiguous 8 KB block per array, so the 1 KB of
-// one instruction is 8 whole 128-byte lines.
+// Issue the direct-to-LDS loads of one stage (starting at K = k0) into ring
+// buffer `buf`: wave w moves rows [ROWS_PER_WAVE w, ROWS_PER_WAVE (w + 1))
+// of each slot, 32 rows (1 KB) per instruction, lane l one 16-byte chunk.
+// With the panel-blocked layout a slot is one contiguous 8 KB block, so the
+// 1 KB of one instruction is 8 whole 128-byte lines.
 template <bool SPLIT>
 __device__ __forceinline__ void issue_stage(const RingAddr& ra, int buf, const Operands& o, int64_t arow0,
                                             int64_t brow0, int64_t k0) {
@@ -124,9 +132,9 @@ __device__ __forceinline__ void issue_stage(const RingAddr& ra, int buf, const O
     const int e = r * BK + c * 8;  // element offset inside the block
     const unsigned mh = m + h * 32 * ROWB;
     dma16((const char*)(o.a_hi + ablk + e), mh + 0 * ARR);
-    if (SPLIT) dma16((const char*)(o.a_lo + ablk + e), mh + 1 * ARR);
+    dma16((const char*)(o.a_lo + ablk + e), mh + 1 * ARR);
     dma16((const char*)(o.b_hi + bblk + e), mh + 2 * ARR);
-    if (SPLIT) dma16((const char*)(o.b_lo + bblk + e), mh + 3 * ARR);
+    dma16((const char*)(o.b_lo + bblk + e), mh + 3 * ARR);
   }
 }
 
@@ -148,12 +156,12 @@ __device__ __forceinline__ void load_frag(Frag& f, const char* st, int wm, int w
 #pragma unroll
   for (int bi = 0; bi < BI; ++bi) {
     f.ah[bi] = *(const bf16x8*)(a + bi * 32 * ROWB);
-    if (SPLIT) f.al[bi] = *(const bf16x8*)(a + ARR + bi * 32 * ROWB);
+    f.al[bi] = *(const bf16x8*)(a + ARR + bi * 32 * ROWB);
   }
 #pragma unroll
   for (int bj = 0; bj < BJ; ++bj) {
     f.bh[bj] = *(const bf16x8*)(b + bj * 32 * ROWB);
-    if (SPLIT) f.bl[bj] = *(const bf16x8*)(b + ARR + bj * 32 * ROWB);
+    f.bl[bj] = *(const bf16x8*)(b + ARR + bj * 32 * ROWB);
   }
 }
 
@@ -167,8 +175,11 @@ __device__ __forceinline__ void mma_rows(const Frag& f, f32x16 (&acc)[BI][BJ]) {
       if (SPLIT) {
         acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.al[bi], f.bh[bj], acc[bi][bj], 0, 0, 0);
         acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.ah[bi], f.bl[bj], acc[bi][bj], 0, 0, 0);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.ah[bi], f.bh[bj], acc[bi][bj], 0, 0, 0);
+      } else {  // two K blocks: slot pairs (hi, hi) and (lo, lo) hold blocks 0 and 1
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.ah[bi], f.bh[bj], acc[bi][bj], 0, 0, 0);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.al[bi], f.bl[bj], acc[bi][bj], 0, 0, 0);
       }
-      acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.ah[bi], f.bh[bj], acc[bi][bj], 0, 0, 0);
     }
 }
 
@@ -183,7 +194,7 @@ template <bool SPLIT>
 __device__ __forceinline__ void pipe_step(Frag& cur, Frag& nxt, char* ring, const RingAddr& ra, const Operands& o,
                                           int64_t kt, int64_t nk, int64_t arow0, int64_t brow0,
                                           f32x16 (&acc)[BI][BJ], int wm, int wn) {
-  constexpr int per = (SPLIT ? 4 : 2) * (ROWS_PER_WAVE / 32);  // loads per thread per stage
+  constexpr int per = 4 * (ROWS_PER_WAVE / 32);  // loads per thread per stage
   mma_rows<SPLIT, 0, BI / 2>(cur, acc);
   __builtin_amdgcn_sched_barrier(0);
   if (kt + 1 < nk) {
@@ -192,32 +203,44 @@ __device__ __forceinline__ void pipe_step(Frag& cur, Frag& nxt, char* ring, cons
     if (later == 2) wait_vm_barrier<2 * per>();
     else if (later == 1) wait_vm_barrier<per>();
     else wait_vm_barrier<0>();
-    if (kt + NSTAGE < nk) issue_stage<SPLIT>(ra, (int)(kt % NSTAGE), o, arow0, brow0, (kt + NSTAGE) * BK);
+    if (kt + NSTAGE < nk) issue_stage<SPLIT>(ra, (int)(kt % NSTAGE), o, arow0, brow0, (kt + NSTAGE) * kstage<SPLIT>());
     load_frag<SPLIT>(nxt, ring + ((kt + 1) % NSTAGE) * STAGE, wm, wn);
   }
   __builtin_amdgcn_sched_barrier(0);
   mma_rows<SPLIT, BI / 2, BI>(cur, acc);
 }
 
-// The same step in the steady state (kt + 4 < nk): stage kt+1 has two
-// stages behind it in flight and the refill always happens, so the step has
-// no branches.
+// The same step in the steady state (kt + 4 < nk), ordered differently: the
+// barrier comes first (stage kt+1 has landed, and every wave is done reading
+// the buffer of stage kt, whose fragments are in registers), then the refill
+// of that buffer with stage kt+4, then the MFMAs of stage kt with the
+// fragment reads of stage kt+1 interleaved among them, so that the reads
+// have the whole stage's MFMA time to complete.  No branches.
 template <bool SPLIT>
 __device__ __forceinline__ void pipe_step_steady(Frag& cur, Frag& nxt, char* ring, const RingAddr& ra, const Operands& o,
                                                  int64_t kt,
                                                  int64_t arow0, int64_t brow0, f32x16 (&acc)[BI][BJ], int wm,
                                                  int wn) {
-  constexpr int per = (SPLIT ? 4 : 2) * (ROWS_PER_WAVE / 32);
-  mma_rows<SPLIT, 0, BI / 2>(cur, acc);
-  __builtin_amdgcn_sched_barrier(0);
+  constexpr int per = 4 * (ROWS_PER_WAVE / 32);
+  constexpr int NMFMA = BI * BJ * (SPLIT ? 3 : 2);
+  constexpr int NREAD = 2 * (BI + BJ);
+  constexpr int RATIO = NMFMA / NREAD;
   wait_vm_barrier<2 * per>();
-  issue_stage<SPLIT>(ra, (int)(kt % NSTAGE), o, arow0, brow0, (kt + NSTAGE) * BK);
-  load_frag<SPLIT>(nxt, ring + ((kt + 1) % NSTAGE) * STAGE, wm, wn);
+  issue_stage<SPLIT>(ra, (int)(kt % NSTAGE), o, arow0, brow0, (kt + NSTAGE) * kstage<SPLIT>());
   __builtin_amdgcn_sched_barrier(0);
-  mma_rows<SPLIT, BI / 2, BI>(cur, acc);
+  load_frag<SPLIT>(nxt, ring + ((kt + 1) % NSTAGE) * STAGE, wm, wn);
+  mma_rows<SPLIT, 0, BI>(cur, acc);
+  // scheduling pattern: RATIO MFMAs (mask 0x008), one LDS read (mask 0x100), ...
+#pragma unroll
+  for (int q = 0; q < NREAD; ++q) {
+    __builtin_amdgcn_sched_group_barrier(0x008, RATIO, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+  }
+  __builtin_amdgcn_sched_group_barrier(0x008, NMFMA - RATIO * NREAD, 0);
+  __builtin_amdgcn_sched_barrier(0);
 }
 
-// C(256 x 256) = A[arow0 .. +256) x B[brow0 .. +256)^T over K (K % BK == 0).
+// C(256 x 256) = A[arow0 .. +256) x B[brow0 .. +256)^T over K (K a multiple of the stage K).
 template <bool SPLIT>
 __device__ __forceinline__ void tile_gemm(const Operands& o, int64_t K, int64_t arow0, int64_t brow0,
                                           char* ring, f32x16 (&acc)[BI][BJ]) {
@@ -227,16 +250,16 @@ __device__ __forceinline__ void tile_gemm(const Operands& o, int64_t K, int64_t 
   for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
     for (int bj = 0; bj < BJ; ++bj) acc[bi][bj] = f32x16{};
-  constexpr int per = (SPLIT ? 4 : 2) * (ROWS_PER_WAVE / 32);
-  const int64_t nk = K / BK;
+  constexpr int per = 4 * (ROWS_PER_WAVE / 32);
+  const int64_t nk = K / kstage<SPLIT>();
   const RingAddr ra = ring_addr(ring);
   for (int s = 0; s < NSTAGE - 1; ++s)
-    if (s < nk) issue_stage<SPLIT>(ra, s, o, arow0, brow0, (int64_t)s * BK);
+    if (s < nk) issue_stage<SPLIT>(ra, s, o, arow0, brow0, (int64_t)s * kstage<SPLIT>());
   // stage 0 must have landed; stages 1 and 2 may be in flight
   if (nk >= 3) wait_vm_barrier<2 * per>();
   else if (nk == 2) wait_vm_barrier<per>();
   else wait_vm_barrier<0>();
-  if (NSTAGE - 1 < nk) issue_stage<SPLIT>(ra, NSTAGE - 1, o, arow0, brow0, (int64_t)(NSTAGE - 1) * BK);
+  if (NSTAGE - 1 < nk) issue_stage<SPLIT>(ra, NSTAGE - 1, o, arow0, brow0, (int64_t)(NSTAGE - 1) * kstage<SPLIT>());
   Frag f0, f1;
   load_frag<SPLIT>(f0, ring, wm, wn);
   int64_t kt = 0;
@@ -413,11 +436,16 @@ hipError_t launch_rw_bf3(const sos_plan_s* p, void* g, bool split, hipStream_t s
   bf3::RwArgs a;
   const char* ws = p->ws;
   a.o.a_hi = (const __bf16*)(ws + p->lay.R_hi);
-  a.o.a_lo = (const __bf16*)(ws + p->lay.R_lo);
   a.o.b_hi = (const __bf16*)(ws + p->lay.t_hi);
-  a.o.b_lo = (const __bf16*)(ws + p->lay.t_lo);
+  if (split) {
+    a.o.a_lo = (const __bf16*)(ws + p->lay.R_lo);
+    a.o.b_lo = (const __bf16*)(ws + p->lay.t_lo);
+  } else {  // second K block of each stage: the next block of the same panel
+    a.o.a_lo = a.o.a_hi + bf3::TM * bf3::BK;
+    a.o.b_lo = a.o.b_hi + bf3::TM * bf3::BK;
+  }
   a.o.pstride = panel_stride(p->Np2 / kBlkK, 2);
-  a.K = p->Np2;
+  a.K = p->Np2;  // a multiple of 64: whole stages in both modes
   a.TI = (int)(p->Np / bf3::TM);
   a.TL = (int)(p->Kp2 / bf3::TM);
   a.N = (int)p->N;
