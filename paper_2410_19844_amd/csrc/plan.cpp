@@ -201,7 +201,11 @@ int plan_create(int n, int d, int rank, int prec, sos_plan_s** out) {
     for (int64_t i = 0; i < N; ++i)
       for (int64_t j = i; j < N; ++j)
         p->pair_idx[fill[rank_of(i, j)]++] = (int32_t)((uint32_t)(i * N + j) | (i < j ? 0x80000000u : 0u));
-    L.bG = take((size_t)N * N * 8);
+    L.bG = take((size_t)batch_slices(rank) * N * N * 8);
+    L.bR = take((size_t)N * N * 4);
+    L.bg = take((size_t)batch_slices((int)N) * N * rank * 4);
+    L.bpart = take((size_t)((M + 255) / 256) * 8);
+    L.bcount = take(4);
     L.pair_off = take(p->pair_off.size() * 4);
     L.pair_idx = take(p->pair_idx.size() * 4);
   }

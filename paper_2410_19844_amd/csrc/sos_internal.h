@@ -38,6 +38,11 @@ constexpr int kPadK = 64;        // operand K extents padded to this multiple (z
 constexpr int kBlkRows = 256;
 constexpr int kBlkK = 16;
 constexpr int kPanelPadBytes = 4096;
+
+// Grouped serving kernels: the contraction length a block covers, and the
+// number of such slices (each with its own partial result) for length len.
+constexpr int kBatchSlice = 256;
+__host__ __device__ inline int batch_slices(int len) { return (len + kBatchSlice - 1) / kBatchSlice; }
 __host__ __device__ inline int64_t panel_stride(int64_t nkb, int elem_bytes) {
   return nkb * kBlkRows * kBlkK + kPanelPadBytes / elem_bytes;
 }
@@ -57,7 +62,11 @@ struct Layout {
   size_t x_f32 = 0;              // FP32 W, panel-blocked (exact forward), rows = Np, K extent Kp
   size_t g = 0;                  // gradient scratch, N x k in W's type
   // grouped (serving) path, FP32 plans with N <= SOS_BATCH_MAX_N only
-  size_t bG = 0;                 // FP64 Gram, N x N row-major (upper triangle used)
+  size_t bG = 0;                 // FP64 partial Gram per K slice: kBatchSlices(k) x N x N (upper triangle used)
+  size_t bR = 0;                 // FP32 R, N x N row-major (both triangles)
+  size_t bg = 0;                 // FP32 partial gradient per j slice: kBatchSlices(N) x N x k
+  size_t bpart = 0;              // FP64 loss partials, one per coefficient block of 256
+  size_t bcount = 0;             // u32 arrival counter of those blocks (zero between calls)
   size_t pair_off = 0;           // M + 1 int32: pairs of coefficient m are pair_idx[off[m] .. off[m+1])
   size_t pair_idx = 0;           // N (N + 1) / 2 int32: i * N + j (i <= j), bit 31 set when i < j
   size_t bytes = 0;

@@ -101,7 +101,7 @@ def test_step_batch_gradient_matches_oracle():
 
 def test_step_batch_matches_single_exact_steps():
     """Three grouped steps = three sos_step calls with the exact forward (FP64
-    sums of FP32 products in both); the backward differs in FP32 rounding only."""
+    sums of FP32 products in both); the backwards differ in FP32 rounding only."""
     shapes = [(3, 2, 20), (4, 3, 70), (5, 2, 42), (8, 4, 990)]
     adam = S.Adam(lr=1e-2)
     plans, Ws, W64s, ps, _ = make_mix(shapes, seed0=80)
@@ -118,8 +118,11 @@ def test_step_batch_matches_single_exact_steps():
         for q in range(len(shapes)):
             want = refs[q][1][t - 1]
             assert abs(losses[q].item() - want) <= (1e-12 if t == 1 else 1e-5) * want, (q, t)
+    # both backwards are FP32 with different summation orders; Adam's g / (|g| + eps)
+    # magnifies the difference where |g| is near eps, so W is compared in norm
     for q in range(len(shapes)):
-        assert torch.allclose(Ws[q], refs[q][0], rtol=1e-5, atol=1e-6), q
+        d = float(torch.linalg.vector_norm((Ws[q] - refs[q][0]).double()))
+        assert d <= 1e-4 * float(torch.linalg.vector_norm(refs[q][0].double())), (q, d)
 
 
 def test_batch_errors():
