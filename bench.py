@@ -257,14 +257,15 @@ def main():
     loss = torch.empty(1, dtype=torch.float64, device="cuda")
     st = pl.new_state()
     for t in range(1, a.warmup + 1):
-        pl.step(W, st, t, p, adam, loss=loss, flags=flags)
+        pl.step(W, st, t, p, adam, loss=loss, flags=flags | (S.FLAG_COPIES_VALID if t > 1 else 0))
     torch.cuda.synchronize()
     pl.timing(True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record(stream)
+    # W changes only through these steps: each may reuse the operand copies the previous one left
     for t in range(a.warmup + 1, a.warmup + a.steps + 1):
-        pl.step(W, st, t, p, adam, loss=loss, flags=flags)
+        pl.step(W, st, t, p, adam, loss=loss, flags=flags | (S.FLAG_COPIES_VALID if t > 1 else 0))
     ev1.record(stream)
     torch.cuda.synchronize()
     ms_total = ev0.elapsed_time(ev1)

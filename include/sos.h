@@ -80,9 +80,13 @@ enum sos_flags {
    * Gram tiles use FP64 MFMA.  Used to reach residuals below the FP32 or
    * split-bf16 floor; ignored for SOS_FP64 (already exact).               */
   SOS_FLAG_EXACT_FORWARD = 1,
-  /* sos_step only: the workspace's operand copies of W (bf16 hi/lo, or
-   * transposed copies) were written by the previous sos_step of this plan
-   * on this same W, so the split pass is skipped.                         */
+  /* sos_step only, a promise by the caller: W has not been modified since
+   * the previous sos_step on this plan returned.  A SOS_BF16X3 step with
+   * SOS_FLAG_SINGLE_BACKWARD (fast or exact forward) updates W inside the
+   * backward GEMM's epilogue and writes there the operand copies the next
+   * step reads; with this flag the next step on the same W pointer and
+   * forward mode skips rebuilding them.  Ignored whenever the library holds
+   * no such copies (other modes, another call on the plan in between).    */
   SOS_FLAG_COPIES_VALID = 2,
   /* SOS_BF16X3 only: the backward takes one bf16 product per element pair
    * (hi * hi) instead of three.  The gradient 4 R W then carries a relative

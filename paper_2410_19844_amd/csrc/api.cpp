@@ -88,17 +88,23 @@ static int fwd_mode(const sos_plan_s* p, int flags) {
   return kFwdFast;
 }
 
-// grad: a backward follows (so the transposed operand copies are needed)
+// grad: a backward follows (so the transposed operand copies are needed).
+// reuse: the operand copies already in the workspace were made from this W
+// for this mode (by the epilogue of the previous fused step): no preparation.
 static int run_forward(sos_plan_s* p, const void* W, const double* d_p, int flags, double* d_loss,
-                       bool grad, hipStream_t s) {
+                       bool grad, hipStream_t s, bool reuse = false) {
   const int mode = fwd_mode(p, flags);
-  PrepNeeds need;
-  need.a = p->prec == SOS_FP64 || mode == kFwdFast;
-  need.a_f32 = mode == kFwdF32;
-  need.x_f32 = mode == kFwdExact;
-  need.t = grad;
-  need.t_lo = grad && (flags & SOS_FLAG_SINGLE_BACKWARD) == 0;
-  TIMED(SOS_K_PREP, launch_prep(p, W, need, s), "prep");
+  if (!reuse) {
+    PrepNeeds need;
+    need.a = p->prec == SOS_FP64 || mode == kFwdFast;
+    need.a_f32 = mode == kFwdF32;
+    need.x_f32 = mode == kFwdExact;
+    need.t = grad;
+    need.t_lo = grad && (flags & SOS_FLAG_SINGLE_BACKWARD) == 0;
+    TIMED(SOS_K_PREP, launch_prep(p, W, need, s), "prep");
+    p->copies_valid = false;
+    p->t_cur = 0;  // the preparation writes the transposed copy into t_hi
+  }
   TIMED(SOS_K_INIT, launch_init_r(p, d_p, s), "init_r");
   TIMED(SOS_K_GRAM, launch_gram(p, mode, s), "gram");
   float* r32 = (grad && p->prec != SOS_FP64) ? (float*)(p->ws + p->lay.r32) : nullptr;
@@ -112,14 +118,33 @@ static int run_backward(sos_plan_s* p, void* g, bool split, hipStream_t s) {
   return SOS_OK;
 }
 
+// One Adam step.  Split plans with the single-product backward and the fast
+// or exact forward run the fused backward (Adam and the next step's operand
+// copies in the GEMM epilogue); with SOS_FLAG_COPIES_VALID the next such
+// step on the same W and mode then skips the preparation.
 static int run_step(sos_plan_s* p, void* W, void* state, int64_t t, const double* d_p,
                     const sos_adam_t& h, double* d_loss, int flags, hipStream_t s) {
-  int rc = run_forward(p, W, d_p, flags, d_loss, true, s);
-  if (rc) return rc;
-  void* g = p->ws + p->lay.g;
-  rc = run_backward(p, g, (flags & SOS_FLAG_SINGLE_BACKWARD) == 0, s);
+  const int mode = fwd_mode(p, flags);
+  const bool single = (flags & SOS_FLAG_SINGLE_BACKWARD) != 0;
+  const bool fuse = p->prec == SOS_BF16X3 && single && (mode == kFwdFast || mode == kFwdExact);
+  const bool reuse = fuse && (flags & SOS_FLAG_COPIES_VALID) && p->copies_valid && p->copies_W == W &&
+                     p->copies_mode == mode;
+  int rc = run_forward(p, W, d_p, flags, d_loss, true, s, reuse);
   if (rc) return rc;
   char* st = (char*)state;
+  if (fuse) {
+    TIMED(SOS_K_GATHER, launch_gather(p, false, s), "gather");
+    TIMED(SOS_K_RW, launch_rw_adam_bf3(p, W, st, st + slot_bytes(p), t, h, mode == kFwdExact, s),
+          "backward + Adam");
+    p->t_cur ^= 1;
+    p->copies_valid = true;
+    p->copies_W = W;
+    p->copies_mode = mode;
+    return SOS_OK;
+  }
+  void* g = p->ws + p->lay.g;
+  rc = run_backward(p, g, !single, s);
+  if (rc) return rc;
   TIMED(SOS_K_ADAM, launch_adam(p, W, st, st + slot_bytes(p), g, t, h, s), "adam");
   return SOS_OK;
 }
@@ -333,14 +358,17 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
     if (o->lr_exact > 0) h.lr = o->lr_exact;
     best_rel = ref_rel = inf;  // values of the more accurate forward from here on
   };
+  bool w_moved = true;  // W changed outside a step (start, rollback): operand copies must be rebuilt
   while (t < o->max_steps && !done) {
     ++t;
     const bool check = (t % o->check_every == 0) || t == o->max_steps;
     if (check) SOS_HIP(hipMemcpyAsync(cand, d_W, wbytes, hipMemcpyDeviceToDevice, s), "sos_solve: snapshot");
     const int flags = (phase == 2 ? SOS_FLAG_EXACT_FORWARD : phase == 1 ? SOS_FLAG_FP32_FORWARD : 0) |
-                      (o->single_backward ? SOS_FLAG_SINGLE_BACKWARD : 0);
+                      (o->single_backward ? SOS_FLAG_SINGLE_BACKWARD : 0) |
+                      (w_moved ? 0 : SOS_FLAG_COPIES_VALID);
     int rc = run_step(p, d_W, st, t, d_p, h, sc + 0, flags, s);
     if (rc) return rc;
+    w_moved = false;
     if (phase == 2) ++exact_steps;
     if (!check) continue;
     SOS_HIP(hipMemcpyAsync(&last_loss, sc + 0, 8, hipMemcpyDeviceToHost, s), "sos_solve: loss");
@@ -361,6 +389,7 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
     if (have_best && (!std::isfinite(rel) || (o->rollback_ratio > 0 && rel > o->rollback_ratio * best_rel))) {
       // diverging: back to the best iterate with half the step size
       SOS_HIP(hipMemcpyAsync(d_W, best, wbytes, hipMemcpyDeviceToDevice, s), "sos_solve: rollback");
+      w_moved = true;
       h.lr *= 0.5;
       stall = 0;
       ref_rel = best_rel;

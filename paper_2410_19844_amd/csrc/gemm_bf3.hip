@@ -409,6 +409,131 @@ __global__ __launch_bounds__(NT) void k_rw_bf3(RwArgs a) {
   }
 }
 
+// The single-product backward with Adam and the next step's operand copies
+// in its epilogue.  W (FP32 master) is not an operand of this GEMM (it reads
+// the bf16 copies of R and W^T), and every (i, l) belongs to exactly one
+// tile, so each tile can update its own W, m and v in place.  From the
+// updated W it writes what the next step's forward reads (the split copy, or
+// the FP32 blocked copy for the exact forward) and the transposed copy for
+// the next backward into the second transposed buffer (the one this GEMM does
+// not read).  Padding rows and columns get zeros, as the preparation kernel
+// writes them.
+struct RwAdamArgs {
+  RwArgs rw;
+  float* __restrict__ W;
+  float* __restrict__ m;
+  float* __restrict__ v;
+  float lr, b1, b2, eps, bc1, bc2;
+  __bf16* a_hi;       // next forward, split copy (fast forward), or nullptr
+  __bf16* a_lo;
+  float* x_f32;       // next forward, FP32 blocked copy (exact forward), or nullptr
+  __bf16* t_next;     // next backward: transposed copy
+  int64_t aps, xps, tps;         // panel strides of those layouts
+  int64_t Np, Kp, Np2, Kp2;
+};
+
+__global__ __launch_bounds__(NT) void k_rw_adam_bf3(RwAdamArgs a) {
+  SOS_BF3_BUFFERS;
+  const RwArgs& r = a.rw;
+  const int nb = r.TI * r.TL;
+  const int v = xcd_order(blockIdx.x, nb);
+  constexpr int GROUP = 8;
+  const int per_group = GROUP * r.TL;
+  const int gidx = v / per_group, first = gidx * GROUP;
+  const int rows = min(GROUP, r.TI - first);
+  const int in = v % per_group;
+  const int I = first + in % rows, L = in / rows;
+  f32x16 acc[BI][BJ];
+  tile_gemm<false>(r.o, r.K, (int64_t)I * TM, (int64_t)L * TM, lds, acc);
+  const int wave = threadIdx.x >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+  constexpr int QROWS = 64;                            // quarter tiles of 64 x 256
+  float* stage = (float*)lds;                          // 64 KB
+  __bf16* tb = (__bf16*)(lds + QROWS * TM * 4);        // 32 KB: bf16 of the updated W
+  static_assert(QROWS * TM * 4 + QROWS * TM * 2 <= NSTAGE * STAGE, "epilogue buffers exceed the ring");
+#pragma unroll
+  for (int qq = 0; qq < TM / QROWS; ++qq) {
+    __syncthreads();
+    if (wm == qq / 2) {
+#pragma unroll
+      for (int bi = 0; bi < BI; ++bi) {
+        if (bi / 2 != (qq & 1)) continue;
+#pragma unroll
+        for (int bj = 0; bj < BJ; ++bj)
+#pragma unroll
+          for (int q = 0; q < 16; ++q)
+            stage[(acc_row(wm, bi, q) - qq * QROWS) * TM + acc_col(wn, bj)] = acc[bi][bj][q];
+      }
+    }
+    __syncthreads();
+    // Adam on the quarter (row-major, coalesced in W, m, v), the forward copy,
+    // and the bf16 of the new W into tb for the transposed copy.  Each thread
+    // takes its elements 8 at a time, and the loads of the next 8 are issued
+    // before the current 8 are computed, so HBM latency overlaps the work.
+    constexpr int PER = QROWS * TM / NT;
+    float wv[2][8], mv[2][8], vv[2][8];
+    auto fetch = [&](int b8, int buf) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = threadIdx.x + NT * (8 * b8 + u);
+        const int64_t i = (int64_t)I * TM + qq * QROWS + e / TM, l = (int64_t)L * TM + e % TM;
+        wv[buf][u] = mv[buf][u] = vv[buf][u] = 0.f;
+        if (i < r.N && l < r.k) {
+          const int64_t o = i * r.k + l;
+          wv[buf][u] = a.W[o];
+          mv[buf][u] = a.m[o];
+          vv[buf][u] = a.v[o];
+        }
+      }
+    };
+    fetch(0, 0);
+#pragma unroll
+    for (int b8 = 0; b8 < PER / 8; ++b8) {
+      const int buf = b8 & 1;
+      if (b8 + 1 < PER / 8) fetch(b8 + 1, buf ^ 1);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = threadIdx.x + NT * (8 * b8 + u);
+        const int64_t i = (int64_t)I * TM + qq * QROWS + e / TM, l = (int64_t)L * TM + e % TM;
+        float w = 0.f;
+        if (i < r.N && l < r.k) {
+          const int64_t o = i * r.k + l;
+          const float ge = 4.0f * stage[e];
+          const float me = a.b1 * mv[buf][u] + (1.f - a.b1) * ge;
+          const float ve = a.b2 * vv[buf][u] + (1.f - a.b2) * ge * ge;
+          a.m[o] = me;
+          a.v[o] = ve;
+          w = wv[buf][u] - a.lr * (me / a.bc1) / (sqrtf(ve / a.bc2) + a.eps);
+          a.W[o] = w;
+        }
+        if (i < a.Np && l < a.Kp) {
+          if (a.x_f32) {
+            a.x_f32[blk_off(i, l, a.xps)] = w;
+          } else {
+            const __bf16 h = (__bf16)w;
+            const int64_t ob = blk_off(i, l, a.aps);
+            a.a_hi[ob] = h;
+            a.a_lo[ob] = (__bf16)(w - (float)h);
+          }
+        }
+        tb[e] = (__bf16)w;
+      }
+    }
+    __syncthreads();
+    // transposed copy: rows l, K = i; 8 consecutive i of one row per thread (16-byte stores)
+    for (int f = threadIdx.x * 8; f < QROWS * TM; f += NT * 8) {
+      const int kb = f / (TM * kBlkK), lrow = (f % (TM * kBlkK)) / kBlkK, ii0 = f % kBlkK;
+      const int64_t l = (int64_t)L * TM + lrow, i0 = (int64_t)I * TM + qq * QROWS + kb * kBlkK + ii0;
+      if (l < a.Kp2 && i0 < a.Np2) {
+        bf16x8 hv;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) hv[u] = tb[(kb * kBlkK + ii0 + u) * TM + lrow];
+        *(bf16x8*)(a.t_next + blk_off(l, i0, a.tps)) = hv;
+      }
+    }
+  }
+}
+
 }  // namespace bf3
 
 // Host side -----------------------------------------------------------------
@@ -436,7 +561,7 @@ hipError_t launch_rw_bf3(const sos_plan_s* p, void* g, bool split, hipStream_t s
   bf3::RwArgs a;
   const char* ws = p->ws;
   a.o.a_hi = (const __bf16*)(ws + p->lay.R_hi);
-  a.o.b_hi = (const __bf16*)(ws + p->lay.t_hi);
+  a.o.b_hi = (const __bf16*)(ws + (p->t_cur ? p->lay.t_lo : p->lay.t_hi));
   if (split) {
     a.o.a_lo = (const __bf16*)(ws + p->lay.R_lo);
     a.o.b_lo = (const __bf16*)(ws + p->lay.t_lo);
@@ -453,6 +578,52 @@ hipError_t launch_rw_bf3(const sos_plan_s* p, void* g, bool split, hipStream_t s
   a.g = (float*)g;
   if (split) bf3::k_rw_bf3<true><<<a.TI * a.TL, bf3::NT, 0, s>>>(a);
   else bf3::k_rw_bf3<false><<<a.TI * a.TL, bf3::NT, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace sos
+
+namespace sos {
+
+hipError_t launch_rw_adam_bf3(const sos_plan_s* p, void* W, void* m, void* v, int64_t t, const sos_adam_t& h,
+                              bool exact_next, hipStream_t s) {
+  bf3::RwAdamArgs a;
+  bf3::RwArgs& r = a.rw;
+  char* ws = p->ws;
+  const size_t t_read = p->t_cur ? p->lay.t_lo : p->lay.t_hi;
+  const size_t t_write = p->t_cur ? p->lay.t_hi : p->lay.t_lo;
+  r.o.a_hi = (const __bf16*)(ws + p->lay.R_hi);
+  r.o.b_hi = (const __bf16*)(ws + t_read);
+  r.o.a_lo = r.o.a_hi + bf3::TM * bf3::BK;
+  r.o.b_lo = r.o.b_hi + bf3::TM * bf3::BK;
+  r.o.pstride = panel_stride(p->Np2 / kBlkK, 2);
+  r.K = p->Np2;
+  r.TI = (int)(p->Np / bf3::TM);
+  r.TL = (int)(p->Kp2 / bf3::TM);
+  r.N = (int)p->N;
+  r.k = p->k;
+  r.g = nullptr;
+  a.W = (float*)W;
+  a.m = (float*)m;
+  a.v = (float*)v;
+  a.lr = (float)h.lr;
+  a.b1 = (float)h.beta1;
+  a.b2 = (float)h.beta2;
+  a.eps = (float)h.eps;
+  a.bc1 = (float)(1.0 - pow(h.beta1, (double)t));
+  a.bc2 = (float)(1.0 - pow(h.beta2, (double)t));
+  a.a_hi = exact_next ? nullptr : (__bf16*)(ws + p->lay.a_hi);
+  a.a_lo = exact_next ? nullptr : (__bf16*)(ws + p->lay.a_lo);
+  a.x_f32 = exact_next ? (float*)(ws + p->lay.x_f32) : nullptr;
+  a.t_next = (__bf16*)(ws + t_write);
+  a.aps = panel_stride(p->Kp / kBlkK, 2);
+  a.xps = panel_stride(p->Kp / kBlkK, 4);
+  a.tps = panel_stride(p->Np2 / kBlkK, 2);
+  a.Np = p->Np;
+  a.Kp = p->Kp;
+  a.Np2 = p->Np2;
+  a.Kp2 = p->Kp2;
+  bf3::k_rw_adam_bf3<<<r.TI * r.TL, bf3::NT, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -90,6 +90,13 @@ struct sos_plan_s {
   int ntiles256 = 0;               // upper-triangle tiles of 256 x 256
   std::vector<int32_t> tile_list;  // 2 * ntiles256
   bool batchable = false;          // grouped (serving) calls supported
+  // operand copies left by the last fused step (single-product backward with
+  // Adam in its epilogue): valid for W pointer copies_W and forward mode
+  // copies_mode until another call rebuilds the copies
+  bool copies_valid = false;
+  const void* copies_W = nullptr;
+  int copies_mode = 0;
+  int t_cur = 0;                   // transposed copy for the next backward: 0 = t_hi, 1 = t_lo
   std::vector<int32_t> pair_off, pair_idx;
   size_t state_bytes = 0;
   char* ws = nullptr;
@@ -140,6 +147,9 @@ hipError_t launch_gram_x64(const sos_plan_s* p, hipStream_t s);
 hipError_t launch_rw_bf3(const sos_plan_s* p, void* g, bool split, hipStream_t s);
 hipError_t launch_adam(const sos_plan_s* p, void* W, void* m, void* v, const void* g, int64_t t,
                        const sos_adam_t& h, hipStream_t s);
+// single-product backward with Adam and the next step's copies in the epilogue
+hipError_t launch_rw_adam_bf3(const sos_plan_s* p, void* W, void* m, void* v, int64_t t, const sos_adam_t& h,
+                              bool exact_next, hipStream_t s);
 // grouped serving kernels (batch.hip); at most batch_capacity() problems per call
 int batch_capacity();
 hipError_t launch_step_group(sos_plan_s* const* plans, void* const* W, void* const* state, const int64_t* t,

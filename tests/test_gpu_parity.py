@@ -325,3 +325,37 @@ def test_sosloss_autograd_matches_fd_and_oracle():
         assert abs(g[i, j] - g_o[i, j]) <= tb * gabs[i, j] + gabs_fwd[i, j]
 
 
+
+
+# ---------------------------------------------------------------------------
+# Fused backward + Adam: the copies its epilogue leaves for the next step
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("exact", [False, True])
+@pytest.mark.parametrize("n,d,k", [(6, 4, 420), (10, 5, 300)])
+def test_fused_step_leaves_the_copies_the_next_step_needs(n, d, k, exact):
+    """A split plan's single-product step updates W in the backward GEMM's
+    epilogue and writes there the operand copies of the new W; the next step
+    with SOS_FLAG_COPIES_VALID uses them instead of preparing its own.  That
+    step's loss and gradient must equal those from freshly prepared copies of
+    the same W (sos_loss_grad), and its update must be the Adam formula."""
+    _, Wd, _, pd = make_case(n, d, k, "bf16x3", seed=9)
+    pl = S.Plan(n, d, k, "bf16x3")
+    N = pl.N
+    st = pl.new_state()
+    base = S.FLAG_SINGLE_BACKWARD | (S.FLAG_EXACT_FORWARD if exact else 0)
+    adam = S.Adam(lr=1e-3)
+    for t in (1, 2):
+        pl.step(Wd, st, t, pd, adam, flags=base | S.FLAG_COPIES_VALID)
+    W_before = Wd.clone()
+    adam0 = S.Adam(lr=1e-3, beta1=0.0)                 # first moment = this step's gradient
+    L3 = pl.step(Wd, st, 3, pd, adam0, flags=base | S.FLAG_COPIES_VALID).item()
+    torch.cuda.synchronize()
+    slot = pl.state_bytes // 4
+    g3 = st[: N * k * 4].view(torch.float32).reshape(N, k).clone()
+    v3 = st[slot: slot + N * k * 4].view(torch.float32).reshape(N, k).clone()
+    L_ref, g_ref, _ = pl.loss_grad(W_before, pd, grad=True, exact=exact, single_backward=True)
+    assert abs(L3 - L_ref.item()) <= 1e-12 * L_ref.item(), (L3, L_ref.item())
+    assert torch.equal(g3, g_ref)
+    want = W_before.double() - 1e-3 * g3.double() / (torch.sqrt(v3.double() / (1 - 0.999 ** 3)) + 1e-8)
+    assert bool(((Wd.double() - want).abs() <= 1e-6 * want.abs() + 1e-8).all())
