@@ -6,7 +6,7 @@ M = 2,704,156 coefficients, rank k = N), split-bf16 contractions, FP32
 master W, FP64 residual.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--precision bf16x3|fp32|fp64]
-                  [--workload n12d6|n10d5|n6d4] [--exact] [--no-cpu-baseline]
+                  [--workload n12d6|n10d5|n6d4|q100] [--exact] [--no-cpu-baseline]
                   [--mode step|ttt] [--tol 1e-8] [--max-steps S]
 
 --mode ttt runs sos_solve from the same start to an FP64-verified relative
@@ -293,8 +293,9 @@ def main():
         "dtype": DTYPE[a.precision] if not a.exact else DTYPE[a.precision] + "+fp64-forward",
         "data": "synthetic",
         "config": {"workload": f"{c.name}: n={c.n} d={c.d} N={c.N} M={c.M} rank={c.rank}; "
-                               f"p=coeff(W0 W0^T), W0 {c.N}x{c.w0_rank} N(0,{c.w0_std:.4g}^2); "
-                               f"W N(0,{c.w_std:.4g}^2)",
+                               f"p=coeff(W0 W0^T), W0 {c.N}x{c.w0_rank} "
+                               + (f"U[-{c.w0_std:.4g},{c.w0_std:.4g}]; " if c.w0_uniform else f"N(0,{c.w0_std:.4g}^2); ")
+                               + f"W N(0,{c.w_std:.4g}^2)",
                    "precision": a.precision, "exact_forward": a.exact, "lr": lr,
                    "single_backward": a.single_backward},
         "roofline": {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",

@@ -14,7 +14,11 @@ from .sos import (  # noqa: F401
     monomials,
     monomials_bruteforce,
     MonomialIndex,
+    monomials_sparse,
+    SparseIndex,
+    merge_lists,
     pair_ranks,
+    pair_ranks_sparse,
     coefficients,
     coefficients_abs,
     residual,

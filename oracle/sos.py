@@ -118,13 +118,98 @@ def pair_ranks(n: int, d: int, rows=None) -> np.ndarray:
 
     ``rows`` restricts i to a subset (for large bases).  Uses the fact that the
     base-(2d+1) code of a sum of two exponent vectors whose entries are <= d is
-    the sum of their codes (no digit exceeds 2d, so nothing carries).
+    the sum of their codes (no digit exceeds 2d, so nothing carries).  When
+    those codes would overflow (many variables), the sparse variable-list
+    index gives the same map (``pair_ranks_sparse``).
     """
+    if (2 * d + 1) ** n >= 2 ** 62:
+        return pair_ranks_sparse(n, d, rows)
     basis = monomials(n, d)
     cidx = MonomialIndex(n, 2 * d)
     bcode = cidx.encode(basis)
     ri = bcode if rows is None else bcode[np.asarray(rows)]
     out = cidx.lookup_codes(ri[:, None] + bcode[None, :])
+    assert (out >= 0).all()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# The same order for many variables and low degree (sparse representation)
+# ---------------------------------------------------------------------------
+#
+# With n ~ 100 and degree <= 4 (the paper's largest quartic workload, Section
+# 1.2 and the Section 3.1 table), dense exponent vectors are wasteful (99
+# entries, at most 4 nonzero) and their base-(D+1) codes overflow.  A monomial
+# of degree t is also the multiset of its variables, written as the
+# ascending list v_1 <= ... <= v_t.  Within one degree, the lexicographically
+# larger exponent vector is exactly the lexicographically smaller list: at
+# the first position where two lists differ, the one with the smaller
+# variable has one more factor of that variable and the same count of every
+# earlier one.  So each degree block of the basis order is the lexicographic
+# enumeration of ascending lists, which is the order in which
+# itertools.combinations_with_replacement produces them.
+
+def monomials_sparse(n: int, D: int) -> np.ndarray:
+    """Monomials of degree <= D in n variables, in the basis order, as
+    ascending variable lists padded with -1: shape (C(n+D, D), D)."""
+    rows = []
+    for t in range(D, -1, -1):
+        for c in itertools.combinations_with_replacement(range(n), t):
+            rows.append(c + (-1,) * (D - t))
+    return np.array(rows, dtype=np.int64).reshape(len(rows), D)
+
+
+class SparseIndex:
+    """Dictionary variable-list -> position in the degree-<=D list.
+
+    A padded ascending list (v_1, .., v_t, -1, ..) is encoded as the integer
+    sum_p (v_p + 1) (n + 1)^(D - 1 - p) (absent entries contribute 0), which
+    is injective; lookups sort the codes once and binary-search them.
+    """
+
+    def __init__(self, n: int, D: int):
+        self.n, self.D = n, D
+        if (n + 1) ** D >= 2 ** 62:
+            raise ValueError("variable-list codes would overflow int64")
+        self.lists = monomials_sparse(n, D)
+        self.weights = np.array([(n + 1) ** (D - 1 - q) for q in range(D)], dtype=np.int64)
+        self.codes = self.encode(self.lists)
+        self._sorter = np.argsort(self.codes, kind="stable")
+        self._sorted = self.codes[self._sorter]
+
+    def __len__(self) -> int:
+        return self.lists.shape[0]
+
+    def encode(self, lists: np.ndarray) -> np.ndarray:
+        return (np.asarray(lists, dtype=np.int64) + 1) @ self.weights
+
+    def lookup(self, lists: np.ndarray) -> np.ndarray:
+        """Positions of padded ascending lists; -1 where absent."""
+        codes = self.encode(lists)
+        pos = np.clip(np.searchsorted(self._sorted, codes), 0, len(self._sorted) - 1)
+        return np.where(self._sorted[pos] == codes, self._sorter[pos], -1)
+
+
+def merge_lists(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Variable list of the product of two monomials given as padded lists
+    (broadcasting over leading axes): the sorted union with multiplicity,
+    padding moved to the end."""
+    a, b = np.broadcast_arrays(np.asarray(a), np.asarray(b))
+    both = np.concatenate([a, b], axis=-1)
+    big = np.iinfo(np.int64).max
+    both = np.sort(np.where(both < 0, big, both), axis=-1)
+    return np.where(both == big, -1, both)
+
+
+def pair_ranks_sparse(n: int, d: int, rows=None, basis=None, cidx=None) -> np.ndarray:
+    """``pair_ranks`` through the sparse representation: entry (i, j) is the
+    position of the merged list of basis monomials i and j among the
+    degree-<=2d lists.  ``basis`` and ``cidx`` (from ``monomials_sparse`` and
+    ``SparseIndex``) may be passed in when calling block by block."""
+    basis = monomials_sparse(n, d) if basis is None else basis
+    cidx = SparseIndex(n, 2 * d) if cidx is None else cidx
+    bi = basis if rows is None else basis[np.asarray(rows)]
+    out = cidx.lookup(merge_lists(bi[:, None, :], basis[None, :, :]))
     assert (out >= 0).all()
     return out
 

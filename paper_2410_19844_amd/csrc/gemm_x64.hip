@@ -129,24 +129,6 @@ __device__ __forceinline__ void mma_stage(const Frag& f, f64x4 (&acc)[4][4]) {
   }
 }
 
-struct RankTab {
-  const uint32_t* __restrict__ codes;
-  const int32_t* __restrict__ tables;
-  int nwords, ngroups;
-};
-
-__device__ __forceinline__ int rank_sum(const RankTab& c, int i, int j) {
-  int r = 0;
-#pragma unroll
-  for (int w = 0; w < kMaxWords; ++w) {
-    if (w < c.nwords) {
-      const uint32_t s = c.codes[(size_t)i * c.nwords + w] + c.codes[(size_t)j * c.nwords + w];
-      r += c.tables[(2 * w) * kGroupEntries + (s & 0xFFFu)];
-      if (2 * w + 1 < c.ngroups) r += c.tables[(2 * w + 1) * kGroupEntries + ((s >> 16) & 0xFFFu)];
-    }
-  }
-  return r;
-}
 
 struct Args {
   const float* w;     // panel-blocked FP32 W: rows Np, K extent Kp
@@ -200,7 +182,7 @@ __global__ __launch_bounds__(NT) void k_gram_x64(Args g) {
         const int i = (int)arow0 + wm * 64 + bi * 16 + (l >> 4) + 4 * q;
         if (i < g.N && j < g.N && i <= j) {
           const double wgt = (i == j) ? 1.0 : 2.0;
-          unsafeAtomicAdd(g.r + rank_sum(g.rk, i, j), wgt * acc[bi][bj][q]);
+          unsafeAtomicAdd(g.r + pair_rank(g.rk, i, j), wgt * acc[bi][bj][q]);
         }
       }
     }
@@ -217,10 +199,7 @@ hipError_t launch_gram_x64(const sos_plan_s* p, hipStream_t s) {
   g.tiles = (const int2*)(ws + p->lay.tiles);
   g.ntiles = p->ntiles256;
   g.N = (int)p->N;
-  g.rk.codes = (const uint32_t*)(ws + p->lay.codes);
-  g.rk.tables = (const int32_t*)(ws + p->lay.tables);
-  g.rk.nwords = p->nwords;
-  g.rk.ngroups = p->ngroups;
+  g.rk = rank_tab(p);
   g.r = (double*)(ws + p->lay.r);
   x64::k_gram_x64<<<2 * g.ntiles, x64::NT, 0, s>>>(g);
   return hipGetLastError();

@@ -26,34 +26,12 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// ---------------------------------------------------------------------------
-// Ranking: rank(alpha_i + alpha_j) from the additive codes (see plan.cpp).
-// ---------------------------------------------------------------------------
-struct RankCtx {
-  const uint32_t* __restrict__ codes;  // N x nwords
-  const int32_t* __restrict__ tables;  // ngroups x 4096
-  int nwords, ngroups;
-};
-
-__device__ __forceinline__ int rank_of_sum(const RankCtx& c, int i, int j) {
-  int r = 0;
-#pragma unroll
-  for (int w = 0; w < kMaxWords; ++w) {
-    if (w < c.nwords) {
-      const uint32_t s = c.codes[(size_t)i * c.nwords + w] + c.codes[(size_t)j * c.nwords + w];
-      r += c.tables[(2 * w) * kGroupEntries + (s & 0xFFFu)];
-      if (2 * w + 1 < c.ngroups) r += c.tables[(2 * w + 1) * kGroupEntries + ((s >> 16) & 0xFFFu)];
-    }
-  }
-  return r;
-}
-
-__global__ void k_pair_ranks(RankCtx c, int N, int32_t* __restrict__ out) {
+__global__ void k_pair_ranks(RankTab c, int N, int32_t* __restrict__ out) {
   const int64_t total = (int64_t)N * N;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(e / N), j = (int)(e % N);
-    out[e] = rank_of_sum(c, i, j);
+    out[e] = pair_rank(c, i, j);
   }
 }
 
@@ -407,7 +385,7 @@ struct GramArgs {
   const void* A[2];   // operand arrays (hi[, lo]); rows Np, ld Kp
   int64_t ld, K;      // ld = K = Kp
   int N, T;           // T = Np / BM tiles per side
-  RankCtx rk;
+  RankTab rk;
   double* r;
 };
 
@@ -438,7 +416,7 @@ __global__ __launch_bounds__(kThreads) void k_gram(GramArgs g) {
     const int i = I * BM + wm * 64 + row, j = J * BM + wn * 64 + col;
     if (i < g.N && j < g.N && i <= j) {
       const double w = (i == j) ? 1.0 : 2.0;
-      unsafeAtomicAdd(g.r + rank_of_sum(g.rk, i, j), w * (double)acc[e]);
+      unsafeAtomicAdd(g.r + pair_rank(g.rk, i, j), w * (double)acc[e]);
     }
   }
 }
@@ -447,7 +425,7 @@ __global__ __launch_bounds__(kThreads) void k_gram(GramArgs g) {
 // Backward: R from r, then g = 4 R W.
 // ---------------------------------------------------------------------------
 template <int MODE>  // 0 FP64, 1 FP32, 2 bf16 hi/lo, 3 bf16 hi only
-__global__ __launch_bounds__(256) void k_gather(RankCtx rk, const double* __restrict__ r, int N,
+__global__ __launch_bounds__(256) void k_gather(RankTab rk, const double* __restrict__ r, int N,
                                                 int64_t Np, int64_t ld, void* R_hi, void* R_lo) {
   const int64_t total = Np * ld;
   const int64_t nkb = ld / kBlkK;
@@ -466,7 +444,7 @@ __global__ __launch_bounds__(256) void k_gather(RankCtx rk, const double* __rest
       j = (int)(e % ld);
     }
     double v = 0.0;
-    if (i < N && j < N) v = r[rank_of_sum(rk, i, j)];
+    if (i < N && j < N) v = r[pair_rank(rk, i, j)];
     if (MODE == 0) ((double*)R_hi)[o] = v;
     else if (MODE == 1) ((float*)R_hi)[o] = (float)v;
     else {
@@ -484,7 +462,7 @@ __global__ __launch_bounds__(256) void k_gather(RankCtx rk, const double* __rest
 // of these modes, so reading the copy gives the same bits as reading r.
 // Mode 1 = FP32 row-major, 2 = bf16 hi and lo (blocked), 3 = bf16 hi only.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_gather8(RankCtx rk, const float* __restrict__ r32, int N, int64_t Np,
+__global__ __launch_bounds__(256) void k_gather8(RankTab rk, const float* __restrict__ r32, int N, int64_t Np,
                                                  int64_t ld, void* R_hi, void* R_lo) {
   const int64_t total8 = Np * ld / 8;
   const int64_t nkb = ld / kBlkK;
@@ -506,25 +484,11 @@ __global__ __launch_bounds__(256) void k_gather8(RankCtx rk, const float* __rest
     }
     float v[8];
     if (i < N) {
-      uint32_t ci[kMaxWords];
-#pragma unroll
-      for (int w = 0; w < kMaxWords; ++w) ci[w] = (w < rk.nwords) ? rk.codes[(size_t)i * rk.nwords + w] : 0u;
+      const RankRow ri = rank_row(rk, i);
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int j = j0 + q;
-        v[q] = 0.f;
-        if (j < N) {
-          int rr = 0;
-#pragma unroll
-          for (int w = 0; w < kMaxWords; ++w) {
-            if (w < rk.nwords) {
-              const uint32_t sw = ci[w] + rk.codes[(size_t)j * rk.nwords + w];
-              rr += rk.tables[(2 * w) * kGroupEntries + (sw & 0xFFFu)];
-              if (2 * w + 1 < rk.ngroups) rr += rk.tables[(2 * w + 1) * kGroupEntries + ((sw >> 16) & 0xFFFu)];
-            }
-          }
-          v[q] = r32[rr];
-        }
+        v[q] = (j < N) ? r32[pair_rank_row(rk, ri, j)] : 0.f;
       }
     } else {
 #pragma unroll
@@ -608,17 +572,8 @@ static inline int grid_for(int64_t n, int threads = 256, int cap = 65536) {
   return (int)b;
 }
 
-static RankCtx rank_ctx(const sos_plan_s* p) {
-  RankCtx c;
-  c.codes = (const uint32_t*)(p->ws + p->lay.codes);
-  c.tables = (const int32_t*)(p->ws + p->lay.tables);
-  c.nwords = p->nwords;
-  c.ngroups = p->ngroups;
-  return c;
-}
-
 hipError_t launch_pair_ranks(const sos_plan_s* p, int32_t* out, hipStream_t s) {
-  k_pair_ranks<<<grid_for(p->N * p->N), 256, 0, s>>>(rank_ctx(p), (int)p->N, out);
+  k_pair_ranks<<<grid_for(p->N * p->N), 256, 0, s>>>(rank_tab(p), (int)p->N, out);
   return hipGetLastError();
 }
 
@@ -661,7 +616,7 @@ static hipError_t gram_launch(const sos_plan_s* p, const void* a0, const void* a
   g.ld = p->Kp; g.K = p->Kp;
   g.N = (int)p->N;
   g.T = (int)(p->Np / BM);
-  g.rk = rank_ctx(p);
+  g.rk = rank_tab(p);
   g.r = (double*)(p->ws + p->lay.r);
   const int tiles = g.T * (g.T + 1) / 2;
   const size_t sm = 2 * sizeof(Stage<Md>);
@@ -707,7 +662,7 @@ static hipError_t rw_launch(const sos_plan_s* p, void* g, hipStream_t s) {
 
 hipError_t launch_gather(const sos_plan_s* p, bool split, hipStream_t s) {
   char* ws = p->ws;
-  const RankCtx rk = rank_ctx(p);
+  const RankTab rk = rank_tab(p);
   const int64_t total = p->Np * p->Np2;
   void* Rh = ws + p->lay.R_hi;
   void* Rl = p->prec == SOS_BF16X3 ? ws + p->lay.R_lo : nullptr;

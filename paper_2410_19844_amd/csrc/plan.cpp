@@ -16,6 +16,7 @@
 // gives C(u_f + n-f-1, n-f).  Every term depends on one field of the code
 // (t or one u_f), which is what makes per-group table lookups possible.
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <new>
 
@@ -75,8 +76,13 @@ int plan_create(int n, int d, int rank, int prec, sos_plan_s** out) {
     return set_error(SOS_EINVAL, "sos_plan: n, d and rank must be >= 1");
   if (prec != SOS_FP64 && prec != SOS_FP32 && prec != SOS_BF16X3)
     return set_error(SOS_EINVAL, "sos_plan: unknown precision");
-  if (2 * d > 15 || n > 16)
-    return set_error(SOS_ERANGE, "sos_plan: needs 2d <= 15 and n <= 16 (4-bit code fields)");
+  // dense codes (4-bit suffix-sum fields) for n <= 16, 2d <= 15; sparse
+  // variable lists (one byte per factor) for more variables at low degree
+  const bool sparse = n > 16;
+  if (!sparse && 2 * d > 15)
+    return set_error(SOS_ERANGE, "sos_plan: needs 2d <= 15 (4-bit code fields)");
+  if (sparse && (2 * d > 8 || n > 255))
+    return set_error(SOS_ERANGE, "sos_plan: with n > 16 needs 2d <= 8 and n <= 255");
   const int64_t N = binom(n + d, d), M = binom(n + 2 * d, 2 * d);
   if (M >= (int64_t(1) << 31) || N * N >= (int64_t(1) << 31))
     return set_error(SOS_ERANGE, "sos_plan: M and N*N must stay below 2^31");
@@ -86,8 +92,9 @@ int plan_create(int n, int d, int rank, int prec, sos_plan_s** out) {
   sos_plan_s* p = new (std::nothrow) sos_plan_s;
   if (!p) return set_error(SOS_ENOMEM, "sos_plan: host allocation failed");
   p->n = n; p->d = d; p->k = rank; p->prec = prec; p->N = N; p->M = M;
-  p->ngroups = (n + kFieldsPerGroup - 1) / kFieldsPerGroup;
-  p->nwords = (p->ngroups + 1) / 2;
+  p->sparse = sparse;
+  p->ngroups = sparse ? 0 : (n + kFieldsPerGroup - 1) / kFieldsPerGroup;
+  p->nwords = sparse ? 1 : (p->ngroups + 1) / 2;
 
   enumerate_monomials(n, d, p->basis);
   if ((int64_t)p->basis.size() != N * n) {
@@ -95,39 +102,63 @@ int plan_create(int n, int d, int rank, int prec, sos_plan_s** out) {
     return set_error(SOS_EINVAL, "sos_plan: internal enumeration count mismatch");
   }
 
-  // codes
-  p->codes.assign(N * p->nwords, 0u);
-  for (int64_t i = 0; i < N; ++i) {
-    const uint8_t* e = &p->basis[i * n];
-    int t = 0;
-    for (int v = 0; v < n; ++v) t += e[v];
-    int u = t;
-    for (int f = 0; f < n; ++f) {
-      if (f > 0) u -= e[f - 1];
-      const int val = (f == 0) ? t : u;
-      const int g = f / kFieldsPerGroup, w = g / 2;
-      const int shift = (g % 2) * 16 + (f % kFieldsPerGroup) * 4;
-      p->codes[i * p->nwords + w] |= (uint32_t)val << shift;
-    }
-  }
-  // tables: T_g[idx] = sum over the group's fields of field_term(field value)
   const int D = 2 * d;
-  p->tables.assign((size_t)p->ngroups * kGroupEntries, 0);
-  for (int g = 0; g < p->ngroups; ++g) {
-    for (int idx = 0; idx < kGroupEntries; ++idx) {
-      int64_t s = 0;
-      bool valid = true;
-      for (int q = 0; q < kFieldsPerGroup; ++q) {
-        const int f = g * kFieldsPerGroup + q;
-        const int val = (idx >> (4 * q)) & 15;
-        if (f >= n) {
-          if (val != 0) valid = false;
-          continue;
+  if (sparse) {
+    // codes: ascending variable list, byte q = (q-th variable) + 1
+    p->codes.assign(N, 0u);
+    for (int64_t i = 0; i < N; ++i) {
+      const uint8_t* e = &p->basis[i * n];
+      uint32_t c = 0;
+      int q = 0;
+      for (int v = 0; v < n; ++v)
+        for (int m = 0; m < e[v]; ++m) c |= (uint32_t)(v + 1) << (8 * q++);
+      p->codes[i] = c;
+    }
+    // binomial table C[x][y], 0 <= x <= n + D, 0 <= y <= D
+    p->tables.assign((size_t)(n + D + 1) * (D + 1), 0);
+    for (int x = 0; x <= n + D; ++x)
+      for (int y = 0; y <= D; ++y) {
+        const int64_t c = binom(x, y);
+        if (c > INT32_MAX) {
+          delete p;
+          return set_error(SOS_ERANGE, "sos_plan: binomial table entry exceeds int32");
         }
-        if (val > D) valid = false;
-        else s += field_term(n, D, f, val);
+        p->tables[(size_t)x * (D + 1) + y] = (int32_t)c;
       }
-      p->tables[(size_t)g * kGroupEntries + idx] = valid ? (int32_t)s : 0;
+  } else {
+    // codes
+    p->codes.assign(N * p->nwords, 0u);
+    for (int64_t i = 0; i < N; ++i) {
+      const uint8_t* e = &p->basis[i * n];
+      int t = 0;
+      for (int v = 0; v < n; ++v) t += e[v];
+      int u = t;
+      for (int f = 0; f < n; ++f) {
+        if (f > 0) u -= e[f - 1];
+        const int val = (f == 0) ? t : u;
+        const int g = f / kFieldsPerGroup, w = g / 2;
+        const int shift = (g % 2) * 16 + (f % kFieldsPerGroup) * 4;
+        p->codes[i * p->nwords + w] |= (uint32_t)val << shift;
+      }
+    }
+    // tables: T_g[idx] = sum over the group's fields of field_term(field value)
+    p->tables.assign((size_t)p->ngroups * kGroupEntries, 0);
+    for (int g = 0; g < p->ngroups; ++g) {
+      for (int idx = 0; idx < kGroupEntries; ++idx) {
+        int64_t s = 0;
+        bool valid = true;
+        for (int q = 0; q < kFieldsPerGroup; ++q) {
+          const int f = g * kFieldsPerGroup + q;
+          const int val = (idx >> (4 * q)) & 15;
+          if (f >= n) {
+            if (val != 0) valid = false;
+            continue;
+          }
+          if (val > D) valid = false;
+          else s += field_term(n, D, f, val);
+        }
+        p->tables[(size_t)g * kGroupEntries + idx] = valid ? (int32_t)s : 0;
+      }
     }
   }
 
@@ -183,14 +214,10 @@ int plan_create(int n, int d, int rank, int prec, sos_plan_s** out) {
   // are the inverse of the ranking map, built here once (counting sort).
   if (prec == SOS_FP32 && N <= SOS_BATCH_MAX_N) {
     p->batchable = true;
+    std::vector<uint8_t> sum(n);
     auto rank_of = [&](int64_t i, int64_t j) {
-      int64_t r = 0;
-      for (int w = 0; w < p->nwords; ++w) {
-        const uint32_t s = p->codes[i * p->nwords + w] + p->codes[j * p->nwords + w];
-        r += p->tables[(size_t)(2 * w) * kGroupEntries + (s & 0xFFFu)];
-        if (2 * w + 1 < p->ngroups) r += p->tables[(size_t)(2 * w + 1) * kGroupEntries + ((s >> 16) & 0xFFFu)];
-      }
-      return r;
+      for (int v = 0; v < n; ++v) sum[v] = (uint8_t)(p->basis[i * n + v] + p->basis[j * n + v]);
+      return rank_closed_form(n, 2 * d, sum.data());
     };
     p->pair_off.assign(M + 1, 0);
     for (int64_t i = 0; i < N; ++i)

@@ -50,6 +50,86 @@ __host__ __device__ inline int64_t blk_off(int64_t row, int64_t k, int64_t pstri
   return (row / kBlkRows) * pstride + ((k / kBlkK) * kBlkRows + row % kBlkRows) * kBlkK + k % kBlkK;
 }
 
+// ---------------------------------------------------------------------------
+// Ranking of pair sums on the device.  plan.cpp builds one of two encodings:
+//
+//  dense (n <= 16): the additive 4-bit suffix-sum codes above; the rank of
+//    alpha_i + alpha_j is a sum of group-table lookups at code_i + code_j.
+//  sparse (n > 16, 2d <= 8, n <= 255): each basis monomial is its ascending
+//    list of variables (byte p holds v_p + 1, 0 = none), the product's list
+//    is the merge of the two, and with D = 2d, t the merged length and
+//    v_0 = 0, m_p = t - p,
+//      rank = C(n+D, D) - C(n+t, t)
+//           + sum_{p=1..t} [ C(n - v_{p-1} + m_p, m_p + 1) - C(n - v_p + m_p, m_p + 1) ],
+//    the number of higher-degree monomials plus, position by position, the
+//    number of same-degree lists that agree before p and are smaller at p
+//    (a hockey-stick sum of multiset counts).  Binomials come from a table
+//    C[x][y], 0 <= x <= n + D, 0 <= y <= D.
+// ---------------------------------------------------------------------------
+struct RankTab {
+  const uint32_t* __restrict__ codes;   // dense: N x nwords; sparse: N packed lists
+  const int32_t* __restrict__ tables;   // dense: ngroups x 4096; sparse: binomial table
+  int nwords, ngroups;
+  int sparse, n, D, total;              // sparse only (total = C(n + D, D))
+};
+
+// The codes of row i, loaded once for many partners j.
+struct RankRow {
+  uint32_t c[kMaxWords];
+};
+
+__device__ __forceinline__ RankRow rank_row(const RankTab& t, int i) {
+  RankRow r;
+#pragma unroll
+  for (int w = 0; w < kMaxWords; ++w) r.c[w] = (w < t.nwords) ? t.codes[(size_t)i * t.nwords + w] : 0u;
+  return r;
+}
+
+__device__ __forceinline__ int rank_binom(const RankTab& t, int x, int y) { return t.tables[x * (t.D + 1) + y]; }
+
+__device__ __forceinline__ int pair_rank_row(const RankTab& t, const RankRow& ri, int j) {
+  if (!t.sparse) {
+    int r = 0;
+#pragma unroll
+    for (int w = 0; w < kMaxWords; ++w) {
+      if (w < t.nwords) {
+        const uint32_t s = ri.c[w] + t.codes[(size_t)j * t.nwords + w];
+        r += t.tables[(2 * w) * kGroupEntries + (s & 0xFFFu)];
+        if (2 * w + 1 < t.ngroups) r += t.tables[(2 * w + 1) * kGroupEntries + ((s >> 16) & 0xFFFu)];
+      }
+    }
+    return r;
+  }
+  uint32_t a = ri.c[0], b = t.codes[j];
+  int g[8];
+  int len = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {  // merge the two ascending lists
+    const uint32_t va = a & 0xFFu, vb = b & 0xFFu;
+    const bool take_a = va != 0 && (vb == 0 || va <= vb);
+    const uint32_t v = take_a ? va : vb;
+    g[q] = (int)v - 1;
+    if (take_a) a >>= 8;
+    else b >>= 8;
+    len += v != 0;
+  }
+  int r = t.total - rank_binom(t, t.n + len, len);
+  int prev = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    if (q < len) {
+      const int m = len - 1 - q, v = g[q];
+      r += rank_binom(t, t.n - prev + m, m + 1) - rank_binom(t, t.n - v + m, m + 1);
+      prev = v;
+    }
+  }
+  return r;
+}
+
+__device__ __forceinline__ int pair_rank(const RankTab& t, int i, int j) {
+  return pair_rank_row(t, rank_row(t, i), j);
+}
+
 struct Layout {
   // byte offsets into the workspace
   size_t codes = 0, tables = 0, r = 0, scal = 0;
@@ -78,6 +158,7 @@ struct sos_plan_s {
   int n = 0, d = 0, k = 0, prec = 0;
   int64_t N = 0, M = 0;
   int ngroups = 0, nwords = 0;
+  bool sparse = false;             // sparse ranking encoding (n > 16)
   std::vector<uint8_t> basis;      // N x n exponents, library order
   std::vector<uint32_t> codes;     // N x nwords
   std::vector<int32_t> tables;     // ngroups x 4096
@@ -124,6 +205,19 @@ int hip_error(hipError_t e, const char* what);
 }  // namespace sos
 
 namespace sos {
+// device ranking view of a bound plan
+inline RankTab rank_tab(const sos_plan_s* p) {
+  RankTab t;
+  t.codes = (const uint32_t*)(p->ws + p->lay.codes);
+  t.tables = (const int32_t*)(p->ws + p->lay.tables);
+  t.nwords = p->nwords;
+  t.ngroups = p->ngroups;
+  t.sparse = p->sparse ? 1 : 0;
+  t.n = p->n;
+  t.D = 2 * p->d;
+  t.total = (int)p->M;
+  return t;
+}
 // kernel launchers (kernels.hip)
 hipError_t launch_pair_ranks(const sos_plan_s* p, int32_t* out, hipStream_t s);
 // which operand copies k_prep writes (the ones the coming forward and backward read)

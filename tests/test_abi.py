@@ -36,6 +36,22 @@ def test_exponents_match_oracle(n, d):
     assert np.array_equal(pl.exponents(1), O.monomials(n, 2 * d))
 
 
+@pytest.mark.parametrize("n,d", [(17, 2), (20, 3), (40, 2)])
+def test_exponents_match_oracle_many_variables(n, d):
+    pl = S.Plan(n, d, 3, "fp32", device="cpu")
+    assert pl.N == comb(n + d, d) and pl.M == comb(n + 2 * d, 2 * d)
+    assert np.array_equal(pl.exponents(0), O.monomials(n, d))
+    if n <= 20:
+        assert np.array_equal(pl.exponents(1), O.monomials(n, 2 * d))
+
+
+def test_quartic_hundred_variable_sizes():
+    """The paper's largest workload, quartic forms in 100 variables (Section
+    1.2: l = 5,050, m = 4,421,275), is (n, d) = (99, 2) in the degree-<=d basis."""
+    pl = S.Plan(99, 2, 5050, "bf16x3", device="cpu")
+    assert (pl.N, pl.M) == (5050, 4421275)
+
+
 @pytest.mark.parametrize("n,d", [(10, 5), (12, 6)])
 def test_large_basis_matches_oracle(n, d):
     pl = S.Plan(n, d, 7, "bf16x3", device="cpu")
@@ -57,7 +73,9 @@ def test_plan_argument_errors():
     assert _plan_rc(3, 2, 0, 0) == -1          # rank < 1
     assert _plan_rc(3, 2, 5, 9) == -1          # unknown precision
     assert _plan_rc(3, 8, 5, 0) == -2          # 2d = 16 > 15
-    assert _plan_rc(17, 1, 5, 0) == -2         # n > 16
+    assert _plan_rc(17, 1, 5, 0) == 0          # n > 16: variable-list ranking
+    assert _plan_rc(17, 5, 5, 0) == -2         # n > 16 needs 2d <= 8
+    assert _plan_rc(256, 1, 5, 0) == -2        # n > 255
     assert _plan_rc(16, 7, 5, 0) == -2         # N*N >= 2^31
     assert b"2d" in S._lib.sos_last_error() or True
 

@@ -75,12 +75,24 @@ def assert_close_scaled(got, want, scale, tol, what):
 # Ranking: bit-exact
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n,d", [(1, 1), (1, 7), (2, 7), (3, 2), (4, 3), (6, 3), (6, 4), (16, 1), (8, 4), (10, 5)])
+@pytest.mark.parametrize("n,d", [(1, 1), (1, 7), (2, 7), (3, 2), (4, 3), (6, 3), (6, 4), (16, 1), (8, 4), (10, 5),
+                                 (17, 1), (17, 2), (20, 3), (40, 2), (24, 3)])
 def test_pair_ranks_bit_exact(n, d):
     pl = S.Plan(n, d, 4, "fp32")
     got = pl.pair_ranks().cpu().numpy()
     want = O.pair_ranks(n, d)
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("n,d", [(18, 4), (99, 2)])
+def test_pair_ranks_many_variables_sampled_rows(n, d):
+    """Variable-list ranking at the longest merged lists (2d = 8) and at the
+    paper's hundred-variable quartic, on sampled rows of the N x N map."""
+    pl = S.Plan(n, d, 8, "bf16x3")
+    got = pl.pair_ranks()
+    rows = np.unique(np.r_[0, 1, pl.N - 1, pl.N // 2, np.random.default_rng(6).integers(0, pl.N, 40)])
+    want = O.pair_ranks_sparse(n, d, rows=rows)
+    assert np.array_equal(got[torch.tensor(rows, device=dev())].cpu().numpy(), want)
 
 
 def test_pair_ranks_n12d6_sampled_rows():
@@ -98,7 +110,8 @@ def test_pair_ranks_n12d6_sampled_rows():
 # Loss / gradient parity at sizes that span several tiles and ragged tails
 # ---------------------------------------------------------------------------
 
-CASES = [(1, 1, 1), (3, 2, 20), (4, 3, 37), (6, 3, 168), (6, 4, 420), (10, 5, 300)]
+# (17, 2) and (40, 2) take the variable-list ranking (n > 16)
+CASES = [(1, 1, 1), (3, 2, 20), (4, 3, 37), (6, 3, 168), (6, 4, 420), (10, 5, 300), (17, 2, 40), (40, 2, 130)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])

@@ -1,0 +1,65 @@
+"""The paper's largest workload at full size: quartic forms in 100 variables
+(Section 1.2, Section 3.1 table), i.e. (n, d) = (99, 2) in the degree-<=d
+basis: N = 5,050, M = 4,421,275, full rank k = N.  The ranking takes the
+variable-list encoding (n > 16).  The oracle forms the whole coefficient
+vector here (25.5 M pairs, row blocks of 505), so the comparison is
+element by element.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import gaussian
+
+torch = pytest.importorskip("torch")
+S = pytest.importorskip("paper_2410_19844_amd")
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def gamma(n):
+    return n * U32 / (1 - n * U32)
+
+
+@pytest.fixture(scope="module")
+def case():
+    n, d = 99, 2
+    N = math.comb(n + d, d)
+    k = N
+    W = gaussian((N, k), 41, 1.0 / math.sqrt(k))
+    Wd = torch.tensor(W, dtype=torch.float32, device="cuda")
+    W64 = Wd.double().cpu().numpy()
+    M = math.comb(n + 2 * d, 2 * d)
+    p = gaussian(M, 42)
+    # oracle coefficients, row block by row block
+    G = W64 @ W64.T
+    Ga = np.abs(W64) @ np.abs(W64).T
+    c = np.zeros(M)
+    cabs = np.zeros(M)
+    basis, cidx = O.monomials_sparse(n, d), O.SparseIndex(n, 2 * d)
+    for r0 in range(0, N, 505):
+        rows = np.arange(r0, min(N, r0 + 505))
+        pr = O.pair_ranks_sparse(n, d, rows=rows, basis=basis, cidx=cidx)
+        c += np.bincount(pr.ravel(), weights=G[rows].ravel(), minlength=M)
+        cabs += np.bincount(pr.ravel(), weights=Ga[rows].ravel(), minlength=M)
+    return dict(n=n, d=d, N=N, M=M, k=k, Wd=Wd, p=p, c=c, cabs=cabs)
+
+
+@pytest.mark.parametrize("prec,exact", [("bf16x3", False), ("bf16x3", True), ("fp32", False)])
+def test_quartic100_coefficients(case, prec, exact):
+    pl = S.Plan(case["n"], case["d"], case["k"], prec)
+    pd = torch.tensor(case["p"], dtype=torch.float64, device="cuda")
+    L, _, r = pl.loss_grad(case["Wd"], pd, grad=False, want_r=True, exact=exact)
+    got = r.cpu().numpy() + case["p"]
+    K = case["k"]
+    tol = 1e-10 if exact else (gamma(K + 1) + U32 if prec == "fp32" else 3.1 * 2.0 ** -16 + gamma(3 * K) + U32)
+    bound = tol * case["cabs"] + 1e-15 * np.abs(case["p"])
+    err = np.abs(got - case["c"]) / bound
+    assert err.max() <= 1.0, f"max |err|/bound {err.max():.3g}"
+    want_L = float(np.sum((case["c"] - case["p"]) ** 2))
+    dc = tol * case["cabs"]
+    assert abs(L.item() - want_L) <= 2 * np.sum(np.abs(case["c"] - case["p"]) * dc) + np.sum(dc * dc) + 1e-12 * want_L

@@ -261,3 +261,53 @@ def test_motzkin_padding_keeps_distance(n):
     base = O.psd_distance(p3, 3, 3).dist2
     pn = O.poly_vector(motzkin_terms(n), n, 3)
     assert abs(O.psd_distance(pn, n, 3, iters=6000).dist2 - base) <= 1e-6 * base
+
+
+# ---------------------------------------------------------------------------
+# Sparse (variable-list) representation for many variables
+# ---------------------------------------------------------------------------
+
+def _dense_of(lists, n):
+    out = np.zeros((lists.shape[0], n), dtype=np.int64)
+    for q in range(lists.shape[1]):
+        v = lists[:, q]
+        ok = v >= 0
+        np.add.at(out, (np.nonzero(ok)[0], v[ok]), 1)
+    return out
+
+
+@pytest.mark.parametrize("n,D", [(1, 3), (3, 4), (5, 4), (20, 3)])
+def test_sparse_order_is_the_basis_order(n, D):
+    """Lexicographic ascending variable lists, degree by degree, reproduce the
+    dense basis order (itself pinned to the Section 1.1 example)."""
+    assert np.array_equal(_dense_of(O.monomials_sparse(n, D), n), O.monomials(n, D))
+
+
+@pytest.mark.parametrize("n,d", [(2, 2), (4, 2), (6, 3), (3, 5)])
+def test_sparse_pair_ranks_equal_dense(n, d):
+    assert np.array_equal(O.pair_ranks_sparse(n, d), O.pair_ranks(n, d))
+
+
+def test_sparse_counts_of_the_hundred_variable_quartic():
+    """Section 1.2: quartics in 100 variables have l = 5,050 basis monomials and
+    m = 4,421,275 coefficients; as forms in n = 100 they are our (99, 2)."""
+    assert len(O.monomials_sparse(99, 2)) == 5050
+    assert len(O.SparseIndex(99, 4)) == 4421275
+
+
+def test_sparse_evaluation_identity_many_variables():
+    """sum_b c_b x^b = ||W^T m_d(x)||^2 with the sparse ranks (n = 40, d = 2)."""
+    n, d, k = 40, 2, 3
+    rng = np.random.default_rng(3)
+    basis = O.monomials_sparse(n, d)
+    coeffs = O.monomials_sparse(n, 2 * d)
+    W = rng.standard_normal((len(basis), k))
+    c = O.coefficients(W, n, d, O.pair_ranks_sparse(n, d))
+    for _ in range(3):
+        x = rng.uniform(-1, 1, n)
+        xe = np.append(x, 1.0)                         # index -1 (padding) reads 1
+        m = np.prod(xe[basis], axis=1)
+        xb = np.prod(xe[coeffs], axis=1)
+        lhs = float(c @ xb)
+        rhs = float(np.sum((W.T @ m) ** 2))
+        assert abs(lhs - rhs) <= 1e-12 * (np.abs(c) @ np.abs(xb))

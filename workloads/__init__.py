@@ -80,6 +80,7 @@ class Workload:
     w_std: float         # standard deviation of W's initial entries
     w0_seed: int = 0
     w_seed: int = 1
+    w0_uniform: bool = False   # W0 entries uniform in [-w0_std, w0_std] instead of normal
 
     @property
     def N(self) -> int:
@@ -90,6 +91,8 @@ class Workload:
         return coeff_size(self.n, self.d)
 
     def W0(self) -> np.ndarray:
+        if self.w0_uniform:
+            return uniform((self.N, self.w0_rank), self.w0_seed, -self.w0_std, self.w0_std)
         return gaussian((self.N, self.w0_rank), self.w0_seed, self.w0_std)
 
     def W_init(self) -> np.ndarray:
@@ -110,6 +113,13 @@ CONFIGS = {
     # n=12, d=6: N=18,564, M=2,704,156.  W0 18564x2000 N(0,1)/sqrt(2000); W 18564^2 N(0, 1/k).
     "n12d6": Workload("n12d6", 12, 6, rank=18564, w0_rank=2000, w0_std=2000 ** -0.5,
                       w_std=18564 ** -0.5),
+    # The paper's largest problem (Sections 1.2 and 3.1): quartic forms in 100
+    # variables = degree <= 2 in n=99: N=5,050, M=4,421,275, full rank k = N.
+    # p = m^T B B^T m with B uniform as in Section 3.1, here N x N and scaled
+    # by 1/sqrt(N) (p scaled by 1/N: the relative residual is unchanged);
+    # W 5050^2 N(0, 1/k).
+    "q100": Workload("q100", 99, 2, rank=5050, w0_rank=5050, w0_std=5050 ** -0.5,
+                     w_std=5050 ** -0.5, w0_uniform=True),
 }
 
 
