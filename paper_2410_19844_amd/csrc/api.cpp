@@ -239,6 +239,10 @@ int sos_plan_bind(sos_plan_t p, void* d_ws, size_t ws_bytes, void* stream) {
                            hipMemcpyHostToDevice, s), "sos_plan_bind: pair offsets");
     SOS_HIP(hipMemcpyAsync(p->ws + p->lay.pair_idx, p->pair_idx.data(), p->pair_idx.size() * 4,
                            hipMemcpyHostToDevice, s), "sos_plan_bind: pair lists");
+    SOS_HIP(hipMemcpyAsync(p->ws + p->lay.pair_pos, p->pair_pos.data(), p->pair_pos.size() * 4,
+                           hipMemcpyHostToDevice, s), "sos_plan_bind: pair positions");
+    SOS_HIP(hipMemcpyAsync(p->ws + p->lay.rank_map, p->rank_map.data(), p->rank_map.size() * 4,
+                           hipMemcpyHostToDevice, s), "sos_plan_bind: rank map");
     SOS_HIP(hipMemsetAsync(p->ws + p->lay.bcount, 0, 4, s), "sos_plan_bind: block counter");
   }
   SOS_HIP(hipStreamSynchronize(s), "sos_plan_bind");

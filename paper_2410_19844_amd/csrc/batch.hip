@@ -8,21 +8,23 @@
 // Every block works on one problem, and every sum runs in an order fixed by
 // that problem's shape alone (no floating-point atomics), so a problem's
 // results do not depend on the other problems in the launch.  No block
-// contracts over more than kBatchSlice elements: longer contractions are
+// contracts over more than kBatchSlice (Gram) or kBatchSliceJ (backward)
+// elements: longer contractions are
 // split into slices with one partial result each, summed in slice order by
 // the consumer, which keeps every block's dependent-load chain short.
 //
 //   k_b_gram   partial G = W W^T per K slice, upper-triangle 32 x 32 tiles,
 //              FP32 entries converted to FP64 (exact products) on
 //              v_mfma_f64_16x16x4, the next K chunk prefetched into
-//              registers while the current one is multiplied
+//              registers while the current one is multiplied; each entry
+//              stored at its pair's place in the coefficient-ordered lists
 //   k_b_coeff  r_m = sum over the pairs (i <= j) of monomial m of
 //              (2 - [i = j]) G_ij (G_ij summed over slices), minus p_m, in
-//              the plan's pair order; R_ij = R_ji = r_m written densely in
-//              FP32; L = sum r_m^2 by a fixed-order block sum and a
-//              fixed-order sum of the block partials in the block that
-//              arrives last
-//   k_b_rw     partial g = 4 R W per slice of the contraction index, FP32
+//              the plan's pair order; L = sum r_m^2 by a fixed-order block
+//              sum and a fixed-order sum of the block partials in the block
+//              that arrives last
+//   k_b_rw     partial g = 4 R W per slice of the contraction index, FP32,
+//              R_ij = r[rank of alpha_i + alpha_j] through the plan's map
 //   k_b_adam   g = sum of the slices, bias-corrected Adam in FP32
 #include <hip/hip_runtime.h>
 
@@ -43,8 +45,9 @@ struct Req {
   float* v;
   const double* p;           // M
   double* r;                 // M
-  double* Gp;                // sg x N x N partial Gram (upper triangle)
-  float* R;                  // N x N
+  double* Gp;                // sg x P partial Gram, P = N (N + 1) / 2 entries in pair-list order
+  const int32_t* pair_pos;   // N x N: position of a pair in the pair lists
+  const int32_t* rank_map;   // N x N: R_ij = r[rank_map[i N + j]]
   float* gp;                 // sr x N x k partial gradient
   double* part;              // loss partials, one per coefficient block
   unsigned* count;           // blocks of k_b_coeff done (returns to zero)
@@ -123,12 +126,15 @@ __global__ __launch_bounds__(256) void k_b_gram(Args a) {
     }
     __syncthreads();
   }
-  double* G = R.Gp + (size_t)s * R.N * R.N;
+  // written at the pair's position in the coefficient-ordered pair lists, so
+  // that each coefficient later reads its pairs from one contiguous range
+  const size_t P = (size_t)R.N * (R.N + 1) / 2;
+  double* G = R.Gp + (size_t)s * P;
   const int j = J * TF + wn * 16 + (l & 15);
 #pragma unroll
   for (int qq = 0; qq < 4; ++qq) {
     const int i = I * TF + wm * 16 + (l >> 4) + 4 * qq;
-    if (i < R.N && j < R.N && i <= j) G[(size_t)i * R.N + j] = acc[qq];
+    if (i < R.N && j < R.N && i <= j) G[R.pair_pos[(size_t)i * R.N + j]] = acc[qq];
   }
 }
 
@@ -143,7 +149,7 @@ __device__ __forceinline__ double block_sum256(double x, double* sh4) {
   return t;
 }
 
-// Coefficients, residual, dense R and the loss; grid (blocks of 256
+// Coefficients, residual and the loss; grid (blocks of 256
 // coefficients, problem).
 __global__ __launch_bounds__(256) void k_b_coeff(Args a) {
   const Req& R = a.q[blockIdx.y];
@@ -155,24 +161,27 @@ __global__ __launch_bounds__(256) void k_b_coeff(Args a) {
   double rr = 0.0;
   if (m < R.M) {
     const int e0 = R.pair_off[m], e1 = R.pair_off[m + 1];
-    const size_t NN = (size_t)R.N * R.N;
+    const size_t P = (size_t)R.N * (R.N + 1) / 2;
+    // G of pair e: the slices in slice order, doubled off the diagonal; the
+    // pairs of m are entries e0 .. e1 - 1 of every slice (contiguous)
+    auto pair_val = [&](int e) {
+      double gij = R.Gp[e];
+      for (int s = 1; s < R.sg; ++s) gij += R.Gp[s * P + e];
+      return ((uint32_t)R.pair_idx[e] >> 31) ? 2.0 * gij : gij;
+    };
+    // pairs four at a time (independent loads in flight), added in pair order
     double c = 0.0;
-    for (int e = e0; e < e1; ++e) {
-      const uint32_t x = (uint32_t)R.pair_idx[e];
-      const double* g = R.Gp + (x & 0x7FFFFFFFu);
-      double gij = g[0];
-      for (int s = 1; s < R.sg; ++s) gij += g[s * NN];
-      c += (x >> 31) ? 2.0 * gij : gij;
+    int e = e0;
+    for (; e + 4 <= e1; e += 4) {
+      const double v0 = pair_val(e), v1 = pair_val(e + 1), v2 = pair_val(e + 2), v3 = pair_val(e + 3);
+      c += v0;
+      c += v1;
+      c += v2;
+      c += v3;
     }
+    for (; e < e1; ++e) c += pair_val(e);
     rr = c - R.p[m];
     R.r[m] = rr;
-    const float rf = (float)rr;
-    for (int e = e0; e < e1; ++e) {
-      const uint32_t idx = (uint32_t)R.pair_idx[e] & 0x7FFFFFFFu;
-      const uint32_t i = idx / (uint32_t)R.N, j = idx % (uint32_t)R.N;
-      R.R[idx] = rf;
-      R.R[(size_t)j * R.N + i] = rf;
-    }
   }
   const double b = block_sum256(rr * rr, sh4);
   if (threadIdx.x == 0) {
@@ -194,7 +203,7 @@ __global__ __launch_bounds__(256) void k_b_coeff(Args a) {
   }
 }
 
-// Partial g = 4 R W over j in one slice: tiles of 32 rows (i) x 64 columns
+// Partial g = 4 R W over j in one slice of kBatchSliceJ: tiles of 32 rows (i) x 64 columns
 // (l), j in chunks of 32 through LDS, the next chunk prefetched into
 // registers.  Thread (ty, tx) of a 16 x 16 grid owns rows 2 ty, 2 ty + 1 and
 // columns tx + 16 w.
@@ -208,8 +217,8 @@ __global__ __launch_bounds__(256) void k_b_rw(Args a) {
   const int t = local / R.sr, s = local % R.sr;
   const int nl = (R.k + TBL - 1) / TBL;
   const int I = t / nl, L = t % nl;
-  const int jb = s * kBatchSlice;
-  const int je = min(R.N, jb + kBatchSlice);
+  const int jb = s * kBatchSliceJ;
+  const int je = min(R.N, jb + kBatchSliceJ);
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   float rr[TBI * TBK / 256], ww[TBK * TBL / 256];
   auto load = [&](int j0) {
@@ -217,7 +226,7 @@ __global__ __launch_bounds__(256) void k_b_rw(Args a) {
     for (int u = 0; u < TBI * TBK / 256; ++u) {
       const int e = threadIdx.x + 256 * u;
       const int i = I * TBI + e / TBK, j = j0 + e % TBK;
-      rr[u] = (i < R.N && j < je) ? R.R[(size_t)i * R.N + j] : 0.f;
+      rr[u] = (i < R.N && j < je) ? (float)R.r[R.rank_map[(size_t)i * R.N + j]] : 0.f;
     }
 #pragma unroll
     for (int u = 0; u < TBK * TBL / 256; ++u) {
@@ -313,18 +322,19 @@ hipError_t launch_step_group(sos_plan_s* const* plans, void* const* W, void* con
     R.p = p[q];
     R.r = (double*)(ws + pl->lay.r);
     R.Gp = (double*)(ws + pl->lay.bG);
-    R.R = (float*)(ws + pl->lay.bR);
+    R.rank_map = (const int32_t*)(ws + pl->lay.rank_map);
     R.gp = (float*)(ws + pl->lay.bg);
     R.part = (double*)(ws + pl->lay.bpart);
     R.count = (unsigned*)(ws + pl->lay.bcount);
     R.pair_off = (const int32_t*)(ws + pl->lay.pair_off);
     R.pair_idx = (const int32_t*)(ws + pl->lay.pair_idx);
+    R.pair_pos = (const int32_t*)(ws + pl->lay.pair_pos);
     R.loss = losses + q;
     R.N = (int)pl->N;
     R.M = (int)pl->M;
     R.k = pl->k;
     R.sg = batch_slices(R.k);
-    R.sr = batch_slices(R.N);
+    R.sr = batch_slices_j(R.N);
     const int ti = (R.N + bat::TF - 1) / bat::TF;
     a.fwd_off[q + 1] = a.fwd_off[q] + ti * (ti + 1) / 2 * R.sg;
     const int bi = (R.N + bat::TBI - 1) / bat::TBI, bl = (R.k + bat::TBL - 1) / bat::TBL;

@@ -224,13 +224,21 @@ int plan_create(int n, int d, int rank, int prec, sos_plan_s** out) {
       for (int64_t j = i; j < N; ++j) ++p->pair_off[rank_of(i, j) + 1];
     for (int64_t m = 0; m < M; ++m) p->pair_off[m + 1] += p->pair_off[m];
     p->pair_idx.assign(N * (N + 1) / 2, 0);
+    p->pair_pos.assign(N * N, 0);
+    p->rank_map.assign(N * N, 0);
     std::vector<int32_t> fill(p->pair_off.begin(), p->pair_off.end() - 1);
     for (int64_t i = 0; i < N; ++i)
-      for (int64_t j = i; j < N; ++j)
-        p->pair_idx[fill[rank_of(i, j)]++] = (int32_t)((uint32_t)(i * N + j) | (i < j ? 0x80000000u : 0u));
-    L.bG = take((size_t)batch_slices(rank) * N * N * 8);
-    L.bR = take((size_t)N * N * 4);
-    L.bg = take((size_t)batch_slices((int)N) * N * rank * 4);
+      for (int64_t j = i; j < N; ++j) {
+        const int64_t m = rank_of(i, j);
+        const int32_t e = fill[m]++;
+        p->pair_idx[e] = (int32_t)((uint32_t)(i * N + j) | (i < j ? 0x80000000u : 0u));
+        p->pair_pos[i * N + j] = p->pair_pos[j * N + i] = e;
+        p->rank_map[i * N + j] = p->rank_map[j * N + i] = (int32_t)m;
+      }
+    L.bG = take((size_t)batch_slices(rank) * p->pair_idx.size() * 8);
+    L.pair_pos = take(p->pair_pos.size() * 4);
+    L.rank_map = take(p->rank_map.size() * 4);
+    L.bg = take((size_t)batch_slices_j((int)N) * N * rank * 4);
     L.bpart = take((size_t)((M + 255) / 256) * 8);
     L.bcount = take(4);
     L.pair_off = take(p->pair_off.size() * 4);

@@ -41,8 +41,10 @@ constexpr int kPanelPadBytes = 4096;
 
 // Grouped serving kernels: the contraction length a block covers, and the
 // number of such slices (each with its own partial result) for length len.
-constexpr int kBatchSlice = 256;
+constexpr int kBatchSlice = 256;    // K slices of the Gram
+constexpr int kBatchSliceJ = 128;   // slices of the backward's contraction index
 __host__ __device__ inline int batch_slices(int len) { return (len + kBatchSlice - 1) / kBatchSlice; }
+__host__ __device__ inline int batch_slices_j(int len) { return (len + kBatchSliceJ - 1) / kBatchSliceJ; }
 __host__ __device__ inline int64_t panel_stride(int64_t nkb, int elem_bytes) {
   return nkb * kBlkRows * kBlkK + kPanelPadBytes / elem_bytes;
 }
@@ -142,9 +144,10 @@ struct Layout {
   size_t x_f32 = 0;              // FP32 W, panel-blocked (exact forward), rows = Np, K extent Kp
   size_t g = 0;                  // gradient scratch, N x k in W's type
   // grouped (serving) path, FP32 plans with N <= SOS_BATCH_MAX_N only
-  size_t bG = 0;                 // FP64 partial Gram per K slice: kBatchSlices(k) x N x N (upper triangle used)
-  size_t bR = 0;                 // FP32 R, N x N row-major (both triangles)
-  size_t bg = 0;                 // FP32 partial gradient per j slice: kBatchSlices(N) x N x k
+  size_t bG = 0;                 // FP64 partial Gram per K slice: batch_slices(k) x P, entries in pair-list order
+  size_t pair_pos = 0;           // N x N int32: position of pair (min(i,j), max(i,j)) in the pair lists
+  size_t rank_map = 0;           // N x N int32: coefficient index of alpha_i + alpha_j (R_ij = r[map])
+  size_t bg = 0;                 // FP32 partial gradient per j slice: batch_slices_j(N) x N x k
   size_t bpart = 0;              // FP64 loss partials, one per coefficient block of 256
   size_t bcount = 0;             // u32 arrival counter of those blocks (zero between calls)
   size_t pair_off = 0;           // M + 1 int32: pairs of coefficient m are pair_idx[off[m] .. off[m+1])
@@ -178,7 +181,7 @@ struct sos_plan_s {
   const void* copies_W = nullptr;
   int copies_mode = 0;
   int t_cur = 0;                   // transposed copy for the next backward: 0 = t_hi, 1 = t_lo
-  std::vector<int32_t> pair_off, pair_idx;
+  std::vector<int32_t> pair_off, pair_idx, pair_pos, rank_map;
   size_t state_bytes = 0;
   char* ws = nullptr;
   size_t ws_size = 0;
