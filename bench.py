@@ -33,6 +33,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAKS_TFLOPS = {"bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6}
+# Adam step sizes (bulk, exact-forward finisher) per workload, chosen by a
+# short sweep of time to 1e-8 and then frozen
+LR_DEFAULTS = {"n12d6": (3e-3, 1e-3), "q100": (3e-3, 3e-3)}
 DTYPE = {"bf16x3": "bf16", "fp32": "fp32", "fp64": "fp64"}
 
 
@@ -53,7 +56,8 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-steps", type=int, default=3000)
     ap.add_argument("--lr", type=float, default=None)
-    ap.add_argument("--lr-exact", type=float, default=1e-3, help="Adam step size in the exact-forward phase")
+    ap.add_argument("--lr-exact", type=float, default=None,
+                    help="Adam step size in the exact-forward phase (default per workload)")
     ap.add_argument("--switch-rel", type=float, default=None,
                     help="ladder switch point (default 1e-5 for bf16x3, 1e-6 for fp32)")
     ap.add_argument("--mid-rel", type=float, default=None,
@@ -219,7 +223,10 @@ def main():
         return
     c, W, p = make_inputs(S, torch, a.workload, a.precision)
     pl = S.Plan(c.n, c.d, c.rank, a.precision)
-    lr = a.lr if a.lr is not None else 3e-3
+    lr_bulk, lr_fin = LR_DEFAULTS.get(a.workload, (3e-3, 1e-3))
+    lr = a.lr if a.lr is not None else lr_bulk
+    if a.lr_exact is None:
+        a.lr_exact = lr_fin
     if a.switch_rel is None:
         a.switch_rel = {"bf16x3": 3e-6, "fp32": 1e-6, "fp64": 0.0}[a.precision]
     adam = S.Adam(lr=lr)
