@@ -50,11 +50,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=1024)
     ap.add_argument("--mode", default="step", choices=["step", "ttt", "serve"])
-    ap.add_argument("--requests", type=int, default=1024, help="serve: requests in the stream")
+    ap.add_argument("--requests", type=int, default=4096, help="serve: requests in the stream")
     ap.add_argument("--slots", type=int, default=48, help="serve: requests on the device at once")
     ap.add_argument("--hbm-budget-gib", type=float, default=32.0, help="serve: device memory for active requests")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-steps", type=int, default=3000)
+    ap.add_argument("--rank", type=int, default=None,
+                    help="number of squares k (columns of W) instead of the workload's (rank study)")
     ap.add_argument("--lr", type=float, default=None)
     ap.add_argument("--lr-exact", type=float, default=None,
                     help="Adam step size in the exact-forward phase (default per workload)")
@@ -96,11 +98,16 @@ def measured_traffic(key):
     return None if v is None else v["read_bytes"] + v["write_bytes"]
 
 
-def make_inputs(S, torch, wl, prec):
-    """W0 -> p on the GPU (exact FP64 forward of the FP32-rounded W0), W init."""
+def make_inputs(S, torch, wl, prec, rank=None):
+    """W0 -> p on the GPU (exact FP64 forward of the FP32-rounded W0), W init.
+    rank: number of squares k of the trained W instead of the workload's
+    (W init then N(0, 1/k), the workloads' convention)."""
+    import dataclasses
     dev = torch.device("cuda")
     from workloads import CONFIGS
     c = CONFIGS[wl]
+    if rank is not None:
+        c = dataclasses.replace(c, rank=rank, w_std=rank ** -0.5)
     W0 = torch.tensor(c.W0(), dtype=torch.float32, device=dev)
     pl0 = S.Plan(c.n, c.d, c.w0_rank, "fp32")
     zeros = torch.zeros(c.M, dtype=torch.float64, device=dev)
@@ -221,7 +228,7 @@ def main():
     if a.mode == "serve":
         serve_mode(a, S, torch)
         return
-    c, W, p = make_inputs(S, torch, a.workload, a.precision)
+    c, W, p = make_inputs(S, torch, a.workload, a.precision, a.rank)
     pl = S.Plan(c.n, c.d, c.rank, a.precision)
     lr_bulk, lr_fin = LR_DEFAULTS.get(a.workload, (3e-3, 1e-3))
     lr = a.lr if a.lr is not None else lr_bulk
