@@ -298,7 +298,7 @@ def main():
     traffic = None
     if c.name == "n12d6" and a.precision == "bf16x3" and a.single_backward:
         key = {("gram", False): "step:k_gram_bf3", ("gram", True): "exact:k_gram_x64",
-               ("rw", False): "step:k_rw_bf3<false>", ("rw", True): "step:k_rw_bf3<false>"}[(dom, a.exact)]
+               ("rw", False): "step:k_rw_adam_bf3", ("rw", True): "step:k_rw_adam_bf3"}[(dom, a.exact)]
         traffic = measured_traffic(key)
     out = {
         "metric": f"grad steps/s at n={c.n} d={c.d}", "value": 1e3 / ms_step, "unit": "steps/s",
