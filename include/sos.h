@@ -240,6 +240,59 @@ int sos_step_batch(const sos_plan_t* plans, void* const* d_W, void* const* d_sta
 int sos_loss_batch(const sos_plan_t* plans, const void* const* d_W, const double* const* d_p,
                    double* d_losses, int count, void* stream);
 
+/* ---------------------------------------------------------------------
+ * Two-layer network (Section 2, eq. NN): a quartic form in n variables as
+ * ||B Z A x||^2 with A (m x n), B (k x n m) and the augmentation
+ * Z(x) A x = (x_1 A x, .., x_n A x); output l is the quadratic form
+ * f_l = sum_{a,c} P[l,a,c] x_a x_c, P[l,a,c] = sum_b B[l, a m + b] A[b, c].
+ * Forms of degree 4 in n variables are the polynomials of degree <= 4 in
+ * x_1 .. x_{n-1} (x_n = 1), so these calls take a bound plan (n - 1, 2) of
+ * rank k: p is indexed like that plan's
+ * coefficients, and the network's factor W = net(A, B) (N x k, the
+ * coefficients of each f_l over the plan's basis, in the plan's W type)
+ * goes through the plan's loss, gradient and certificate.  With an
+ * SOS_FP64 plan W is formed in FP64 from exact products of the FP32
+ * weights; with FP32 and split plans W is rounded to FP32 after the map,
+ * which puts a floor of about 3e-8 under the reachable relative residual.
+ * The weights are stored transposed, row-major FP32: d_At = A^T (n x m),
+ * d_Bt = B^T (n m x k).  d_state is caller memory of sos_net_query's size
+ * (Adam moments of both, W, scratch); its first call uploads small index
+ * maps into it.  Errors: SOS_EINVAL for a plan that is not (n - 1, 2),
+ * n < 2, m < 1; SOS_ERANGE when n^2 k or n m k reaches 2^31.              */
+int sos_net_query(sos_plan_t plan, int n, int m, size_t* state_bytes);
+
+/* d_W (N x k, the plan's W type) = net(At, Bt).  Asynchronous.          */
+int sos_net_weights(sos_plan_t plan, int n, int m, const float* d_At, const float* d_Bt, void* d_W,
+                    void* d_state, void* stream);
+
+/* L of W = net(At, Bt) (d_loss, device) and its gradient with respect to
+ * the weights: d_dBt (n m x k) and, unless d_dAt is NULL, d_dAt (n x m),
+ * FP32, by the chain rule through dL/dW = 4 R W (flags as for
+ * sos_loss_grad).  Asynchronous on stream.                                */
+int sos_net_grad(sos_plan_t plan, int n, int m, const float* d_At, const float* d_Bt, void* d_state,
+                 const double* d_p, double* d_loss, float* d_dAt, float* d_dBt, int flags, void* stream);
+
+/* One Adam step on the weights at iteration t (1-based): W = net(At, Bt),
+ * the plan's loss and dL/dW (flags: SOS_FLAG_EXACT_FORWARD,
+ * SOS_FLAG_SINGLE_BACKWARD as in sos_loss_grad), the chain rule to dL/dAt
+ * and dL/dBt (FP32 GEMMs), then Adam on Bt, and on At when train_first is
+ * nonzero (train_first = 0 keeps the first layer fixed, e.g. A = I).
+ * d_loss (device) receives L at the weights before the update.            */
+int sos_net_step(sos_plan_t plan, int n, int m, float* d_At, float* d_Bt, void* d_state, int64_t t,
+                 const double* d_p, const sos_adam_t* adam, double* d_loss, int flags, int train_first,
+                 void* stream);
+
+/* Adam on the weights from their current values until the FP64-verified
+ * relative residual of W = net(At, Bt) is <= opts->tol or opts->max_steps
+ * (uses tol, max_steps, check_every, ladder, switch_rel, lr_exact and
+ * single_backward of opts: the fast forward until rel <= switch_rel, then
+ * the exact forward with step size lr_exact).  The Adam moments are zeroed
+ * first.  h_res as for sos_solve (steps, exact_steps, the verified rel of the
+ * final weights).  Blocks until done.                                      */
+int sos_net_solve(sos_plan_t plan, int n, int m, float* d_At, float* d_Bt, void* d_state, const double* d_p,
+                  const sos_adam_t* adam, const sos_solve_opts_t* opts, int train_first, sos_result_t* h_res,
+                  void* stream);
+
 /* Kernel classes reported by sos_timing_read. */
 enum sos_kernel_class {
   SOS_K_PREP = 0,    /* operand copies / bf16 split of W                  */

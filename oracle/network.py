@@ -76,3 +76,38 @@ def network_factor(A: np.ndarray, B: np.ndarray) -> np.ndarray:
             row = int(idx.lookup(np.array([e]))[0])
             W[row] += blk @ A[:, c]
     return W
+
+
+def network_loss_grad(A: np.ndarray, B: np.ndarray, p: np.ndarray):
+    """L(A, B) = ||coeff(W W^T) - p||^2 for W = network_factor(A, B), and its
+    gradient with respect to A and B (Section 2's network trained as in
+    Section 3).  p is indexed like MonomialIndex(n, 4) (all monomials of
+    degree <= 4 in the n variables; a quartic form has zeros below degree 4).
+
+    Chain rule: column l of W holds f_l = sum_{a,c} P[l,a,c] x_a x_c with
+    P[l,a,c] = sum_b B[l, a m + b] A[b, c]; the row of x_a x_c receives
+    P[l,a,c] + P[l,c,a] (a != c) or P[l,a,a], so dL/dP[l,a,c] is the
+    gradient dL/dW = 4 R W at that row, for both orders of (a, c).
+    """
+    from .sos import loss_grad, pair_ranks
+    A = np.asarray(A, float)
+    B = np.asarray(B, float)
+    m, n = A.shape
+    k = B.shape[0]
+    W = network_factor(A, B)
+    L, gW, _ = loss_grad(W, p, n, 2, pair_ranks(n, 2))
+    idx = MonomialIndex(n, 2)
+    dP = np.zeros((k, n, n))
+    for a in range(n):
+        for c in range(n):
+            e = [0] * n
+            e[a] += 1
+            e[c] += 1
+            dP[:, a, c] = gW[int(idx.lookup(np.array([e]))[0])]
+    dB = np.zeros_like(B)
+    dA = np.zeros_like(A)
+    for a in range(n):
+        blk = B[:, a * m:(a + 1) * m]            # k x m
+        dB[:, a * m:(a + 1) * m] = dP[:, a, :] @ A.T
+        dA += blk.T @ dP[:, a, :]
+    return L, dA, dB

@@ -76,6 +76,12 @@ def _load():
         "sos_step_batch": (I, [ctypes.POINTER(P), ctypes.POINTER(V), ctypes.POINTER(V),
                                ctypes.POINTER(I64), ctypes.POINTER(V), ctypes.POINTER(_Adam), V, I, V]),
         "sos_loss_batch": (I, [ctypes.POINTER(P), ctypes.POINTER(V), ctypes.POINTER(V), V, I, V]),
+        "sos_net_query": (I, [P, I, I, ctypes.POINTER(ctypes.c_size_t)]),
+        "sos_net_weights": (I, [P, I, I, V, V, V, V, V]),
+        "sos_net_grad": (I, [P, I, I, V, V, V, V, V, V, V, I, V]),
+        "sos_net_step": (I, [P, I, I, V, V, V, I64, V, ctypes.POINTER(_Adam), V, I, I, V]),
+        "sos_net_solve": (I, [P, I, I, V, V, V, V, ctypes.POINTER(_Adam), ctypes.POINTER(_SolveOpts), I,
+                              ctypes.POINTER(_Result), V]),
         "sos_timing": (I, [P, I]),
         "sos_timing_read": (I, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]),
         "sos_last_error": (ctypes.c_char_p, []),
@@ -90,7 +96,8 @@ def _load():
 _lib = _load()
 EXPORTS = ("sos_plan", "sos_plan_query", "sos_plan_bind", "sos_plan_destroy", "sos_exponents",
            "sos_pair_ranks", "sos_loss_grad", "sos_step", "sos_solve", "sos_verify",
-           "sos_step_batch", "sos_loss_batch", "sos_timing", "sos_timing_read", "sos_last_error")
+           "sos_step_batch", "sos_loss_batch", "sos_net_query", "sos_net_weights", "sos_net_grad", "sos_net_step",
+           "sos_net_solve", "sos_timing", "sos_timing_read", "sos_last_error")
 KERNEL_CLASSES = ("prep", "init_r", "gram", "loss", "gather", "rw", "adam")
 
 
@@ -269,6 +276,61 @@ def loss_batch(plans, Ws, ps, losses, stream=None):
     Pv = (ctypes.c_void_p * n)(*[p.data_ptr() for p in ps])
     _check(_lib.sos_loss_batch(P, Wv, Pv, _ptr(losses), n, _stream(stream)))
     return losses
+
+
+class Net:
+    """The paper's two-layer network ||B Z A x||^2 for quartic forms in n
+    variables (Section 2): weights At = A^T (n x m) and Bt = B^T (n m x k),
+    FP32 on the device, trained through a plan (n - 1, 2) of rank k."""
+
+    def __init__(self, n: int, m: int, k: int, precision="bf16x3", At=None, Bt=None, device="cuda"):
+        self.n, self.m, self.k = n, m, k
+        self.plan = Plan(n - 1, 2, k, precision, device=device)
+        sz = ctypes.c_size_t()
+        _check(_lib.sos_net_query(self.plan._h, n, m, ctypes.byref(sz)))
+        self.state = torch.zeros(sz.value, dtype=torch.uint8, device=device)
+        f32 = dict(dtype=torch.float32, device=device)
+        self.At = torch.zeros((n, m), **f32) if At is None else At.to(**f32).contiguous()
+        self.Bt = torch.zeros((n * m, k), **f32) if Bt is None else Bt.to(**f32).contiguous()
+        if tuple(self.At.shape) != (n, m) or tuple(self.Bt.shape) != (n * m, k):
+            raise ValueError(f"At must be ({n}, {m}) and Bt ({n * m}, {k})")
+
+    def weights(self, stream=None):
+        W = torch.empty((self.plan.N, self.k), dtype=self.plan.wdtype, device=self.At.device)
+        _check(_lib.sos_net_weights(self.plan._h, self.n, self.m, _ptr(self.At), _ptr(self.Bt), _ptr(W),
+                                    _ptr(self.state), _stream(stream)))
+        return W
+
+    def grad(self, p, flags=0, want_dA=True, stream=None):
+        """(loss, dL/dAt or None, dL/dBt) at the current weights."""
+        self.plan._p(p)
+        loss = torch.empty(1, dtype=torch.float64, device=self.At.device)
+        dA = torch.empty_like(self.At) if want_dA else None
+        dB = torch.empty_like(self.Bt)
+        _check(_lib.sos_net_grad(self.plan._h, self.n, self.m, _ptr(self.At), _ptr(self.Bt), _ptr(self.state),
+                                 _ptr(p), _ptr(loss), _ptr(dA), _ptr(dB), int(flags), _stream(stream)))
+        return loss, dA, dB
+
+    def step(self, t, p, adam: Adam, loss=None, flags=0, train_first=True, stream=None):
+        self.plan._p(p)
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float64, device=self.At.device)
+        _check(_lib.sos_net_step(self.plan._h, self.n, self.m, _ptr(self.At), _ptr(self.Bt), _ptr(self.state),
+                                 int(t), _ptr(p), ctypes.byref(adam.c()), _ptr(loss), int(flags),
+                                 1 if train_first else 0, _stream(stream)))
+        return loss
+
+    def solve(self, p, adam: Adam, tol=1e-8, max_steps=10000, check_every=10, ladder=True, switch_rel=3e-6,
+              lr_exact=0.0, single_backward=True, train_first=True, stream=None):
+        self.plan._p(p)
+        opts = _SolveOpts(tol, max_steps, check_every, 1 if ladder else 0, 0, 0.0, switch_rel, lr_exact, 0.0,
+                          1 if single_backward else 0, 0, 0.0)
+        res = _Result()
+        _check(_lib.sos_net_solve(self.plan._h, self.n, self.m, _ptr(self.At), _ptr(self.Bt), _ptr(self.state),
+                                  _ptr(p), ctypes.byref(adam.c()), ctypes.byref(opts), 1 if train_first else 0,
+                                  ctypes.byref(res), _stream(stream)),
+               allow=(OK, NOT_CONVERGED))
+        return {f: getattr(res, f) for f, _ in _Result._fields_}
 
 
 class SosLoss(torch.autograd.Function):

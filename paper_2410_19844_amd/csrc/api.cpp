@@ -478,6 +478,216 @@ int sos_loss_batch(const sos_plan_t* plans, const void* const* d_W, const double
   return SOS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Two-layer network (Section 2): W = net(At, Bt), then the plan's path
+// ---------------------------------------------------------------------------
+
+namespace {
+struct NetLayout {
+  size_t rowpair, rowmap, mA, vA, mB, vB, W, P, gW, dA, dB, bytes;
+};
+
+NetLayout net_layout(const sos_plan_s* p, int n, int m) {
+  NetLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = (off + bytes + 255) / 256 * 256; return o; };
+  const size_t N = (size_t)p->N, k = (size_t)p->k, nm = (size_t)n * m;
+  const size_t we = p->prec == SOS_FP64 ? 8 : 4;  // W, P and dW in the plan's W type
+  L.rowpair = take(N * 4);
+  L.rowmap = take((size_t)n * n * 4);
+  L.mA = take(nm * 4);
+  L.vA = take(nm * 4);
+  L.mB = take(nm * k * 4);
+  L.vB = take(nm * k * 4);
+  L.W = take(N * k * we);
+  L.P = take((size_t)n * n * k * we);
+  L.gW = take(N * k * we);
+  L.dA = take(nm * 4);
+  L.dB = take(nm * k * 4);
+  L.bytes = off;
+  return L;
+}
+
+// plan (n - 1, 2); builds the row maps on first use
+int net_check(sos_plan_s* p, int n, int m, const char* fn) {
+  if (n < 2 || m < 1) return set_error(SOS_EINVAL, std::string(fn) + ": needs n >= 2 and m >= 1");
+  if (p->n != n - 1 || p->d != 2)
+    return set_error(SOS_EINVAL, std::string(fn) + ": quartic forms in n variables need a plan (n - 1, 2)");
+  if ((int64_t)n * n * p->k >= (int64_t(1) << 31) || (int64_t)n * m * p->k >= (int64_t(1) << 31))
+    return set_error(SOS_ERANGE, std::string(fn) + ": n^2 k and n m k must stay below 2^31");
+  if (p->net_rowpair.empty()) {
+    // basis row i is x_a x_c with the homogenising variable x_{n-1} filling the degree up to 2
+    p->net_rowpair.assign(p->N, 0);
+    p->net_rowmap.assign((size_t)n * n, 0);
+    for (int64_t i = 0; i < p->N; ++i) {
+      int v[2] = {n - 1, n - 1}, q = 0;
+      for (int u = 0; u < n - 1; ++u)
+        for (int e = 0; e < p->basis[i * (n - 1) + u]; ++e) v[q++] = u;
+      const int a = std::min(v[0], v[1]), c = std::max(v[0], v[1]);
+      p->net_rowpair[i] = a * n + c;
+      p->net_rowmap[(size_t)a * n + c] = p->net_rowmap[(size_t)c * n + a] = (int32_t)i;
+    }
+  }
+  return SOS_OK;
+}
+
+int net_upload_maps(sos_plan_s* p, char* st, const NetLayout& L, hipStream_t s) {
+  if (p->net_maps_at == st) return SOS_OK;
+  SOS_HIP(hipMemcpyAsync(st + L.rowpair, p->net_rowpair.data(), p->net_rowpair.size() * 4, hipMemcpyHostToDevice, s),
+          "net: row pairs");
+  SOS_HIP(hipMemcpyAsync(st + L.rowmap, p->net_rowmap.data(), p->net_rowmap.size() * 4, hipMemcpyHostToDevice, s),
+          "net: row map");
+  p->net_maps_at = st;
+  return SOS_OK;
+}
+
+int net_forward_W(sos_plan_s* p, int n, int m, const float* At, const float* Bt, char* st, const NetLayout& L,
+                  void* W, hipStream_t s) {
+  if (int rc = net_upload_maps(p, st, L, s)) return rc;
+  SOS_HIP(launch_net_forward(p->prec == SOS_FP64, n, m, p->k, (int)p->N, At, Bt, st + L.P,
+                             (const int32_t*)(st + L.rowpair), W, s), "net: forward");
+  return SOS_OK;
+}
+
+// L and dL/dAt (when dA != nullptr), dL/dBt of the weights
+int net_grad(sos_plan_s* p, int n, int m, const float* At, const float* Bt, char* st, const NetLayout& L,
+             const double* d_p, double* d_loss, int flags, float* dA, float* dB, hipStream_t s) {
+  void* W = st + L.W;
+  void* gW = st + L.gW;
+  if (int rc = net_forward_W(p, n, m, At, Bt, st, L, W, s)) return rc;
+  if (int rc = run_forward(p, W, d_p, flags, d_loss, true, s)) return rc;
+  if (int rc = run_backward(p, gW, (flags & SOS_FLAG_SINGLE_BACKWARD) == 0, s)) return rc;
+  SOS_HIP(launch_net_backward(p->prec == SOS_FP64, n, m, p->k, At, Bt, gW, (const int32_t*)(st + L.rowmap),
+                              st + L.P, dA, dB, dA != nullptr, s), "net: backward");
+  return SOS_OK;
+}
+
+int net_step(sos_plan_s* p, int n, int m, float* At, float* Bt, char* st, const NetLayout& L, int64_t t,
+             const double* d_p, const sos_adam_t& h, double* d_loss, int flags, bool train_first, hipStream_t s) {
+  float* dA = (float*)(st + L.dA);
+  float* dB = (float*)(st + L.dB);
+  if (int rc = net_grad(p, n, m, At, Bt, st, L, d_p, d_loss, flags, train_first ? dA : nullptr, dB, s)) return rc;
+  const int64_t nm = (int64_t)n * m;
+  if (train_first)
+    SOS_HIP(launch_adam_f32(At, (float*)(st + L.mA), (float*)(st + L.vA), dA, nm, t, h, s), "net: Adam A");
+  SOS_HIP(launch_adam_f32(Bt, (float*)(st + L.mB), (float*)(st + L.vB), dB, nm * p->k, t, h, s), "net: Adam B");
+  return SOS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int sos_net_query(sos_plan_t p, int n, int m, size_t* state_bytes) {
+  if (!p || !state_bytes) return set_error(SOS_EINVAL, "sos_net_query: NULL argument");
+  if (int rc = net_check(p, n, m, "sos_net_query")) return rc;
+  *state_bytes = net_layout(p, n, m).bytes;
+  return SOS_OK;
+}
+
+int sos_net_weights(sos_plan_t p, int n, int m, const float* d_At, const float* d_Bt, void* d_W, void* d_state,
+                    void* stream) {
+  if (int rc = check_bound(p, "sos_net_weights")) return rc;
+  if (int rc = net_check(p, n, m, "sos_net_weights")) return rc;
+  if (!d_At || !d_Bt || !d_W || !d_state) return set_error(SOS_EINVAL, "sos_net_weights: NULL argument");
+  return net_forward_W(p, n, m, d_At, d_Bt, (char*)d_state, net_layout(p, n, m), d_W, (hipStream_t)stream);
+}
+
+int sos_net_grad(sos_plan_t p, int n, int m, const float* d_At, const float* d_Bt, void* d_state, const double* d_p,
+                 double* d_loss, float* d_dAt, float* d_dBt, int flags, void* stream) {
+  if (int rc = check_bound(p, "sos_net_grad")) return rc;
+  if (int rc = net_check(p, n, m, "sos_net_grad")) return rc;
+  if (!d_At || !d_Bt || !d_state || !d_p || !d_loss || !d_dBt)
+    return set_error(SOS_EINVAL, "sos_net_grad: NULL argument");
+  if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_SINGLE_BACKWARD))
+    return set_error(SOS_EINVAL, "sos_net_grad: flags may be SOS_FLAG_EXACT_FORWARD | SOS_FLAG_SINGLE_BACKWARD");
+  return net_grad(p, n, m, d_At, d_Bt, (char*)d_state, net_layout(p, n, m), d_p, d_loss, flags, d_dAt, d_dBt,
+                  (hipStream_t)stream);
+}
+
+int sos_net_step(sos_plan_t p, int n, int m, float* d_At, float* d_Bt, void* d_state, int64_t t, const double* d_p,
+                 const sos_adam_t* adam, double* d_loss, int flags, int train_first, void* stream) {
+  if (int rc = check_bound(p, "sos_net_step")) return rc;
+  if (int rc = net_check(p, n, m, "sos_net_step")) return rc;
+  if (int rc = check_adam(adam, "sos_net_step")) return rc;
+  if (!d_At || !d_Bt || !d_state || !d_p || !d_loss) return set_error(SOS_EINVAL, "sos_net_step: NULL argument");
+  if (t < 1) return set_error(SOS_EINVAL, "sos_net_step: t is 1-based");
+  if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_SINGLE_BACKWARD))
+    return set_error(SOS_EINVAL, "sos_net_step: flags may be SOS_FLAG_EXACT_FORWARD | SOS_FLAG_SINGLE_BACKWARD");
+  return net_step(p, n, m, d_At, d_Bt, (char*)d_state, net_layout(p, n, m), t, d_p, *adam, d_loss, flags,
+                  train_first != 0, (hipStream_t)stream);
+}
+
+int sos_net_solve(sos_plan_t p, int n, int m, float* d_At, float* d_Bt, void* d_state, const double* d_p,
+                  const sos_adam_t* adam, const sos_solve_opts_t* o, int train_first, sos_result_t* res,
+                  void* stream) {
+  if (int rc = check_bound(p, "sos_net_solve")) return rc;
+  if (int rc = net_check(p, n, m, "sos_net_solve")) return rc;
+  if (int rc = check_adam(adam, "sos_net_solve")) return rc;
+  if (!d_At || !d_Bt || !d_state || !d_p || !o || !res) return set_error(SOS_EINVAL, "sos_net_solve: NULL argument");
+  if (o->max_steps < 0 || o->check_every < 1 || !(o->tol >= 0) || !(o->lr_exact >= 0))
+    return set_error(SOS_EINVAL, "sos_net_solve: needs max_steps >= 0, check_every >= 1, tol and lr_exact >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  std::memset(res, 0, sizeof(*res));
+  const NetLayout L = net_layout(p, n, m);
+  char* st = (char*)d_state;
+  SOS_HIP(hipMemsetAsync(st + L.mA, 0, L.mB - L.mA, s), "sos_net_solve: zero moments of A");
+  SOS_HIP(hipMemsetAsync(st + L.mB, 0, L.W - L.mB, s), "sos_net_solve: zero moments of B");
+  double* sc = scal(p);
+  SOS_HIP(launch_sumsq(p, d_p, p->M, sc + 1, s), "sos_net_solve: ||p||");
+  double pn2 = 0;
+  SOS_HIP(hipMemcpyAsync(&pn2, sc + 1, 8, hipMemcpyDeviceToHost, s), "sos_net_solve: readback");
+  SOS_HIP(hipStreamSynchronize(s), "sos_net_solve");
+  const double pnorm = pn2 > 0 ? std::sqrt(pn2) : 1.0;
+  sos_adam_t h = *adam;
+  const bool can_ladder = o->ladder != 0;
+  int phase = 0;
+  int64_t t = 0, exact_steps = 0;
+  double loss = 0, best = std::numeric_limits<double>::infinity();
+  bool done = false;
+  while (t < o->max_steps && !done) {
+    ++t;
+    const int flags = (phase ? SOS_FLAG_EXACT_FORWARD : 0) | (o->single_backward ? SOS_FLAG_SINGLE_BACKWARD : 0);
+    if (int rc = net_step(p, n, m, d_At, d_Bt, st, L, t, d_p, h, sc + 0, flags, train_first != 0, s)) return rc;
+    if (phase) ++exact_steps;
+    if (t % o->check_every && t != o->max_steps) continue;
+    SOS_HIP(hipMemcpyAsync(&loss, sc + 0, 8, hipMemcpyDeviceToHost, s), "sos_net_solve: loss");
+    SOS_HIP(hipStreamSynchronize(s), "sos_net_solve");
+    const double rel = std::sqrt(std::max(loss, 0.0)) / pnorm;
+    if (!std::isfinite(rel)) return set_error(SOS_ENUMERIC, "sos_net_solve: loss is not finite");
+    best = std::min(best, rel);
+    if (can_ladder && phase == 0 && rel <= o->switch_rel) {
+      phase = 1;
+      if (o->lr_exact > 0) h.lr = o->lr_exact;
+    }
+    if (rel <= o->tol) {
+      // certify the current weights: W = net(A, B), FP64 forward
+      void* W = st + L.W;
+      if (int rc = net_forward_W(p, n, m, d_At, d_Bt, st, L, W, s)) return rc;
+      double vrel = 0;
+      if (int rc = sos_verify(p, W, d_p, &vrel, nullptr, stream)) return rc;
+      if (vrel <= o->tol) done = true;
+      else if (can_ladder && phase == 0) {
+        phase = 1;
+        if (o->lr_exact > 0) h.lr = o->lr_exact;
+      }
+    }
+  }
+  void* W = st + L.W;
+  if (int rc = net_forward_W(p, n, m, d_At, d_Bt, st, L, W, s)) return rc;
+  double vrel = 0;
+  if (int rc = sos_verify(p, W, d_p, &vrel, nullptr, stream)) return rc;
+  res->steps = t;
+  res->exact_steps = exact_steps;
+  res->loss = loss;
+  res->rel = vrel;
+  res->best_rel = best;
+  res->phase = phase ? 2 : 0;
+  res->status = vrel <= o->tol ? SOS_OK : SOS_NOT_CONVERGED;
+  return res->status;
+}
+
+}  // extern "C"
+
 const char* sos_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"

@@ -685,6 +685,14 @@ hipError_t launch_rw(const sos_plan_s* p, void* g, bool split, hipStream_t s) {
   return launch_rw_bf3(p, g, split, s);
 }
 
+hipError_t launch_adam_f32(float* W, float* m, float* v, const float* g, int64_t n, int64_t t,
+                           const sos_adam_t& h, hipStream_t s) {
+  const double bc1 = 1.0 - pow(h.beta1, (double)t), bc2 = 1.0 - pow(h.beta2, (double)t);
+  k_adam<float><<<grid_for(n), 256, 0, s>>>(W, m, v, g, n, (float)h.lr, (float)h.beta1, (float)h.beta2,
+                                            (float)h.eps, (float)bc1, (float)bc2);
+  return hipGetLastError();
+}
+
 hipError_t launch_adam(const sos_plan_s* p, void* W, void* m, void* v, const void* g, int64_t t,
                        const sos_adam_t& h, hipStream_t s) {
   const int64_t n = p->N * (int64_t)p->k;

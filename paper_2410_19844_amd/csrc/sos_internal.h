@@ -182,6 +182,10 @@ struct sos_plan_s {
   int copies_mode = 0;
   int t_cur = 0;                   // transposed copy for the next backward: 0 = t_hi, 1 = t_lo
   std::vector<int32_t> pair_off, pair_idx, pair_pos, rank_map;
+  // two-layer network (plans (n - 1, 2)): basis row <-> variable pair maps,
+  // built on first use; net_maps_at = the state buffer they were uploaded to
+  std::vector<int32_t> net_rowpair, net_rowmap;
+  const void* net_maps_at = nullptr;
   size_t state_bytes = 0;
   char* ws = nullptr;
   size_t ws_size = 0;
@@ -247,6 +251,15 @@ hipError_t launch_adam(const sos_plan_s* p, void* W, void* m, void* v, const voi
 // single-product backward with Adam and the next step's copies in the epilogue
 hipError_t launch_rw_adam_bf3(const sos_plan_s* p, void* W, void* m, void* v, int64_t t, const sos_adam_t& h,
                               bool exact_next, hipStream_t s);
+// two-layer network (net.hip)
+// fp64: P, W and dW are double (FP64 plans), else float
+hipError_t launch_net_forward(bool fp64, int n, int m, int k, int N, const float* At, const float* Bt, void* P,
+                              const int32_t* rowpair, void* W, hipStream_t s);
+hipError_t launch_net_backward(bool fp64, int n, int m, int k, const float* At, const float* Bt, const void* dW,
+                               const int32_t* rowmap, void* dP, float* dAt, float* dBt, bool want_dAt,
+                               hipStream_t s);
+hipError_t launch_adam_f32(float* W, float* m, float* v, const float* g, int64_t n, int64_t t,
+                           const sos_adam_t& h, hipStream_t s);
 // grouped serving kernels (batch.hip); at most batch_capacity() problems per call
 int batch_capacity();
 hipError_t launch_step_group(sos_plan_s* const* plans, void* const* W, void* const* state, const int64_t* t,

@@ -1,0 +1,118 @@
+"""The two-layer network ||B Z A x||^2 (Section 2) through the C ABI, against
+the FP64 oracle: the factor W = net(A, B), the quartic's coefficients (by the
+paper's pairing identities, an independent route), the gradient with respect
+to A and B, and a solve to an FP64-verified relative residual.
+
+Quartic forms in n variables are compared with the library's plan (n - 1, 2)
+through dehomogenisation (x_n = 1), a bijection between the forms' monomials
+and the plan's; the maps are built from the oracle's own indexes.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle.sos import MonomialIndex
+
+torch = pytest.importorskip("torch")
+S = pytest.importorskip("paper_2410_19844_amd")
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def dehom_maps(n):
+    """Positions, in the oracle's n-variable indexes, of the plan (n-1, 2)'s
+    basis rows (degree-2 forms) and coefficients (degree-4 forms)."""
+    b = O.monomials(n - 1, 2)
+    c = O.monomials(n - 1, 4)
+    rows = MonomialIndex(n, 2).lookup(np.hstack([b, (2 - b.sum(1))[:, None]]))
+    cols = MonomialIndex(n, 4).lookup(np.hstack([c, (4 - c.sum(1))[:, None]]))
+    assert (rows >= 0).all() and (cols >= 0).all()
+    return rows, cols
+
+
+def make_net(n, m, k, seed, prec="fp32", scale=0.5):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((m, n)) * scale
+    B = rng.standard_normal((k, n * m)) * scale / math.sqrt(n * m)
+    At = torch.tensor(A.T.copy(), dtype=torch.float32, device="cuda")
+    Bt = torch.tensor(B.T.copy(), dtype=torch.float32, device="cuda")
+    net = S.Net(n, m, k, prec, At=At, Bt=Bt)
+    # the weights exactly as the GPU holds them
+    A32 = net.At.double().cpu().numpy().T
+    B32 = net.Bt.double().cpu().numpy().T
+    return net, A32, B32
+
+
+@pytest.mark.parametrize("n,m,k", [(3, 3, 4), (5, 7, 9), (8, 11, 30)])
+def test_net_weights_and_coefficients(n, m, k):
+    net, A, B = make_net(n, m, k, seed=n)
+    rows, cols = dehom_maps(n)
+    W = net.weights().double().cpu().numpy()
+    W_o = O.network_factor(A, B)[rows]
+    Wabs = O.network_factor(np.abs(A), np.abs(B))[rows]
+    assert np.all(np.abs(W - W_o) <= (2 * m + 2) * U32 * Wabs + 1e-30)
+    # coefficients of ||f||^2 by the pairing identities (no Gram matrix) vs the plan's exact forward of W
+    coef = O.network_quartic_coefficients(A, B)
+    cexp = MonomialIndex(n, 4).exps
+    c_o = np.array([coef.get(tuple(int(v) for v in cexp[j]), 0.0) for j in cols])
+    zeros = torch.zeros(net.plan.M, dtype=torch.float64, device="cuda")
+    _, _, r = net.plan.loss_grad(net.weights(), zeros, grad=False, want_r=True, exact=True)
+    c = r.cpu().numpy()
+    # W is FP32 on the GPU (|dW| <= (2m+2) u Wabs), so |dc| <= 2 (2m+2) u coeff(Wabs Wabs^T)
+    cabs = O.coefficients(Wabs, n - 1, 2)
+    assert np.all(np.abs(c - c_o) <= 2 * (2 * m + 2) * U32 * cabs + 1e-12 * np.abs(c_o).max())
+
+
+@pytest.mark.parametrize("prec,flags", [("fp32", 0), ("bf16x3", 0), ("bf16x3", 1), ("fp64", 0)])
+def test_net_gradient_matches_oracle(prec, flags):
+    n, m, k = 5, 6, 15
+    net, A, B = make_net(n, m, k, seed=21, prec=prec)
+    rows, cols = dehom_maps(n)
+    p_o = np.zeros(len(MonomialIndex(n, 4)))
+    p_o[cols] = np.random.default_rng(22).standard_normal(len(cols))
+    pd = torch.tensor(p_o[cols], dtype=torch.float64, device="cuda")
+    fl = S.FLAG_EXACT_FORWARD if flags else 0
+    L, dA, dB = net.grad(pd, flags=fl)
+    L_o, dA_o, dB_o = O.network_loss_grad(A, B, p_o)
+    # FP32 weights and W (rounding ~1e-7), FP32 or split-bf16 (~2^-16 per term) contractions
+    tol_L = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-5 if flags else 1e-3}[prec]
+    tol_g = {"fp64": 1e-6, "fp32": 1e-4, "bf16x3": 1e-3}[prec]
+    assert abs(L.item() - L_o) <= tol_L * L_o
+    gA = dA.double().cpu().numpy().T
+    gB = dB.double().cpu().numpy().T
+    assert np.linalg.norm(gA - dA_o) <= tol_g * np.linalg.norm(dA_o)
+    assert np.linalg.norm(gB - dB_o) <= tol_g * np.linalg.norm(dB_o)
+
+
+@pytest.mark.parametrize("train_first", [True, False])
+def test_net_solve_certifies(train_first):
+    """p from a random network; train from another start to FP64-verified 1e-8
+    (FP64 plan: W formed in FP64 from the FP32 weights).  With train_first =
+    False the first layer stays A = I (m = n)."""
+    n, m, k = 6, 6, 21
+    rng = np.random.default_rng(0)
+    A0 = rng.uniform(-1, 1, (m, n))
+    B0 = rng.uniform(-1, 1, (k, n * m)) / math.sqrt(n * m)
+    rows, cols = dehom_maps(n)
+    p_o = O.coefficients(O.network_factor(A0, B0), n, 2)
+    pd = torch.tensor(p_o[cols], dtype=torch.float64, device="cuda")
+    if train_first:
+        net, _, _ = make_net(n, m, k, seed=5, prec="fp64", scale=0.3)
+    else:
+        net, _, _ = make_net(n, m, k, seed=5, prec="fp64", scale=0.3)
+        net.At.copy_(torch.eye(n, m, dtype=torch.float32, device="cuda"))
+    res = net.solve(pd, S.Adam(lr=3e-3), tol=1e-8, max_steps=12000, check_every=50, ladder=False,
+                    single_backward=False, train_first=train_first)
+    assert res["status"] == S.OK, res
+    # the oracle's own check of the returned weights
+    A = net.At.double().cpu().numpy().T
+    B = net.Bt.double().cpu().numpy().T
+    if not train_first:
+        assert np.array_equal(A, np.eye(m, n))
+    W = O.network_factor(A, B)
+    rel = np.linalg.norm(O.coefficients(W, n, 2) - p_o) / np.linalg.norm(p_o)
+    assert rel <= 1e-8, rel

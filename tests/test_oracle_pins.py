@@ -311,3 +311,28 @@ def test_sparse_evaluation_identity_many_variables():
         lhs = float(c @ xb)
         rhs = float(np.sum((W.T @ m) ** 2))
         assert abs(lhs - rhs) <= 1e-12 * (np.abs(c) @ np.abs(xb))
+
+
+def test_network_gradient_matches_finite_differences():
+    """dL/dA and dL/dB of the two-layer network (chain rule through 4 R W)
+    against Richardson central differences (L is a polynomial in each weight)."""
+    from oracle.sos import MonomialIndex
+    n, m, k = 3, 4, 5
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((m, n)) * 0.5
+    B = rng.standard_normal((k, n * m)) * 0.5
+    p = rng.standard_normal(len(MonomialIndex(n, 4)))
+    L, dA, dB = O.network_loss_grad(A, B, p)
+
+    def fd(M, i, j):
+        def Lat(h):
+            M2 = M.copy()
+            M2[i, j] += h
+            args = (M2, B) if M is A else (A, M2)
+            return O.network_loss_grad(*args, p)[0]
+        D = lambda h: (Lat(h) - Lat(-h)) / (2 * h)
+        return (4 * D(1e-4) - D(2e-4)) / 3
+    for (i, j) in [(0, 0), (3, 2), (1, 1)]:
+        assert abs(fd(A, i, j) - dA[i, j]) <= 1e-6 * max(1.0, abs(dA[i, j]))
+    for (i, j) in [(0, 0), (4, 11), (2, 5)]:
+        assert abs(fd(B, i, j) - dB[i, j]) <= 1e-6 * max(1.0, abs(dB[i, j]))
