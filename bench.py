@@ -49,7 +49,13 @@ def parse():
     ap.add_argument("--exact", action="store_true", help="FP64 forward (the finishing phase)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=1024)
-    ap.add_argument("--mode", default="step", choices=["step", "ttt", "serve"])
+    ap.add_argument("--mode", default="step", choices=["step", "ttt", "serve", "net"])
+    ap.add_argument("--net-n", type=int, default=30, help="net: variables of the quartic forms")
+    ap.add_argument("--net-case", choices=("one", "many", "uniform"), default="one",
+                    help="net: one x_i^4 coefficient set to --net-big, every x_i^4 and x_i^2 x_j^2 raised by "
+                         "U[0, --net-big], or no perturbation")
+    ap.add_argument("--net-big", type=float, default=1e4,
+                    help="net: the size of the perturbation in the paper's units (before the 1/N scaling)")
     ap.add_argument("--requests", type=int, default=4096, help="serve: requests in the stream")
     ap.add_argument("--slots", type=int, default=48, help="serve: requests on the device at once")
     ap.add_argument("--hbm-budget-gib", type=float, default=32.0, help="serve: device memory for active requests")
@@ -216,6 +222,77 @@ def serve_mode(a, S, torch):
     print(json.dumps(out), flush=True)
 
 
+def net_mode(a, S, torch):
+    """Section 3.3: the first layer of the network on non-uniform coefficients.
+
+    Quartic forms in n variables, p = m_2^T B0 B0^T m_2 with B0 uniform (N x N,
+    scaled by 1/sqrt(N) as in the q100 workload, so the paper's unscaled
+    coefficients are divided by N), then perturbed:
+      one      the coefficient of x_i^4, for a seeded random i, set to big / N;
+      many     every x_i^4 and x_i^2 x_j^2 coefficient raised by U[0, big] / N;
+      uniform  no change.
+    The network ||B Z A x||^2 (k = N) is trained by Adam from a seeded random
+    start to an FP64-verified relative residual of tol, three ways: A = I
+    fixed (m = n), A general (m = n, trained), A of size 2n x n (trained).
+    FP64 plan: W = net(A, B) is formed from exact products.  Reported: the
+    time, the steps, the final verified residual and the smallest residual
+    seen at a check (the paper's measure of success is the minimal error).
+    """
+    import numpy as np
+
+    from workloads import uniform
+    n = a.net_n
+    dev = torch.device("cuda")
+    plan0 = S.Plan(n - 1, 2, 1, "fp32", device="cpu")
+    N = plan0.N
+    ex = plan0.exponents(1).astype(np.int64)                  # coefficient monomials of the plan (n - 1, 2)
+    ex = np.hstack([ex, 4 - ex.sum(1, keepdims=True)])        # as quartic forms in n variables (x_n = 1)
+    B0 = torch.tensor(uniform((N, N), 0, -N ** -0.5, N ** -0.5), dtype=torch.float32, device=dev)
+    pl0 = S.Plan(n - 1, 2, N, "fp32")
+    zeros = torch.zeros(pl0.M, dtype=torch.float64, device=dev)
+    _, _, p = pl0.loss_grad(B0, zeros, grad=False, want_r=True, exact=True)
+    del pl0, B0
+    rng = np.random.default_rng(12)
+    if a.net_case == "one":
+        i = int(rng.integers(n))
+        pos = np.flatnonzero(ex[:, i] == 4)
+        p[torch.as_tensor(pos, device=dev)] = a.net_big / N
+        what = f"c(x_{i + 1}^4) = {a.net_big:g}/N"
+    elif a.net_case == "many":
+        pos = np.flatnonzero((ex == 4).any(1) | ((ex == 2).sum(1) == 2))
+        add = rng.uniform(0, a.net_big, len(pos)) / N
+        p[torch.as_tensor(pos, device=dev)] += torch.as_tensor(add, device=dev)
+        what = f"c(x_i^4), c(x_i^2 x_j^2) += U[0, {a.net_big:g}]/N"
+    else:
+        what = "uniform coefficients"
+    lr = a.lr if a.lr is not None else 3e-3
+    out = {}
+    for label, m, train_first in (("A=I", n, False), ("A general", n, True), ("A 2n x n", 2 * n, True)):
+        Bt = torch.tensor(uniform((n * m, N), 1, -N ** -0.5, N ** -0.5), dtype=torch.float32, device=dev)
+        if train_first:
+            # entries of variance 1/m, so that P = A^T B has the scale it has for A = I
+            At = torch.tensor(uniform((n, m), 2, -(3 / m) ** 0.5, (3 / m) ** 0.5), dtype=torch.float32,
+                              device=dev)
+        else:
+            At = torch.eye(n, m, dtype=torch.float32, device=dev)
+        net = S.Net(n, m, N, "fp64", At=At, Bt=Bt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = net.solve(p, S.Adam(lr=lr), tol=a.tol, max_steps=a.max_steps, check_every=50, ladder=False,
+                        single_backward=False, train_first=train_first)
+        torch.cuda.synchronize()
+        out[label] = {"seconds": round(time.perf_counter() - t0, 3), "steps": res["steps"], "rel": res["rel"],
+                      "best_rel": res["best_rel"],
+                      "status": "certified" if res["status"] == 0 else "not certified"}
+        del net
+    print(json.dumps({"metric": f"network time-to-rel-residual {a.tol:g}, quartic forms in {n} variables",
+                      "unit": "s", "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": f"forms n={n}: plan ({n - 1}, 2) N={N}, network k={N}, "
+                                             f"p = m_2^T B0 B0^T m_2 (B0 uniform), {what}",
+                                 "precision": "fp64", "lr": lr, "max_steps": a.max_steps},
+                      "results": out}), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -227,6 +304,9 @@ def main():
 
     if a.mode == "serve":
         serve_mode(a, S, torch)
+        return
+    if a.mode == "net":
+        net_mode(a, S, torch)
         return
     c, W, p = make_inputs(S, torch, a.workload, a.precision, a.rank)
     pl = S.Plan(c.n, c.d, c.rank, a.precision)

@@ -484,7 +484,7 @@ int sos_loss_batch(const sos_plan_t* plans, const void* const* d_W, const double
 
 namespace {
 struct NetLayout {
-  size_t rowpair, rowmap, mA, vA, mB, vB, W, P, gW, dA, dB, bytes;
+  size_t rowpair, rowmap, mA, vA, mB, vB, W, P, gW, dA, dB, dAz, bytes;
 };
 
 NetLayout net_layout(const sos_plan_s* p, int n, int m) {
@@ -504,6 +504,7 @@ NetLayout net_layout(const sos_plan_s* p, int n, int m) {
   L.gW = take(N * k * we);
   L.dA = take(nm * 4);
   L.dB = take(nm * k * 4);
+  L.dAz = take((size_t)n * nm * we);
   L.bytes = off;
   return L;
 }
@@ -558,7 +559,7 @@ int net_grad(sos_plan_s* p, int n, int m, const float* At, const float* Bt, char
   if (int rc = run_forward(p, W, d_p, flags, d_loss, true, s)) return rc;
   if (int rc = run_backward(p, gW, (flags & SOS_FLAG_SINGLE_BACKWARD) == 0, s)) return rc;
   SOS_HIP(launch_net_backward(p->prec == SOS_FP64, n, m, p->k, At, Bt, gW, (const int32_t*)(st + L.rowmap),
-                              st + L.P, dA, dB, dA != nullptr, s), "net: backward");
+                              st + L.P, dA, dB, st + L.dAz, dA != nullptr, s), "net: backward");
   return SOS_OK;
 }
 

@@ -127,6 +127,16 @@ static hipError_t gemm(const GemmArgs<TA, TB, TC>& g, hipStream_t s) {
   return hipGetLastError();
 }
 
+// out[i] = sum over z of part[z * len + i], in z order
+template <class T>
+__global__ void k_sum_z(const T* __restrict__ part, int Z, int64_t len, float* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x) {
+    T acc = part[i];
+    for (int z = 1; z < Z; ++z) acc += part[z * len + i];
+    out[i] = (float)acc;
+  }
+}
+
 static int grid_for(int64_t n) {
   int64_t b = (n + 255) / 256;
   return (int)(b < 1 ? 1 : (b > 65536 ? 65536 : b));
@@ -151,10 +161,12 @@ static hipError_t net_forward(int n, int m, int k, int N, const float* At, const
 }
 
 // dP from dW; dBt_a = At^T dP_a; dAt = sum_a dP_a Bt_a^T (FP32 results,
-// accumulated in T).  dP may alias P.
+// accumulated in T; the n products dP_a Bt_a^T go to dAz, n x n x m of T,
+// and are summed in a order).  dP may alias P.
 template <class T>
 static hipError_t net_backward(int n, int m, int k, const float* At, const float* Bt, const T* dW,
-                               const int32_t* rowmap, T* dP, float* dAt, float* dBt, bool want_dAt, hipStream_t s) {
+                               const int32_t* rowmap, T* dP, float* dAt, float* dBt, T* dAz, bool want_dAt,
+                               hipStream_t s) {
   net::k_net_gather<T><<<net::grid_for((int64_t)n * n * k), 256, 0, s>>>(dW, rowmap, n, k, dP);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -165,12 +177,15 @@ static hipError_t net_backward(int n, int m, int k, const float* At, const float
   g.M = m; g.N = k; g.K = n; g.Z = n;
   e = net::gemm<T>(g, s);
   if (e != hipSuccess || !want_dAt) return e;
-  net::GemmArgs<T, float, float> h = {};
+  net::GemmArgs<T, float, T> h = {};
   h.A = dP; h.sAm = k; h.sAk = 1; h.zA = (int64_t)n * k;          // dP_a: (c, l)
   h.B = Bt; h.sBk = 1; h.sBn = k; h.zB = (int64_t)m * k;          // Bt_a^T: element (l, b) = Bt[a m + b, l]
-  h.C = dAt; h.sCm = m; h.sCn = 1;
-  h.M = n; h.N = m; h.K = k; h.Z = n; h.reduce_z = 1;
-  return net::gemm<T>(h, s);
+  h.C = dAz; h.sCm = m; h.sCn = 1; h.zC = (int64_t)n * m;
+  h.M = n; h.N = m; h.K = k; h.Z = n;
+  e = net::gemm<T>(h, s);
+  if (e != hipSuccess) return e;
+  net::k_sum_z<T><<<net::grid_for((int64_t)n * m), 256, 0, s>>>(dAz, n, (int64_t)n * m, dAt);
+  return hipGetLastError();
 }
 
 hipError_t launch_net_forward(bool fp64, int n, int m, int k, int N, const float* At, const float* Bt, void* P,
@@ -180,10 +195,12 @@ hipError_t launch_net_forward(bool fp64, int n, int m, int k, int N, const float
 }
 
 hipError_t launch_net_backward(bool fp64, int n, int m, int k, const float* At, const float* Bt, const void* dW,
-                               const int32_t* rowmap, void* dP, float* dAt, float* dBt, bool want_dAt,
+                               const int32_t* rowmap, void* dP, float* dAt, float* dBt, void* dAz, bool want_dAt,
                                hipStream_t s) {
-  return fp64 ? net_backward<double>(n, m, k, At, Bt, (const double*)dW, rowmap, (double*)dP, dAt, dBt, want_dAt, s)
-              : net_backward<float>(n, m, k, At, Bt, (const float*)dW, rowmap, (float*)dP, dAt, dBt, want_dAt, s);
+  return fp64 ? net_backward<double>(n, m, k, At, Bt, (const double*)dW, rowmap, (double*)dP, dAt, dBt,
+                                     (double*)dAz, want_dAt, s)
+              : net_backward<float>(n, m, k, At, Bt, (const float*)dW, rowmap, (float*)dP, dAt, dBt, (float*)dAz,
+                                    want_dAt, s);
 }
 
 }  // namespace sos

@@ -256,7 +256,7 @@ hipError_t launch_rw_adam_bf3(const sos_plan_s* p, void* W, void* m, void* v, in
 hipError_t launch_net_forward(bool fp64, int n, int m, int k, int N, const float* At, const float* Bt, void* P,
                               const int32_t* rowpair, void* W, hipStream_t s);
 hipError_t launch_net_backward(bool fp64, int n, int m, int k, const float* At, const float* Bt, const void* dW,
-                               const int32_t* rowmap, void* dP, float* dAt, float* dBt, bool want_dAt,
+                               const int32_t* rowmap, void* dP, float* dAt, float* dBt, void* dAz, bool want_dAt,
                                hipStream_t s);
 hipError_t launch_adam_f32(float* W, float* m, float* v, const float* g, int64_t n, int64_t t,
                            const sos_adam_t& h, hipStream_t s);

@@ -116,3 +116,34 @@ def test_net_solve_certifies(train_first):
     W = O.network_factor(A, B)
     rel = np.linalg.norm(O.coefficients(W, n, 2) - p_o) / np.linalg.norm(p_o)
     assert rel <= 1e-8, rel
+
+
+@pytest.mark.parametrize("mult", [1, 2])
+def test_net_first_layer_many_perturbed_coefficients(mult):
+    """Section 3.3's second experiment at n = 10: uniform-coefficient quartic
+    forms (B0 uniform) with every x_i^4 and x_i^2 x_j^2 coefficient raised by
+    U[0, 1e4] (divided by N, as B0 is scaled by 1/sqrt(N)).  A trained first
+    layer of size n x n or 2n x n reaches an FP64-verified 1e-8 from a random
+    start; the oracle re-checks the returned weights."""
+    n = 10
+    m = mult * n
+    rows, cols = dehom_maps(n)
+    N = len(rows)                                   # quadratic forms in n variables
+    rng = np.random.default_rng(3)
+    W0 = np.zeros((len(MonomialIndex(n, 2)), N))
+    W0[rows] = rng.uniform(-1, 1, (N, N)) / math.sqrt(N)
+    p_o = O.coefficients(W0, n, 2)
+    ex = MonomialIndex(n, 4).exps
+    hit = (ex.sum(1) == 4) & ((ex == 4).any(1) | ((ex == 2).sum(1) == 2))
+    p_o[hit] += rng.uniform(0, 1e4, int(hit.sum())) / N
+    pd = torch.tensor(p_o[cols], dtype=torch.float64, device="cuda")
+    At = torch.tensor(rng.uniform(-1, 1, (n, m)) * math.sqrt(3 / m), dtype=torch.float32, device="cuda")
+    Bt = torch.tensor(rng.uniform(-1, 1, (n * m, N)) / math.sqrt(N), dtype=torch.float32, device="cuda")
+    net = S.Net(n, m, N, "fp64", At=At, Bt=Bt)
+    res = net.solve(pd, S.Adam(lr=3e-3), tol=1e-8, max_steps=20000, check_every=50, ladder=False,
+                    single_backward=False, train_first=True)
+    assert res["status"] == S.OK, res
+    A = net.At.double().cpu().numpy().T
+    B = net.Bt.double().cpu().numpy().T
+    rel = np.linalg.norm(O.coefficients(O.network_factor(A, B), n, 2) - p_o) / np.linalg.norm(p_o)
+    assert rel <= 1e-8, rel
