@@ -183,7 +183,7 @@ def serve_mode(a, S, torch):
     import dataclasses
     reqs = serve_requests(S, torch, a.requests)
     mk = lambda: serve.Server(hbm_budget=int(a.hbm_budget_gib * (1 << 30)), max_active=a.slots,
-                              check_every=50, tol=1e-6, max_steps=20000, stall_checks=20, stall_ratio=0.5)
+                              check_every=50, tol=1e-6, max_steps=20000, stall_checks=10, stall_ratio=0.5)
     at0 = lambda rs: [dataclasses.replace(r, arrival=0.0) for r in rs]
     mk().run(at0(reqs[:min(len(reqs), 2 * a.slots)]))        # warm-up: kernels loaded, pools grown
     torch.cuda.synchronize()
@@ -212,7 +212,7 @@ def serve_mode(a, S, torch):
            "dtype": "fp32+fp64-forward", "data": "synthetic",
            "config": {"workload": f"serving stream: {len(reqs)} requests (seed 12345), {labels}",
                       "slots": a.slots, "hbm_budget_gib": a.hbm_budget_gib, "check_every": 50,
-                      "max_steps": 20000, "stall": "20 checks without halving", "lr": 3e-2},
+                      "max_steps": 20000, "stall": "10 checks without halving", "lr": 3e-2},
            "closed_loop": {"solves_per_s": sat, "wall_s": wall, "grouped_steps": srv.iterations * 50,
                            "request_steps": int(steps.sum()), "peak_active": srv.peak_active,
                            "peak_bytes": srv.peak_bytes, "verdicts": verdicts},

@@ -456,59 +456,113 @@ __global__ __launch_bounds__(256) void k_gather(RankTab rk, const double* __rest
   }
 }
 
-// Gather of R for FP32 and split plans, 8 consecutive columns j per thread:
-// one 16-byte store per array (bf16) or two (FP32), the row's code loaded
-// once.  r32 is the FP32 copy of r: R is rounded to FP32 first in every one
-// of these modes, so reading the copy gives the same bits as reading r.
-// Mode 1 = FP32 row-major, 2 = bf16 hi and lo (blocked), 3 = bf16 hi only.
+// Offset of R(i, j) in the gather's output layout, and a 16-value store.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_gather8(RankTab rk, const float* __restrict__ r32, int N, int64_t Np,
-                                                 int64_t ld, void* R_hi, void* R_lo) {
-  const int64_t total8 = Np * ld / 8;
-  const int64_t nkb = ld / kBlkK;
-  const int64_t ps = panel_stride(nkb, 2);
-  for (int64_t e8 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e8 < total8;
-       e8 += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t e = e8 * 8;
-    int i, j0;
-    int64_t o;
-    if (MODE >= 2) {  // e walks the blocks of the panel-blocked layout in order (see blk_off)
-      const int64_t blk = e / (kBlkRows * kBlkK), in = e % (kBlkRows * kBlkK);
-      i = (int)((blk / nkb) * kBlkRows + in / kBlkK);
-      j0 = (int)((blk % nkb) * kBlkK + in % kBlkK);
-      o = blk_off(i, j0, ps);
-    } else {
-      i = (int)(e / ld);
-      j0 = (int)(e % ld);
-      o = e;
+__device__ __forceinline__ int64_t gather_off(int64_t i, int64_t j, int64_t ld, int64_t ps) {
+  return MODE >= 2 ? blk_off(i, j, ps) : i * ld + j;
+}
+
+template <int MODE>
+__device__ __forceinline__ void gather_store16(void* R_hi, void* R_lo, int64_t o, const float* v) {
+  if (MODE == 1) {
+    float4* d = (float4*)((float*)R_hi + o);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) d[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+  } else {
+    bf16x8 h[2], lo[2];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      h[q >> 3][q & 7] = (__bf16)v[q];
+      lo[q >> 3][q & 7] = (__bf16)(v[q] - (float)h[q >> 3][q & 7]);
     }
-    float v[8];
-    if (i < N) {
-      const RankRow ri = rank_row(rk, i);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int j = j0 + q;
-        v[q] = (j < N) ? r32[pair_rank_row(rk, ri, j)] : 0.f;
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = 0.f;
-    }
-    if (MODE == 1) {
-      float4* d = (float4*)((float*)R_hi + o);
-      d[0] = make_float4(v[0], v[1], v[2], v[3]);
-      d[1] = make_float4(v[4], v[5], v[6], v[7]);
-    } else {
-      bf16x8 h, lo;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        h[q] = (__bf16)v[q];
-        lo[q] = (__bf16)(v[q] - (float)h[q]);
-      }
-      *(bf16x8*)((__bf16*)R_hi + o) = h;
-      if (MODE == 2) *(bf16x8*)((__bf16*)R_lo + o) = lo;
+    bf16x8* dh = (bf16x8*)((__bf16*)R_hi + o);
+    dh[0] = h[0];
+    dh[1] = h[1];
+    if (MODE == 2) {
+      bf16x8* dl = (bf16x8*)((__bf16*)R_lo + o);
+      dl[0] = lo[0];
+      dl[1] = lo[1];
     }
   }
+}
+
+// R from r32 through the ranking, using R = R^T: each 256-thread block
+// takes one 64 x 64 tile (I, J) with I <= J of the T2 x T2 tiles covering the
+// N x N matrix (T2 = Np2 / 64), computes its values once, writes them at
+// (I, J) and, through LDS, transposed at (J, I).  Blocks past the triangle
+// write the zero rows Np2 .. Np - 1.  Per thread: one row, 16 consecutive
+// columns (one 32-byte run of a 16-column block in the blocked layouts).
+// The ranking's small table (field terms or binomials) and the tile's column
+// codes are staged in LDS.  r32 is the FP32 copy of r: R is rounded to FP32
+// first in every mode, so reading the copy gives the same bits as reading r.
+// Mode 1 = FP32 row-major, 2 = bf16 hi and lo (blocked), 3 = bf16 hi only.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_gather_sym(RankTab rk, const float* __restrict__ r32, int N, int64_t Np,
+                                                    int64_t ld, int T2, int64_t nup, void* R_hi, void* R_lo) {
+  __shared__ float V[64][65];
+  __shared__ int32_t Tab[kStageTabMax];            // field terms (dense) or binomials (sparse)
+  __shared__ uint32_t Cj[64 * kMaxWords];          // codes of the tile's 64 columns
+  const int64_t ps = panel_stride(ld / kBlkK, 2);
+  const int il = threadIdx.x >> 2, jc = (threadIdx.x & 3) * 16;
+  const int64_t b = blockIdx.x;
+  float v[16];
+  if (b >= nup) {  // zero rows past the T2 tiles
+    const int64_t z = b - nup;
+    const int64_t i = (int64_t)T2 * 64 + (z / T2) * 64 + il, j = (z % T2) * 64 + jc;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = 0.f;
+    gather_store16<MODE>(R_hi, R_lo, gather_off<MODE>(i, j, ld, ps), v);
+    return;
+  }
+  // b -> (I, J), I <= J, row-major over the upper triangle
+  const double tt = 2.0 * T2 + 1.0;
+  int I = (int)((tt - sqrt(tt * tt - 8.0 * (double)b)) * 0.5);
+  auto first = [&](int r) { return (int64_t)r * T2 - (int64_t)r * (r - 1) / 2; };
+  while (I > 0 && first(I) > b) --I;
+  while (first(I + 1) <= b) ++I;
+  const int J = I + (int)(b - first(I));
+  const int i = I * 64 + il, j0 = J * 64 + jc;
+  {
+    const int32_t* src = stage_tab(rk);
+    for (int e = threadIdx.x; e < rk.ntab; e += 256) Tab[e] = src[e];
+    for (int e = threadIdx.x; e < 64 * rk.nwords; e += 256) {
+      const int jj = J * 64 + e / rk.nwords;
+      Cj[e] = jj < N ? rk.codes[(size_t)jj * rk.nwords + e % rk.nwords] : 0u;
+    }
+  }
+  __syncthreads();
+  if (i < N) {
+    if (!rk.sparse) {
+      uint32_t ci[kMaxWords], cj[kMaxWords];
+#pragma unroll
+      for (int w = 0; w < kMaxWords; ++w) ci[w] = w < rk.nwords ? rk.codes[(size_t)i * rk.nwords + w] : 0u;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+#pragma unroll
+        for (int w = 0; w < kMaxWords; ++w) cj[w] = w < rk.nwords ? Cj[(jc + q) * rk.nwords + w] : 0u;
+        v[q] = (j0 + q < N) ? r32[dense_rank_fields(ci, cj, rk.n, Tab)] : 0.f;
+      }
+    } else {
+      const uint32_t ci = rk.codes[i];
+      const int D1 = rk.D + 1;
+      auto binom = [&](int x, int y) { return Tab[x * D1 + y]; };
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        v[q] = (j0 + q < N) ? r32[sparse_pair_rank(ci, Cj[jc + q], rk.n, rk.total, binom)] : 0.f;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = 0.f;
+  }
+  gather_store16<MODE>(R_hi, R_lo, gather_off<MODE>(i, j0, ld, ps), v);
+  if (I == J) return;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) V[il][jc + q] = v[q];
+  __syncthreads();
+  // transposed tile: row J*64 + il, columns I*64 + jc .. + 15
+#pragma unroll
+  for (int q = 0; q < 16; ++q) v[q] = V[jc + q][il];
+  gather_store16<MODE>(R_hi, R_lo, gather_off<MODE>((int64_t)J * 64 + il, (int64_t)I * 64 + jc, ld, ps), v);
 }
 
 struct RwArgs {
@@ -672,10 +726,16 @@ hipError_t launch_gather(const sos_plan_s* p, bool split, hipStream_t s) {
     return hipGetLastError();
   }
   const float* r32 = (const float*)(ws + p->lay.r32);
-  const int grid = grid_for(total / 8);
-  if (p->prec == SOS_FP32) k_gather8<1><<<grid, 256, 0, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, Rh, Rl);
-  else if (split) k_gather8<2><<<grid, 256, 0, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, Rh, Rl);
-  else k_gather8<3><<<grid, 256, 0, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, Rh, Rl);
+  const int T2 = (int)(p->Np2 / 64);
+  const int64_t nup = (int64_t)T2 * (T2 + 1) / 2;
+  const int64_t blocks = nup + (p->Np - p->Np2) / 64 * T2;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (p->prec == SOS_FP32)
+    k_gather_sym<1><<<(unsigned)blocks, 256, 0, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, T2, nup, Rh, Rl);
+  else if (split)
+    k_gather_sym<2><<<(unsigned)blocks, 256, 0, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, T2, nup, Rh, Rl);
+  else
+    k_gather_sym<3><<<(unsigned)blocks, 256, 0, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, T2, nup, Rh, Rl);
   return hipGetLastError();
 }
 

@@ -160,6 +160,11 @@ int plan_create(int n, int d, int rank, int prec, sos_plan_s** out) {
         p->tables[(size_t)g * kGroupEntries + idx] = valid ? (int32_t)s : 0;
       }
     }
+    // then the field terms one at a time: F[f * 16 + v] = field_term(f, v)
+    p->tables.resize((size_t)p->ngroups * kGroupEntries + kFieldTerms, 0);
+    int32_t* F = p->tables.data() + (size_t)p->ngroups * kGroupEntries;
+    for (int f = 0; f < n; ++f)
+      for (int v = 0; v <= D; ++v) F[f * 16 + v] = (int32_t)field_term(n, D, f, v);
   }
 
   // padded extents and workspace layout

@@ -70,10 +70,70 @@ __host__ __device__ inline int64_t blk_off(int64_t row, int64_t k, int64_t pstri
 // ---------------------------------------------------------------------------
 struct RankTab {
   const uint32_t* __restrict__ codes;   // dense: N x nwords; sparse: N packed lists
-  const int32_t* __restrict__ tables;   // dense: ngroups x 4096; sparse: binomial table
+  const int32_t* __restrict__ tables;   // dense: ngroups x 4096, then the field terms (16 x 16);
+                                        // sparse: binomial table (n + D + 1) x (D + 1)
   int nwords, ngroups;
   int sparse, n, D, total;              // sparse only (total = C(n + D, D))
+  int ntab;                             // entries of the table a kernel may stage in LDS:
+                                        // dense: the 256 field terms; sparse: the binomial table
 };
+
+constexpr int kFieldTerms = 256;        // dense: F[f * 16 + v], f < 16, v < 16
+constexpr int kStageTabMax = 2376;      // largest ntab: (255 + 8 + 1) x (8 + 1)
+
+// The field-term table of a dense plan, or the binomial table of a sparse one.
+__host__ __device__ inline const int32_t* stage_tab(const RankTab& t) {
+  return t.sparse ? t.tables : t.tables + (size_t)t.ngroups * kGroupEntries;
+}
+
+// Rank of alpha_i + alpha_j for dense codes from the per-field terms:
+// rank = sum over fields f < n of F[f][suffix sum f] (the closed form of
+// plan.cpp, field by field).  Field f sits in group f / 3 (4 bits each),
+// two groups per word.  At most 2d + 1 distinct values per field, so a
+// wave's lookups of one field touch consecutive words.
+__device__ __forceinline__ int dense_rank_fields(const uint32_t* ci, const uint32_t* cj, int n, const int32_t* F) {
+  uint32_t s[kMaxWords];
+#pragma unroll
+  for (int w = 0; w < kMaxWords; ++w) s[w] = ci[w] + cj[w];
+  int r = 0;
+#pragma unroll
+  for (int f = 0; f < 16; ++f) {
+    if (f < n) {
+      const int g = f / kFieldsPerGroup, w = g >> 1, sh = 16 * (g & 1) + 4 * (f % kFieldsPerGroup);
+      r += F[f * 16 + ((s[w] >> sh) & 15u)];
+    }
+  }
+  return r;
+}
+
+// Rank of the sum of two sparse monomials (ascending variable lists packed
+// one byte per factor, byte = variable + 1) through binom(x, y) = C(x, y).
+template <class Binom>
+__device__ __forceinline__ int sparse_pair_rank(uint32_t a, uint32_t b, int n, int total, const Binom& binom) {
+  int g[8];
+  int len = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {  // merge the two ascending lists
+    const uint32_t va = a & 0xFFu, vb = b & 0xFFu;
+    const bool take_a = va != 0 && (vb == 0 || va <= vb);
+    const uint32_t v = take_a ? va : vb;
+    g[q] = (int)v - 1;
+    if (take_a) a >>= 8;
+    else b >>= 8;
+    len += v != 0;
+  }
+  int r = total - binom(n + len, len);
+  int prev = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    if (q < len) {
+      const int m = len - 1 - q, v = g[q];
+      r += binom(n - prev + m, m + 1) - binom(n - v + m, m + 1);
+      prev = v;
+    }
+  }
+  return r;
+}
 
 // The codes of row i, loaded once for many partners j.
 struct RankRow {
@@ -102,30 +162,7 @@ __device__ __forceinline__ int pair_rank_row(const RankTab& t, const RankRow& ri
     }
     return r;
   }
-  uint32_t a = ri.c[0], b = t.codes[j];
-  int g[8];
-  int len = 0;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {  // merge the two ascending lists
-    const uint32_t va = a & 0xFFu, vb = b & 0xFFu;
-    const bool take_a = va != 0 && (vb == 0 || va <= vb);
-    const uint32_t v = take_a ? va : vb;
-    g[q] = (int)v - 1;
-    if (take_a) a >>= 8;
-    else b >>= 8;
-    len += v != 0;
-  }
-  int r = t.total - rank_binom(t, t.n + len, len);
-  int prev = 0;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    if (q < len) {
-      const int m = len - 1 - q, v = g[q];
-      r += rank_binom(t, t.n - prev + m, m + 1) - rank_binom(t, t.n - v + m, m + 1);
-      prev = v;
-    }
-  }
-  return r;
+  return sparse_pair_rank(ri.c[0], t.codes[j], t.n, t.total, [&](int x, int y) { return rank_binom(t, x, y); });
 }
 
 __device__ __forceinline__ int pair_rank(const RankTab& t, int i, int j) {
@@ -223,6 +260,7 @@ inline RankTab rank_tab(const sos_plan_s* p) {
   t.n = p->n;
   t.D = 2 * p->d;
   t.total = (int)p->M;
+  t.ntab = p->sparse ? (p->n + 2 * p->d + 1) * (2 * p->d + 1) : kFieldTerms;
   return t;
 }
 // kernel launchers (kernels.hip)

@@ -113,7 +113,7 @@ class Server:
 
     def __init__(self, hbm_budget: int = 8 << 30, max_active: int = 48, check_every: int = 50,
                  tol: float = 1e-6, max_steps: int = 20000, adam: Adam | None = None,
-                 stall_checks: int = 20, stall_ratio: float = 0.5, keep_W: bool = False, stream=None):
+                 stall_checks: int = 10, stall_ratio: float = 0.5, keep_W: bool = False, stream=None):
         self.hbm_budget = int(hbm_budget)
         self.max_active = int(max_active)
         self.check_every = int(check_every)
