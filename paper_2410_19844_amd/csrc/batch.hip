@@ -23,7 +23,7 @@
 //              the plan's pair order; L = sum r_m^2 by a fixed-order block
 //              sum and a fixed-order sum of the block partials in the block
 //              that arrives last
-//   k_b_rw     partial g = 4 R W per slice of the contraction index, FP32,
+//   k_b_rw     partial g = 4 R W per slice of the contraction index, FP32 MFMA,
 //              R_ij = r[rank of alpha_i + alpha_j] through the plan's map
 //   k_b_adam   g = sum of the slices, bias-corrected Adam in FP32
 #include <hip/hip_runtime.h>
@@ -203,14 +203,21 @@ __global__ __launch_bounds__(256) void k_b_coeff(Args a) {
   }
 }
 
-// Partial g = 4 R W over j in one slice of kBatchSliceJ: tiles of 32 rows (i) x 64 columns
-// (l), j in chunks of 32 through LDS, the next chunk prefetched into
-// registers.  Thread (ty, tx) of a 16 x 16 grid owns rows 2 ty, 2 ty + 1 and
-// columns tx + 16 w.
-constexpr int TBI = 32, TBL = 64, TBK = 32;
+// Partial g = 4 R W over j in one slice of kBatchSliceJ on FP32 MFMA
+// (v_mfma_f32_32x32x2f32), in tiles of 64 rows (i) x 64 columns (l), one
+// 32 x 32 block per wave.  j runs in chunks of 32 through LDS, the next chunk
+// prefetched into registers.  Within each group of 8 j, lane half h
+// contracts j = 4 h + s in k-step s (s = 0..3), so a lane's operands of four
+// k-steps are one 16-byte LDS read from R (rows i) and from W^T (rows l).
+// The order of the sum is fixed by the problem's shape alone.  (Tiles of
+// 64 x 256 fetch each R value fewer times and are faster on the largest
+// problems alone, but slower on the serving mix, where they leave too few
+// blocks per problem.)
+constexpr int TBI = 64, TBL = 64, TBK = 32, TBS = TBK + 4;
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 __global__ __launch_bounds__(256) void k_b_rw(Args a) {
-  __shared__ float Rs[TBI][TBK + 1];
-  __shared__ float Ws[TBK][TBL + 1];
+  __shared__ __align__(16) float Rs[TBI][TBS];   // R_ij, j within the chunk
+  __shared__ __align__(16) float Wt[TBL][TBS];   // W_jl stored at [l][j]
   const int q = find_req(a.bwd_off, a.count, blockIdx.x);
   const Req& R = a.q[q];
   const int local = blockIdx.x - a.bwd_off[q];
@@ -219,7 +226,9 @@ __global__ __launch_bounds__(256) void k_b_rw(Args a) {
   const int I = t / nl, L = t % nl;
   const int jb = s * kBatchSliceJ;
   const int je = min(R.N, jb + kBatchSliceJ);
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int h = lane >> 5, lr = lane & 31;
+  const int row0 = (wave >> 1) * 32, col0 = (wave & 1) * 32;
   float rr[TBI * TBK / 256], ww[TBK * TBL / 256];
   auto load = [&](int j0) {
 #pragma unroll
@@ -235,7 +244,7 @@ __global__ __launch_bounds__(256) void k_b_rw(Args a) {
       ww[u] = (j < je && c < R.k) ? R.W[(size_t)j * R.k + c] : 0.f;
     }
   };
-  float acc[2][4] = {};
+  f32x16 acc = {};
   load(jb);
   for (int j0 = jb; j0 < je; j0 += TBK) {
 #pragma unroll
@@ -246,30 +255,28 @@ __global__ __launch_bounds__(256) void k_b_rw(Args a) {
 #pragma unroll
     for (int u = 0; u < TBK * TBL / 256; ++u) {
       const int e = threadIdx.x + 256 * u;
-      Ws[e / TBL][e % TBL] = ww[u];
+      Wt[e % TBL][e / TBL] = ww[u];
     }
     __syncthreads();
     if (j0 + TBK < je) load(j0 + TBK);
-#pragma unroll 8
-    for (int jj = 0; jj < TBK; ++jj) {
-      const float r0 = Rs[2 * ty][jj], r1 = Rs[2 * ty + 1][jj];
 #pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        const float x = Ws[jj][tx + 16 * w];
-        acc[0][w] = fmaf(r0, x, acc[0][w]);
-        acc[1][w] = fmaf(r1, x, acc[1][w]);
-      }
+    for (int g8 = 0; g8 < TBK / 8; ++g8) {
+      const float4 a4 = *(const float4*)&Rs[row0 + lr][g8 * 8 + 4 * h];
+      const float4 b4 = *(const float4*)&Wt[col0 + lr][g8 * 8 + 4 * h];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, b4.x, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, b4.y, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, b4.z, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, b4.w, acc, 0, 0, 0);
     }
     __syncthreads();
   }
   float* g = R.gp + (size_t)s * R.N * R.k;
+  const int c = L * TBL + col0 + lr;
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      const int i = I * TBI + 2 * ty + u, c = L * TBL + tx + 16 * w;
-      if (i < R.N && c < R.k) g[(size_t)i * R.k + c] = 4.f * acc[u][w];
-    }
+  for (int r = 0; r < 16; ++r) {
+    const int i = I * TBI + row0 + (r >> 2) * 8 + h * 4 + (r & 3);
+    if (i < R.N && c < R.k) g[(size_t)i * R.k + c] = 4.f * acc[r];
+  }
 }
 
 // g = sum of the slices (in slice order), then Adam; grid.y = problem.
