@@ -15,6 +15,8 @@
 // K-contiguous, padded so that tiles never read out of bounds.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cstdint>
 
 #include "sos_internal.h"
@@ -157,6 +159,7 @@ __global__ __launch_bounds__(256) void k_sumsq_final(const double* __restrict__ 
 // ---------------------------------------------------------------------------
 constexpr int BM = 128;
 constexpr int kThreads = 256;
+constexpr int kGramMinBlocks = 512;   // contraction splits of the gram below this many tiles
 
 // Mode F64: double operands, f64 16x16x4 MFMA.  Output of one 16x16 block:
 // lane l, register q holds row (l / 16) + 4 q, column l % 16.
@@ -384,7 +387,9 @@ __device__ __forceinline__ void gemm_tile(const typename Md::GT* const* A, const
 struct GramArgs {
   const void* A[2];   // operand arrays (hi[, lo]); rows Np, ld Kp
   int64_t ld, K;      // ld = K = Kp
+  int64_t kslice;     // contraction length per block (a multiple of 64)
   int N, T;           // T = Np / BM tiles per side
+  int tiles;          // T (T + 1) / 2
   RankTab rk;
   double* r;
 };
@@ -398,15 +403,20 @@ __device__ __forceinline__ void tri_tile(int b, int& I, int& J) {
   I = b - j * (j + 1) / 2;
 }
 
+// Block b takes tile b % tiles over the contraction slice b / tiles (more
+// than one slice only when the tiles alone would leave the chip idle); the
+// FP64 atomics sum tiles and slices alike.
 template <class Md>
 __global__ __launch_bounds__(kThreads) void k_gram(GramArgs g) {
   extern __shared__ __align__(16) char smem[];
   Stage<Md>* st = (Stage<Md>*)smem;
   int I, J;
-  tri_tile(blockIdx.x, I, J);
-  const typename Md::GT* ops[2] = {(const typename Md::GT*)g.A[0], (const typename Md::GT*)g.A[1]};
+  tri_tile((int)(blockIdx.x % g.tiles), I, J);
+  const int64_t k0 = (int64_t)(blockIdx.x / g.tiles) * g.kslice;
+  const int64_t klen = g.K - k0 < g.kslice ? g.K - k0 : g.kslice;
+  const typename Md::GT* ops[2] = {(const typename Md::GT*)g.A[0] + k0, (const typename Md::GT*)g.A[1] + k0};
   typename Md::Acc acc[Md::NACC];
-  gemm_tile<Md>(ops, ops, g.ld, g.K, (int64_t)I * BM, (int64_t)J * BM, st, acc);
+  gemm_tile<Md>(ops, ops, g.ld, klen, (int64_t)I * BM, (int64_t)J * BM, st, acc);
   const int wave = threadIdx.x / 64;
   const int wm = wave / 2, wn = wave % 2;
 #pragma unroll
@@ -673,6 +683,14 @@ static hipError_t gram_launch(const sos_plan_s* p, const void* a0, const void* a
   g.rk = rank_tab(p);
   g.r = (double*)(p->ws + p->lay.r);
   const int tiles = g.T * (g.T + 1) / 2;
+  g.tiles = tiles;
+  // split the contraction when there are too few tiles to fill the chip
+  int64_t splits = 1;
+  if (tiles < kGramMinBlocks) splits = std::min<int64_t>((kGramMinBlocks + tiles - 1) / tiles, g.K / 64);
+  if (splits < 1) splits = 1;
+  g.kslice = (g.K + splits - 1) / splits;
+  g.kslice = (g.kslice + 63) / 64 * 64;
+  splits = (g.K + g.kslice - 1) / g.kslice;
   const size_t sm = 2 * sizeof(Stage<Md>);
   static bool attr = false;
   if (!attr) {
@@ -680,7 +698,7 @@ static hipError_t gram_launch(const sos_plan_s* p, const void* a0, const void* a
     if (e != hipSuccess) return e;
     attr = true;
   }
-  k_gram<Md><<<tiles, kThreads, sm, s>>>(g);
+  k_gram<Md><<<(unsigned)(tiles * splits), kThreads, sm, s>>>(g);
   return hipGetLastError();
 }
 
