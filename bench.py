@@ -77,14 +77,17 @@ def parse():
     return ap.parse_args()
 
 
+# the sources the counted kernels (k_gram_bf3, k_rw_adam_bf3, k_gram_x64) are built from
+COUNTED_SOURCES = ("csrc/gemm_bf3.hip", "csrc/gemm_x64.hip", "csrc/sos_internal.h", "build.py")
+
+
 def kernel_sources_hash():
-    """Hash of the library's kernel sources (the HBM counters stored under
-    profiles/ are only used while it still matches)."""
+    """Hash of the counted kernels' sources and build flags (the HBM counters
+    stored under profiles/ are only used while it still matches)."""
     h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_2410_19844_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in COUNTED_SOURCES:
         h.update(f.encode())
-        with open(os.path.join(d, f), "rb") as fh:
+        with open(os.path.join(ROOT, "paper_2410_19844_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
