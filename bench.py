@@ -78,13 +78,15 @@ def parse():
 
 
 # the sources the counted kernels (k_gram_bf3, k_rw_adam_bf3, k_gram_x64) are built from
-COUNTED_SOURCES = ("csrc/gemm_bf3.hip", "csrc/gemm_x64.hip", "csrc/sos_internal.h", "build.py")
+COUNTED_SOURCES = ("csrc/gemm_bf3.hip", "csrc/gemm_x64.hip", "csrc/sos_internal.h")
 
 
 def kernel_sources_hash():
-    """Hash of the counted kernels' sources and build flags (the HBM counters
-    stored under profiles/ are only used while it still matches)."""
+    """Hash of the counted kernels' sources and compile flags (the HBM
+    counters stored under profiles/ are only used while it still matches)."""
+    from paper_2410_19844_amd.build import HIP_FLAGS
     h = hashlib.sha256()
+    h.update(" ".join(HIP_FLAGS).encode())
     for f in COUNTED_SOURCES:
         h.update(f.encode())
         with open(os.path.join(ROOT, "paper_2410_19844_amd", f), "rb") as fh:

@@ -31,15 +31,38 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found: libsos needs ROCm's hipcc to build")
 
 
+# the compiler's per-kernel resource report (registers, scratch, occupancy),
+# kept in _build/kernel_resources.tsv; it does not change the generated code
+REPORT_FLAGS = ["-Rpass-analysis=kernel-resource-usage"]
+RESOURCES = os.path.join(HERE, "_build", "kernel_resources.tsv")
+
+
+def parse_resources(text: str) -> list[dict]:
+    """Kernels and their resource figures from hipcc's remarks."""
+    out, cur = [], None
+    for line in text.splitlines():
+        if "remark:" not in line:
+            continue
+        body = line.split("remark:", 1)[1].split("[-Rpass", 1)[0].strip()
+        if body.startswith("Function Name:"):
+            cur = {"kernel": body.split(":", 1)[1].strip()}
+            out.append(cur)
+        elif cur is not None and ":" in body:
+            key, val = body.rsplit(":", 1)
+            cur[key.strip()] = val.strip()
+    return out
+
+
 def build(verbose: bool = False) -> str:
     """Compile every source and link libsos.so; returns the library path."""
     objs = []
     obj_dir = os.path.join(HERE, "_build")
     os.makedirs(obj_dir, exist_ok=True)
     cc = hipcc()
+    report = []
     for src in SOURCES:
         obj = os.path.join(obj_dir, src.rsplit(".", 1)[0] + ".o")
-        cmd = [cc, *HIP_FLAGS, "-I", os.path.join(HERE, "..", "include"), "-c",
+        cmd = [cc, *HIP_FLAGS, *REPORT_FLAGS, "-I", os.path.join(HERE, "..", "include"), "-c",
                os.path.join(CSRC, src), "-o", obj]
         if not src.endswith(".hip"):
             cmd[1:1] = ["-x", "hip"]
@@ -49,7 +72,14 @@ def build(verbose: bool = False) -> str:
         if res.returncode != 0:
             sys.stderr.write(res.stdout + res.stderr)
             raise RuntimeError(f"hipcc failed on {src}")
+        report += [dict(r, source=src) for r in parse_resources(res.stderr)]
         objs.append(obj)
+    cols = ["source", "kernel", "VGPRs", "AGPRs", "ScratchSize [bytes/lane]", "Occupancy [waves/SIMD]",
+            "LDS Size [bytes/block]"]
+    with open(RESOURCES, "w") as f:
+        f.write("\t".join(cols) + "\n")
+        for r in report:
+            f.write("\t".join(str(r.get(c, "")) for c in cols) + "\n")
     tmp = LIB + ".tmp"
     cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -419,14 +419,31 @@ __global__ __launch_bounds__(kThreads) void k_gram(GramArgs g) {
   gemm_tile<Md>(ops, ops, g.ld, klen, (int64_t)I * BM, (int64_t)J * BM, st, acc);
   const int wave = threadIdx.x / 64;
   const int wm = wave / 2, wn = wave % 2;
+  // Epilogue through LDS in two row halves (the stage buffers are free now):
+  // the copy-out indexes the accumulators at compile time, so they stay in
+  // registers; the rank-and-add loop indexes LDS instead.
+  using Acc = typename Md::Acc;
+  constexpr int HR = BM / 2;
+  static_assert(HR * BM * sizeof(Acc) <= 2 * sizeof(Stage<Md>), "half tile must fit the stage buffers");
+  Acc* half = (Acc*)smem;
 #pragma unroll
-  for (int e = 0; e < Md::NACC; ++e) {
-    int row, col;
-    acc_pos<Md>(e, row, col);
-    const int i = I * BM + wm * 64 + row, j = J * BM + wn * 64 + col;
-    if (i < g.N && j < g.N && i <= j) {
-      const double w = (i == j) ? 1.0 : 2.0;
-      unsafeAtomicAdd(g.r + pair_rank(g.rk, i, j), w * (double)acc[e]);
+  for (int hh = 0; hh < 2; ++hh) {
+    __syncthreads();
+    if (wm == hh) {
+#pragma unroll
+      for (int e = 0; e < Md::NACC; ++e) {
+        int row, col;
+        acc_pos<Md>(e, row, col);
+        half[row * BM + wn * 64 + col] = acc[e];
+      }
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < HR * BM; x += kThreads) {
+      const int i = I * BM + hh * HR + x / BM, j = J * BM + x % BM;
+      if (i < g.N && j < g.N && i <= j) {
+        const double w = (i == j) ? 1.0 : 2.0;
+        unsafeAtomicAdd(g.r + pair_rank(g.rk, i, j), w * (double)half[x]);
+      }
     }
   }
 }

@@ -107,27 +107,28 @@ __device__ __forceinline__ int dense_rank_fields(const uint32_t* ci, const uint3
 }
 
 // Rank of the sum of two sparse monomials (ascending variable lists packed
-// one byte per factor, byte = variable + 1) through binom(x, y) = C(x, y).
+// one byte per factor, byte = variable + 1, at most four factors each) through
+// binom(x, y) = C(x, y).  The merged list is walked once, the term of each
+// factor added as it is taken; no per-thread array (which would live in
+// scratch memory).
+__device__ __forceinline__ int packed_len(uint32_t x) {
+  return (x != 0u) + ((x >> 8) != 0u) + ((x >> 16) != 0u) + ((x >> 24) != 0u);
+}
+
 template <class Binom>
 __device__ __forceinline__ int sparse_pair_rank(uint32_t a, uint32_t b, int n, int total, const Binom& binom) {
-  int g[8];
-  int len = 0;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {  // merge the two ascending lists
-    const uint32_t va = a & 0xFFu, vb = b & 0xFFu;
-    const bool take_a = va != 0 && (vb == 0 || va <= vb);
-    const uint32_t v = take_a ? va : vb;
-    g[q] = (int)v - 1;
-    if (take_a) a >>= 8;
-    else b >>= 8;
-    len += v != 0;
-  }
+  const int len = packed_len(a) + packed_len(b);
   int r = total - binom(n + len, len);
   int prev = 0;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     if (q < len) {
-      const int m = len - 1 - q, v = g[q];
+      const uint32_t va = a & 0xFFu, vb = b & 0xFFu;
+      const bool take_a = va != 0 && (vb == 0 || va <= vb);
+      const int v = (int)(take_a ? va : vb) - 1;
+      if (take_a) a >>= 8;
+      else b >>= 8;
+      const int m = len - 1 - q;
       r += binom(n - prev + m, m + 1) - binom(n - v + m, m + 1);
       prev = v;
     }

@@ -1,0 +1,45 @@
+"""Per-kernel resources of the built library (the compiler's report, kept by
+the build in _build/kernel_resources.tsv).
+
+Scratch memory per lane must be zero everywhere except a few epilogues that
+spill one 16-register block of accumulators once per tile (outside the
+MFMA loop).  A private array that the compiler cannot keep in registers
+(dynamically indexed accumulators, a per-thread list) lands in scratch and
+slows a kernel several times; this test catches that at build time.
+"""
+import csv
+import os
+
+import pytest
+
+RES = os.path.join(os.path.dirname(__file__), "..", "paper_2410_19844_amd", "_build", "kernel_resources.tsv")
+
+# kernel name fragment -> largest scratch allowed (bytes per lane)
+EPILOGUE_SPILLS = {
+    "k_gram_bf3": 128,   # accumulators of the second row half, kept across the first half's scatter
+    "k_rw_bf3": 128,     # the same in the unfused R W epilogue
+}
+
+HOT = ["k_gram_bf3", "k_rw_adam_bf3", "k_gram_x64", "k_gather_sym", "k_gramINS_4MF32", "k_gramINS_4MF64",
+       "k_b_gram", "k_b_coeff", "k_b_rw", "k_b_adam", "k_prep", "k_sumsq"]
+
+
+@pytest.fixture(scope="module")
+def rows():
+    if not os.path.exists(RES):
+        pytest.skip("library not built (run __graft_entry__.build())")
+    with open(RES) as f:
+        return list(csv.DictReader(f, delimiter="\t"))
+
+
+def test_report_covers_the_hot_kernels(rows):
+    names = [r["kernel"] for r in rows]
+    for frag in HOT:
+        assert any(frag in n for n in names), frag
+
+
+def test_no_scratch_outside_known_epilogue_spills(rows):
+    for r in rows:
+        scratch = int(r["ScratchSize [bytes/lane]"] or 0)
+        limit = next((v for k, v in EPILOGUE_SPILLS.items() if k in r["kernel"]), 0)
+        assert scratch <= limit, (r["source"], r["kernel"], scratch)
