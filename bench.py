@@ -48,7 +48,8 @@ def parse():
     ap.add_argument("--workload", default="n12d6")
     ap.add_argument("--exact", action="store_true", help="FP64 forward (the finishing phase)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=1024)
+    ap.add_argument("--cpu-rows", type=int, default=12288,
+                    help="rows of one step the oracle baseline times (about 10-30 s of host work)")
     ap.add_argument("--mode", default="step", choices=["step", "ttt", "serve", "net"])
     ap.add_argument("--net-n", type=int, default=30, help="net: variables of the quartic forms")
     ap.add_argument("--net-case", choices=("one", "many", "uniform"), default="one",

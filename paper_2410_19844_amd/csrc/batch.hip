@@ -20,7 +20,8 @@
 //              stored at its pair's place in the coefficient-ordered lists
 //   k_b_coeff  r_m = sum over the pairs (i <= j) of monomial m of
 //              (2 - [i = j]) G_ij (G_ij summed over slices), minus p_m, in
-//              the plan's pair order; L = sum r_m^2 by a fixed-order block
+//              the plan's pair order (a block's pairs staged through LDS in
+//              coalesced chunks); L = sum r_m^2 by a fixed-order block
 //              sum and a fixed-order sum of the block partials in the block
 //              that arrives last
 //   k_b_rw     partial g = 4 R W per slice of the contraction index, FP32 MFMA,
@@ -38,6 +39,7 @@ namespace bat {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMaxBatch = 24;
+constexpr int kCoeffChunk = 2048;   // pair values staged in LDS per round of k_b_coeff
 
 struct Req {
   const float* W;            // N x k
@@ -157,29 +159,32 @@ __global__ __launch_bounds__(256) void k_b_coeff(Args a) {
   if ((int)blockIdx.x >= nb) return;
   __shared__ double sh4[4];
   __shared__ int last;
+  __shared__ double vals[kCoeffChunk];
   const int m = blockIdx.x * 256 + threadIdx.x;
+  const int m0 = blockIdx.x * 256, m1 = min(R.M, m0 + 256);
+  const size_t P = (size_t)R.N * (R.N + 1) / 2;
+  // G of pair e: the slices in slice order, doubled off the diagonal
+  auto pair_val = [&](int e) {
+    double gij = R.Gp[e];
+    for (int s = 1; s < R.sg; ++s) gij += R.Gp[s * P + e];
+    return ((uint32_t)R.pair_idx[e] >> 31) ? 2.0 * gij : gij;
+  };
+  // The pairs of this block's coefficients are one contiguous range of the
+  // pair lists: stage it through LDS in coalesced chunks, then each thread
+  // adds its own coefficient's pairs, in pair order.
+  const int eb = R.pair_off[m0], ee = R.pair_off[m1];
+  const int my0 = m < R.M ? R.pair_off[m] : 0, my1 = m < R.M ? R.pair_off[m + 1] : 0;
+  double c = 0.0;
+  for (int cb = eb; cb < ee; cb += kCoeffChunk) {
+    const int ce = min(ee, cb + kCoeffChunk);
+    __syncthreads();
+    for (int e = cb + threadIdx.x; e < ce; e += 256) vals[e - cb] = pair_val(e);
+    __syncthreads();
+    const int lo = max(my0, cb), hi = min(my1, ce);
+    for (int e = lo; e < hi; ++e) c += vals[e - cb];
+  }
   double rr = 0.0;
   if (m < R.M) {
-    const int e0 = R.pair_off[m], e1 = R.pair_off[m + 1];
-    const size_t P = (size_t)R.N * (R.N + 1) / 2;
-    // G of pair e: the slices in slice order, doubled off the diagonal; the
-    // pairs of m are entries e0 .. e1 - 1 of every slice (contiguous)
-    auto pair_val = [&](int e) {
-      double gij = R.Gp[e];
-      for (int s = 1; s < R.sg; ++s) gij += R.Gp[s * P + e];
-      return ((uint32_t)R.pair_idx[e] >> 31) ? 2.0 * gij : gij;
-    };
-    // pairs four at a time (independent loads in flight), added in pair order
-    double c = 0.0;
-    int e = e0;
-    for (; e + 4 <= e1; e += 4) {
-      const double v0 = pair_val(e), v1 = pair_val(e + 1), v2 = pair_val(e + 2), v3 = pair_val(e + 3);
-      c += v0;
-      c += v1;
-      c += v2;
-      c += v3;
-    }
-    for (; e < e1; ++e) c += pair_val(e);
     rr = c - R.p[m];
     R.r[m] = rr;
   }
