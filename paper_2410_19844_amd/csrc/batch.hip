@@ -234,14 +234,22 @@ __global__ __launch_bounds__(256) void k_b_rw(Args a) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int h = lane >> 5, lr = lane & 31;
   const int row0 = (wave >> 1) * 32, col0 = (wave & 1) * 32;
-  float rr[TBI * TBK / 256], ww[TBK * TBL / 256];
-  auto load = [&](int j0) {
+  // R_ij needs two dependent loads (the rank map, then r): the map entries
+  // are fetched two chunks ahead, the values and W one chunk ahead.
+  constexpr int NR = TBI * TBK / 256;
+  int idx[NR];
+  float rr[NR], ww[TBK * TBL / 256];
+  auto load_idx = [&](int j0) {
 #pragma unroll
-    for (int u = 0; u < TBI * TBK / 256; ++u) {
+    for (int u = 0; u < NR; ++u) {
       const int e = threadIdx.x + 256 * u;
       const int i = I * TBI + e / TBK, j = j0 + e % TBK;
-      rr[u] = (i < R.N && j < je) ? (float)R.r[R.rank_map[(size_t)i * R.N + j]] : 0.f;
+      idx[u] = (i < R.N && j < je) ? R.rank_map[(size_t)i * R.N + j] : -1;
     }
+  };
+  auto load_vals = [&](int j0) {
+#pragma unroll
+    for (int u = 0; u < NR; ++u) rr[u] = idx[u] >= 0 ? (float)R.r[idx[u]] : 0.f;
 #pragma unroll
     for (int u = 0; u < TBK * TBL / 256; ++u) {
       const int e = threadIdx.x + 256 * u;
@@ -250,7 +258,9 @@ __global__ __launch_bounds__(256) void k_b_rw(Args a) {
     }
   };
   f32x16 acc = {};
-  load(jb);
+  load_idx(jb);
+  load_vals(jb);
+  if (jb + TBK < je) load_idx(jb + TBK);
   for (int j0 = jb; j0 < je; j0 += TBK) {
 #pragma unroll
     for (int u = 0; u < TBI * TBK / 256; ++u) {
@@ -263,7 +273,8 @@ __global__ __launch_bounds__(256) void k_b_rw(Args a) {
       Wt[e % TBL][e / TBL] = ww[u];
     }
     __syncthreads();
-    if (j0 + TBK < je) load(j0 + TBK);
+    if (j0 + TBK < je) load_vals(j0 + TBK);
+    if (j0 + 2 * TBK < je) load_idx(j0 + 2 * TBK);
 #pragma unroll
     for (int g8 = 0; g8 < TBK / 8; ++g8) {
       const float4 a4 = *(const float4*)&Rs[row0 + lr][g8 * 8 + 4 * h];
