@@ -145,9 +145,12 @@ typedef struct {
 } sos_result_t;
 
 /* Plan a problem (host only; enumerates the bases of Section 1.1, builds
- * the ranking tables and sizes the buffers).  n, d, rank >= 1;
- * SOS_ERANGE if 2d > 15, n > 16, M >= 2^31 or N*N >= 2^31.
- * The plan must be bound to a workspace before any device call.          */
+ * the ranking tables and sizes the buffers).  n, d, rank >= 1.  Up to 16
+ * variables the ranking uses 4-bit suffix-sum codes (2d <= 15); with more
+ * variables it uses sorted variable lists (2d <= 8, n <= 255, as for the
+ * paper's quartics in 100 variables).  SOS_ERANGE outside these, or when
+ * M >= 2^31 or N*N >= 2^31.  The plan must be bound to a workspace before
+ * any device call.                                                        */
 int sos_plan(int n, int d, int rank, int precision, sos_plan_t* out);
 
 /* Sizes: basis length N, coefficient count M, workspace bytes (one per

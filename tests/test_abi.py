@@ -73,11 +73,14 @@ def test_plan_argument_errors():
     assert _plan_rc(3, 2, 0, 0) == -1          # rank < 1
     assert _plan_rc(3, 2, 5, 9) == -1          # unknown precision
     assert _plan_rc(3, 8, 5, 0) == -2          # 2d = 16 > 15
+    assert b"2d <= 15" in S._lib.sos_last_error()
     assert _plan_rc(17, 1, 5, 0) == 0          # n > 16: variable-list ranking
     assert _plan_rc(17, 5, 5, 0) == -2         # n > 16 needs 2d <= 8
+    assert b"2d <= 8" in S._lib.sos_last_error()
     assert _plan_rc(256, 1, 5, 0) == -2        # n > 255
+    assert b"n <= 255" in S._lib.sos_last_error()
     assert _plan_rc(16, 7, 5, 0) == -2         # N*N >= 2^31
-    assert b"2d" in S._lib.sos_last_error() or True
+    assert b"2^31" in S._lib.sos_last_error()
 
 
 def test_unbound_plan_rejects_device_calls():
