@@ -221,7 +221,8 @@ int sos_verify(sos_plan_t plan, const void* d_W, const double* d_p, double* h_re
  * FP32, row-major), d_state[q] (sos_plan_query's state_bytes; m and v as in
  * sos_step), t[q] (1-based Adam step count) and d_p[q] (M FP64) as in
  * sos_step.  d_losses[q] (device) receives L of problem q at the W before
- * the update.  Any count >= 0 is accepted; the library launches in groups.
+ * the update.  Any count >= 0 is accepted; the library launches in groups
+ * of problems of similar size (largest basis first).
  *
  * Numerics: the forward forms every Gram entry from exact FP64 products of
  * the FP32 entries, summed in FP64, then each coefficient sums its (i <= j)

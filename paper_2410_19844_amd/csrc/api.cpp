@@ -1,6 +1,7 @@
 // C ABI of libsos (declared in include/sos.h): argument checks, call
 // sequencing on the caller's stream, and the host side of the solve loop.
 #include <algorithm>
+#include <numeric>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -446,6 +447,31 @@ static int check_batch(const sos_plan_t* plans, const void* const* W, const doub
   return SOS_OK;
 }
 
+// The problems of a grouped call in launch order: largest basis first
+// (stable), so that each group holds problems of similar size and a group of
+// small problems is not held up by one large problem.  A problem's results
+// do not depend on its group, so the order changes only the time.
+struct BatchOrder {
+  std::vector<sos_plan_s*> P;
+  std::vector<void*> W, S;
+  std::vector<int64_t> T;
+  std::vector<const double*> p;
+  std::vector<int> slot;
+  BatchOrder(const sos_plan_t* plans, void* const* d_W, void* const* d_state, const int64_t* t,
+             const double* const* d_p, int count)
+      : slot(count) {
+    std::iota(slot.begin(), slot.end(), 0);
+    std::stable_sort(slot.begin(), slot.end(), [&](int a, int b) { return plans[a]->N > plans[b]->N; });
+    for (int q : slot) {
+      P.push_back(plans[q]);
+      W.push_back(d_W[q]);
+      p.push_back(d_p[q]);
+      if (d_state) S.push_back(d_state[q]);
+      if (t) T.push_back(t[q]);
+    }
+  }
+};
+
 int sos_step_batch(const sos_plan_t* plans, void* const* d_W, void* const* d_state, const int64_t* t,
                    const double* const* d_p, const sos_adam_t* adam, double* d_losses, int count,
                    void* stream) {
@@ -457,11 +483,13 @@ int sos_step_batch(const sos_plan_t* plans, void* const* d_W, void* const* d_sta
     if (!d_state[q]) return set_error(SOS_EINVAL, "sos_step_batch: NULL state");
     if (t[q] < 1) return set_error(SOS_EINVAL, "sos_step_batch: t is 1-based");
   }
+  const BatchOrder o(plans, (void* const*)d_W, d_state, t, d_p, count);
   const int cap = batch_capacity();
   for (int q0 = 0; q0 < count; q0 += cap) {
     const int c = std::min(cap, count - q0);
-    SOS_HIP(launch_step_group(plans + q0, d_W + q0, d_state + q0, t + q0, d_p + q0, adam, d_losses + q0, c,
-                              (hipStream_t)stream), "sos_step_batch");
+    SOS_HIP(launch_step_group(o.P.data() + q0, o.W.data() + q0, o.S.data() + q0, o.T.data() + q0, o.p.data() + q0,
+                              adam, d_losses, o.slot.data() + q0, c, (hipStream_t)stream),
+            "sos_step_batch");
   }
   return SOS_OK;
 }
@@ -469,11 +497,13 @@ int sos_step_batch(const sos_plan_t* plans, void* const* d_W, void* const* d_sta
 int sos_loss_batch(const sos_plan_t* plans, const void* const* d_W, const double* const* d_p, double* d_losses,
                    int count, void* stream) {
   if (int rc = check_batch(plans, d_W, d_p, d_losses, count, "sos_loss_batch")) return rc;
+  const BatchOrder o(plans, (void* const*)d_W, nullptr, nullptr, d_p, count);
   const int cap = batch_capacity();
   for (int q0 = 0; q0 < count; q0 += cap) {
     const int c = std::min(cap, count - q0);
-    SOS_HIP(launch_step_group(plans + q0, (void* const*)(d_W + q0), nullptr, nullptr, d_p + q0, nullptr,
-                              d_losses + q0, c, (hipStream_t)stream), "sos_loss_batch");
+    SOS_HIP(launch_step_group(o.P.data() + q0, o.W.data() + q0, nullptr, nullptr, o.p.data() + q0, nullptr,
+                              d_losses, o.slot.data() + q0, c, (hipStream_t)stream),
+            "sos_loss_batch");
   }
   return SOS_OK;
 }

@@ -316,10 +316,11 @@ __global__ __launch_bounds__(256) void k_b_adam(Args a) {
 int batch_capacity() { return bat::kMaxBatch; }
 
 // Problems [0, count), count <= kMaxBatch.  state == nullptr: forward and
-// loss only (the certificate); otherwise the whole step.
+// loss only (the certificate); otherwise the whole step.  Problem q's loss
+// goes to losses[slot[q]] (losses[q] without a slot map).
 hipError_t launch_step_group(sos_plan_s* const* plans, void* const* W, void* const* state, const int64_t* t,
-                             const double* const* p, const sos_adam_t* h, double* losses, int count,
-                             hipStream_t s) {
+                             const double* const* p, const sos_adam_t* h, double* losses, const int* slot,
+                             int count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   const bool step = state != nullptr;
   bat::Args a = {};
@@ -352,7 +353,7 @@ hipError_t launch_step_group(sos_plan_s* const* plans, void* const* W, void* con
     R.pair_off = (const int32_t*)(ws + pl->lay.pair_off);
     R.pair_idx = (const int32_t*)(ws + pl->lay.pair_idx);
     R.pair_pos = (const int32_t*)(ws + pl->lay.pair_pos);
-    R.loss = losses + q;
+    R.loss = losses + (slot ? slot[q] : q);
     R.N = (int)pl->N;
     R.M = (int)pl->M;
     R.k = pl->k;

@@ -301,7 +301,8 @@ hipError_t launch_adam_f32(float* W, float* m, float* v, const float* g, int64_t
                            const sos_adam_t& h, hipStream_t s);
 // grouped serving kernels (batch.hip); at most batch_capacity() problems per call
 int batch_capacity();
+// losses + slot[q] (slot NULL: losses + q) receives problem q's loss
 hipError_t launch_step_group(sos_plan_s* const* plans, void* const* W, void* const* state, const int64_t* t,
-                             const double* const* p, const sos_adam_t* h, double* losses, int count,
-                             hipStream_t s);
+                             const double* const* p, const sos_adam_t* h, double* losses, const int* slot,
+                             int count, hipStream_t s);
 }  // namespace sos
