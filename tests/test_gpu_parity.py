@@ -253,7 +253,19 @@ def test_solve_config_n3d2_fp64():
     res = pl.solve(Wd, to_dev(p, torch.float64), S.Adam(lr=0.1), tol=1e-30, max_steps=2000, check_every=1)
     assert res["steps"] == 2000 and res["status"] == S.NOT_CONVERGED
     assert res["best_rel"] <= 1e-3
-    assert abs(res["best_rel"] - o_rel) <= 0.02 * o_rel
+    # Adam at this step size on this sublinear problem amplifies rounding-level
+    # differences over 2000 steps: the oracle's own best residual moves by
+    # several percent when its start is perturbed at 1e-15, and the GPU sums
+    # in another order (FP64 atomics).  The per-step parity is pinned by the
+    # 50-step trajectory test; here the GPU must land inside the oracle's
+    # spread under such perturbations (with 10% slack on either side).
+    rng = np.random.default_rng(11)
+    pn = np.linalg.norm(p)
+    spread = [o_rel]
+    for _ in range(6):
+        Wp = c.W_init() * (1 + 1e-15 * rng.standard_normal((c.N, c.rank)))
+        spread.append(math.sqrt(O.solve(p, c.n, c.d, Wp, 2000, 0.1).best_loss) / pn)
+    assert 0.9 * min(spread) <= res["best_rel"] <= 1.1 * max(spread), (res["best_rel"], spread)
     L_o, _, _ = O.loss_grad(Wd.cpu().numpy(), p, c.n, c.d)
     assert abs(res["rel"] - math.sqrt(L_o) / np.linalg.norm(p)) <= 1e-9 * res["rel"]
 
