@@ -709,12 +709,10 @@ static hipError_t gram_launch(const sos_plan_s* p, const void* a0, const void* a
   g.kslice = (g.kslice + 63) / 64 * 64;
   splits = (g.K + g.kslice - 1) / g.kslice;
   const size_t sm = 2 * sizeof(Stage<Md>);
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_gram<Md>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  // set on every launch (a host-side setting, cheap next to these kernels):
+  // no shared flag between threads or devices
+  hipError_t e = hipFuncSetAttribute((const void*)k_gram<Md>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+  if (e != hipSuccess) return e;
   k_gram<Md><<<(unsigned)(tiles * splits), kThreads, sm, s>>>(g);
   return hipGetLastError();
 }
@@ -738,12 +736,10 @@ static hipError_t rw_launch(const sos_plan_s* p, void* g, hipStream_t s) {
   a.K = p->Np2; a.N = (int)p->N; a.k = p->k;
   a.g = g; a.g_double = (p->prec == SOS_FP64);
   const size_t sm = 2 * sizeof(Stage<Md>);
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_rw<Md>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  // set on every launch (a host-side setting, cheap next to these kernels):
+  // no shared flag between threads or devices
+  hipError_t e = hipFuncSetAttribute((const void*)k_rw<Md>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+  if (e != hipSuccess) return e;
   dim3 grid((unsigned)(p->Kp2 / BM), (unsigned)(p->Np / BM));
   k_rw<Md><<<grid, kThreads, sm, s>>>(a);
   return hipGetLastError();
