@@ -219,26 +219,40 @@ int plan_create(int n, int d, int rank, int prec, sos_plan_s** out) {
   // are the inverse of the ranking map, built here once (counting sort).
   if (prec == SOS_FP32 && N <= SOS_BATCH_MAX_N) {
     p->batchable = true;
-    std::vector<uint8_t> sum(n);
+    // rank of alpha_i + alpha_j by the closed form, one field term per
+    // variable looked up in a table (the terms depend on (f, value) only)
+    std::vector<int64_t> ft((size_t)n * (D + 1));
+    for (int f = 0; f < n; ++f)
+      for (int v = 0; v <= D; ++v) ft[(size_t)f * (D + 1) + v] = field_term(n, D, f, v);
     auto rank_of = [&](int64_t i, int64_t j) {
-      for (int v = 0; v < n; ++v) sum[v] = (uint8_t)(p->basis[i * n + v] + p->basis[j * n + v]);
-      return rank_closed_form(n, 2 * d, sum.data());
+      const uint8_t* a = &p->basis[i * n];
+      const uint8_t* b = &p->basis[j * n];
+      int u = 0;
+      for (int v = 0; v < n; ++v) u += a[v] + b[v];
+      int64_t r = 0;
+      for (int f = 0; f < n; ++f) {
+        if (f > 0) u -= a[f - 1] + b[f - 1];
+        r += ft[(size_t)f * (D + 1) + u];
+      }
+      return r;
     };
     p->pair_off.assign(M + 1, 0);
-    for (int64_t i = 0; i < N; ++i)
-      for (int64_t j = i; j < N; ++j) ++p->pair_off[rank_of(i, j) + 1];
-    for (int64_t m = 0; m < M; ++m) p->pair_off[m + 1] += p->pair_off[m];
     p->pair_idx.assign(N * (N + 1) / 2, 0);
     p->pair_pos.assign(N * N, 0);
     p->rank_map.assign(N * N, 0);
-    std::vector<int32_t> fill(p->pair_off.begin(), p->pair_off.end() - 1);
     for (int64_t i = 0; i < N; ++i)
       for (int64_t j = i; j < N; ++j) {
         const int64_t m = rank_of(i, j);
-        const int32_t e = fill[m]++;
+        p->rank_map[i * N + j] = p->rank_map[j * N + i] = (int32_t)m;
+        ++p->pair_off[m + 1];
+      }
+    for (int64_t m = 0; m < M; ++m) p->pair_off[m + 1] += p->pair_off[m];
+    std::vector<int32_t> fill(p->pair_off.begin(), p->pair_off.end() - 1);
+    for (int64_t i = 0; i < N; ++i)
+      for (int64_t j = i; j < N; ++j) {
+        const int32_t e = fill[p->rank_map[i * N + j]]++;
         p->pair_idx[e] = (int32_t)((uint32_t)(i * N + j) | (i < j ? 0x80000000u : 0u));
         p->pair_pos[i * N + j] = p->pair_pos[j * N + i] = e;
-        p->rank_map[i * N + j] = p->rank_map[j * N + i] = (int32_t)m;
       }
     L.bG = take((size_t)batch_slices(rank) * p->pair_idx.size() * 8);
     L.pair_pos = take(p->pair_pos.size() * 4);
