@@ -245,6 +245,8 @@ int sos_plan_bind(sos_plan_t p, void* d_ws, size_t ws_bytes, void* stream) {
     SOS_HIP(hipMemcpyAsync(p->ws + p->lay.rank_map, p->rank_map.data(), p->rank_map.size() * 4,
                            hipMemcpyHostToDevice, s), "sos_plan_bind: rank map");
     SOS_HIP(hipMemsetAsync(p->ws + p->lay.bcount, 0, 4, s), "sos_plan_bind: block counter");
+    SOS_HIP(hipMemcpyAsync(p->ws + p->lay.bhdr, &p->bhdr, sizeof(BatchHeader), hipMemcpyHostToDevice, s),
+            "sos_plan_bind: batch header");
   }
   SOS_HIP(hipStreamSynchronize(s), "sos_plan_bind");
   p->bound = true;

@@ -3,7 +3,9 @@
 // per launch of each kernel.  Each problem keeps its own plan workspace
 // (pair lists, partial-result scratch, residual r, R), its own W and its own
 // Adam state; the kernels read all of them through a descriptor table passed
-// by value in the kernel arguments, so a call allocates nothing.
+// by value in the kernel arguments (a few pointers per problem; the plan's
+// sizes and array places come from a header in its workspace, written at
+// bind), so a call allocates nothing.
 //
 // Every block works on one problem, and every sum runs in an order fixed by
 // that problem's shape alone (no floating-point atomics), so a problem's
@@ -38,7 +40,7 @@ namespace bat {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kMaxBatch = 24;
+constexpr int kMaxBatch = 64;
 constexpr int kCoeffChunk = 2048;   // pair values staged in LDS per round of k_b_coeff
 
 struct Req {
@@ -60,14 +62,53 @@ struct Req {
   float bc1, bc2;
 };
 
+// What a launch passes per problem; the plan's constants and array places
+// come from the BatchHeader in its workspace (expand() below).
+struct Desc {
+  const float* W;            // N x k
+  float* m;                  // Adam state (v follows at the header's offset)
+  const double* p;           // M
+  const char* hdr;           // the plan's BatchHeader in its workspace
+  double* loss;
+  float bc1, bc2;
+};
+
 struct Args {
   int count;
   int fwd_off[kMaxBatch + 1];  // prefix sums of gram blocks
   int bwd_off[kMaxBatch + 1];  // prefix sums of backward blocks
   float lr, b1, b2, eps;
-  Req q[kMaxBatch];
+  Desc q[kMaxBatch];
 };
 static_assert(sizeof(Args) <= 4000, "kernel argument block too large");
+
+__device__ __forceinline__ Req expand(const Desc& d) {
+  const BatchHeader& h = *(const BatchHeader*)d.hdr;
+  char* b = const_cast<char*>(d.hdr);
+  Req R;
+  R.W = d.W;
+  R.m = d.m;
+  R.v = (float*)((char*)d.m + h.v);
+  R.p = d.p;
+  R.r = (double*)(b + h.r);
+  R.Gp = (double*)(b + h.Gp);
+  R.pair_pos = (const int32_t*)(b + h.pair_pos);
+  R.rank_map = (const int32_t*)(b + h.rank_map);
+  R.gp = (float*)(b + h.gp);
+  R.part = (double*)(b + h.part);
+  R.count = (unsigned*)(b + h.count);
+  R.pair_off = (const int32_t*)(b + h.pair_off);
+  R.pair_idx = (const int32_t*)(b + h.pair_idx);
+  R.loss = d.loss;
+  R.N = h.N;
+  R.M = h.M;
+  R.k = h.k;
+  R.sg = h.sg;
+  R.sr = h.sr;
+  R.bc1 = d.bc1;
+  R.bc2 = d.bc2;
+  return R;
+}
 
 // problem owning flat block b (off: prefix sums, off[count] = total)
 __device__ __forceinline__ int find_req(const int* off, int count, int b) {
@@ -87,7 +128,7 @@ constexpr int TF = 32, TK = 32;
 __global__ __launch_bounds__(256) void k_b_gram(Args a) {
   __shared__ float As[TF][TK + 1], Bs[TF][TK + 1];
   const int q = find_req(a.fwd_off, a.count, blockIdx.x);
-  const Req& R = a.q[q];
+  const Req R = expand(a.q[q]);
   const int local = blockIdx.x - a.fwd_off[q];
   const int t = local / R.sg, s = local % R.sg;
   int J = 0;
@@ -154,7 +195,7 @@ __device__ __forceinline__ double block_sum256(double x, double* sh4) {
 // Coefficients, residual and the loss; grid (blocks of 256
 // coefficients, problem).
 __global__ __launch_bounds__(256) void k_b_coeff(Args a) {
-  const Req& R = a.q[blockIdx.y];
+  const Req R = expand(a.q[blockIdx.y]);
   const int nb = (R.M + 255) / 256;
   if ((int)blockIdx.x >= nb) return;
   __shared__ double sh4[4];
@@ -224,7 +265,7 @@ __global__ __launch_bounds__(256) void k_b_rw(Args a) {
   __shared__ __align__(16) float Rs[TBI][TBS];   // R_ij, j within the chunk
   __shared__ __align__(16) float Wt[TBL][TBS];   // W_jl stored at [l][j]
   const int q = find_req(a.bwd_off, a.count, blockIdx.x);
-  const Req& R = a.q[q];
+  const Req R = expand(a.q[q]);
   const int local = blockIdx.x - a.bwd_off[q];
   const int t = local / R.sr, s = local % R.sr;
   const int nl = (R.k + TBL - 1) / TBL;
@@ -297,7 +338,7 @@ __global__ __launch_bounds__(256) void k_b_rw(Args a) {
 
 // g = sum of the slices (in slice order), then Adam; grid.y = problem.
 __global__ __launch_bounds__(256) void k_b_adam(Args a) {
-  const Req& R = a.q[blockIdx.y];
+  const Req R = expand(a.q[blockIdx.y]);
   float* W = const_cast<float*>(R.W);
   const int n = R.N * R.k;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
@@ -334,37 +375,23 @@ hipError_t launch_step_group(sos_plan_s* const* plans, void* const* W, void* con
   int maxM = 0, maxNK = 0;
   for (int q = 0; q < count; ++q) {
     const sos_plan_s* pl = plans[q];
-    bat::Req& R = a.q[q];
-    char* ws = pl->ws;
-    R.W = (const float*)W[q];
+    bat::Desc& D = a.q[q];
+    D.W = (const float*)W[q];
     if (step) {
-      R.m = (float*)state[q];
-      R.v = (float*)((char*)state[q] + pl->state_bytes / 4);
-      R.bc1 = (float)(1.0 - pow(h->beta1, (double)t[q]));
-      R.bc2 = (float)(1.0 - pow(h->beta2, (double)t[q]));
+      D.m = (float*)state[q];
+      D.bc1 = (float)(1.0 - pow(h->beta1, (double)t[q]));
+      D.bc2 = (float)(1.0 - pow(h->beta2, (double)t[q]));
     }
-    R.p = p[q];
-    R.r = (double*)(ws + pl->lay.r);
-    R.Gp = (double*)(ws + pl->lay.bG);
-    R.rank_map = (const int32_t*)(ws + pl->lay.rank_map);
-    R.gp = (float*)(ws + pl->lay.bg);
-    R.part = (double*)(ws + pl->lay.bpart);
-    R.count = (unsigned*)(ws + pl->lay.bcount);
-    R.pair_off = (const int32_t*)(ws + pl->lay.pair_off);
-    R.pair_idx = (const int32_t*)(ws + pl->lay.pair_idx);
-    R.pair_pos = (const int32_t*)(ws + pl->lay.pair_pos);
-    R.loss = losses + (slot ? slot[q] : q);
-    R.N = (int)pl->N;
-    R.M = (int)pl->M;
-    R.k = pl->k;
-    R.sg = batch_slices(R.k);
-    R.sr = batch_slices_j(R.N);
-    const int ti = (R.N + bat::TF - 1) / bat::TF;
-    a.fwd_off[q + 1] = a.fwd_off[q] + ti * (ti + 1) / 2 * R.sg;
-    const int bi = (R.N + bat::TBI - 1) / bat::TBI, bl = (R.k + bat::TBL - 1) / bat::TBL;
-    a.bwd_off[q + 1] = a.bwd_off[q] + bi * bl * R.sr;
-    maxM = R.M > maxM ? R.M : maxM;
-    maxNK = R.N * R.k > maxNK ? R.N * R.k : maxNK;
+    D.p = p[q];
+    D.hdr = pl->ws + pl->lay.bhdr;
+    D.loss = losses + (slot ? slot[q] : q);
+    const BatchHeader& H = pl->bhdr;
+    const int ti = (H.N + bat::TF - 1) / bat::TF;
+    a.fwd_off[q + 1] = a.fwd_off[q] + ti * (ti + 1) / 2 * H.sg;
+    const int bi = (H.N + bat::TBI - 1) / bat::TBI, bl = (H.k + bat::TBL - 1) / bat::TBL;
+    a.bwd_off[q + 1] = a.bwd_off[q] + bi * bl * H.sr;
+    maxM = H.M > maxM ? H.M : maxM;
+    maxNK = H.N * H.k > maxNK ? H.N * H.k : maxNK;
   }
   auto blocks = [](int n) {
     const int b = (n + 255) / 256;

@@ -262,9 +262,29 @@ int plan_create(int n, int d, int rank, int prec, sos_plan_s** out) {
     L.bcount = take(4);
     L.pair_off = take(p->pair_off.size() * 4);
     L.pair_idx = take(p->pair_idx.size() * 4);
+    L.bhdr = take(sizeof(BatchHeader));
   }
   L.bytes = off;
   p->state_bytes = round_up((size_t)N * rank * wel, 256) * 4;  // m, v, best W, candidate W
+  if (p->batchable) {
+    BatchHeader& h = p->bhdr;
+    h.N = (int32_t)N;
+    h.M = (int32_t)M;
+    h.k = rank;
+    h.sg = batch_slices(rank);
+    h.sr = batch_slices_j((int)N);
+    h.v = (int64_t)(p->state_bytes / 4);
+    auto rel = [&](size_t at) { return (int64_t)at - (int64_t)L.bhdr; };
+    h.r = rel(L.r);
+    h.Gp = rel(L.bG);
+    h.pair_pos = rel(L.pair_pos);
+    h.rank_map = rel(L.rank_map);
+    h.gp = rel(L.bg);
+    h.part = rel(L.bpart);
+    h.count = rel(L.bcount);
+    h.pair_off = rel(L.pair_off);
+    h.pair_idx = rel(L.pair_idx);
+  }
   *out = p;
   return SOS_OK;
 }

@@ -190,7 +190,18 @@ struct Layout {
   size_t bcount = 0;             // u32 arrival counter of those blocks (zero between calls)
   size_t pair_off = 0;           // M + 1 int32: pairs of coefficient m are pair_idx[off[m] .. off[m+1])
   size_t pair_idx = 0;           // N (N + 1) / 2 int32: i * N + j (i <= j), bit 31 set when i < j
+  size_t bhdr = 0;               // BatchHeader: sizes and the places of the arrays above
   size_t bytes = 0;
+};
+
+// A serving plan's constants, kept in its workspace (written at bind) so that
+// a grouped launch passes only a few pointers per problem.  Array places are
+// byte offsets from the header itself; v is the byte offset of the second
+// Adam moment from the first inside a problem's state.
+struct BatchHeader {
+  int32_t N, M, k, sg, sr, pad;
+  int64_t v;
+  int64_t r, Gp, pair_pos, rank_map, gp, part, count, pair_off, pair_idx;
 };
 
 }  // namespace sos
@@ -212,6 +223,7 @@ struct sos_plan_s {
   int ntiles256 = 0;               // upper-triangle tiles of 256 x 256
   std::vector<int32_t> tile_list;  // 2 * ntiles256
   bool batchable = false;          // grouped (serving) calls supported
+  sos::BatchHeader bhdr{};         // uploaded to lay.bhdr at bind (batchable plans)
   // operand copies left by the last fused step (single-product backward with
   // Adam in its epilogue): valid for W pointer copies_W and forward mode
   // copies_mode until another call rebuilds the copies

@@ -10,7 +10,7 @@ stops improving (``stall_checks`` checks in a row without a factor
 The server keeps every active request's W, Adam state and plan workspace
 resident on the GPU.  Each iteration advances all active requests by
 ``check_every`` steps with grouped launches (``sos_step_batch``: one launch
-per kernel type for up to 24 requests), then reads all their losses with one
+per kernel type for up to 64 requests), then reads all their losses with one
 device-to-host copy.  Requests that arrive meanwhile are admitted as soon as
 a slot is free and their device footprint fits the HBM budget, so they join
 the work already on the device instead of waiting for a batch to drain.
