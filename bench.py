@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--net-case", choices=("one", "many", "uniform"), default="one",
                     help="net: one x_i^4 coefficient set to --net-big, every x_i^4 and x_i^2 x_j^2 raised by "
                          "U[0, --net-big], or no perturbation")
+    ap.add_argument("--net-rollback", type=float, default=0.0,
+                    help="net: restore the best weights and halve the step size when a check's residual exceeds "
+                         "this multiple of the best (0: plain Adam)")
     ap.add_argument("--net-big", type=float, default=1e4,
                     help="net: the size of the perturbation in the paper's units (before the 1/N scaling)")
     ap.add_argument("--requests", type=int, default=4096, help="serve: requests in the stream")
@@ -285,7 +288,7 @@ def net_mode(a, S, torch):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = net.solve(p, S.Adam(lr=lr), tol=a.tol, max_steps=a.max_steps, check_every=50, ladder=False,
-                        single_backward=False, train_first=train_first)
+                        single_backward=False, train_first=train_first, rollback_ratio=a.net_rollback)
         torch.cuda.synchronize()
         out[label] = {"seconds": round(time.perf_counter() - t0, 3), "steps": res["steps"], "rel": res["rel"],
                       "best_rel": res["best_rel"],
@@ -295,7 +298,8 @@ def net_mode(a, S, torch):
                       "unit": "s", "n_gpus": 1, "data": "synthetic",
                       "config": {"workload": f"forms n={n}: plan ({n - 1}, 2) N={N}, network k={N}, "
                                              f"p = m_2^T B0 B0^T m_2 (B0 uniform), {what}",
-                                 "precision": "fp64", "lr": lr, "max_steps": a.max_steps},
+                                 "precision": "fp64", "lr": lr, "max_steps": a.max_steps,
+                                 "rollback_ratio": a.net_rollback},
                       "results": out}), flush=True)
 
 

@@ -288,11 +288,15 @@ int sos_net_step(sos_plan_t plan, int n, int m, float* d_At, float* d_Bt, void* 
 
 /* Adam on the weights from their current values until the FP64-verified
  * relative residual of W = net(At, Bt) is <= opts->tol or opts->max_steps
- * (uses tol, max_steps, check_every, ladder, switch_rel, lr_exact and
- * single_backward of opts: the fast forward until rel <= switch_rel, then
- * the exact forward with step size lr_exact).  The Adam moments are zeroed
- * first.  h_res as for sos_solve (steps, exact_steps, the verified rel of the
- * final weights).  Blocks until done.                                      */
+ * (uses tol, max_steps, check_every, ladder, switch_rel, lr_exact,
+ * rollback_ratio and single_backward of opts: the fast forward until
+ * rel <= switch_rel, then the exact forward with step size lr_exact).  As in
+ * sos_solve, success is judged on the best weights seen at a check, which
+ * are returned in d_At, d_Bt; a check whose rel exceeds rollback_ratio times
+ * the best restores the best weights and halves the step size (0: off).  The
+ * Adam moments are zeroed first; d_state holds two extra copies of the
+ * weights for this.  h_res as for sos_solve (steps, exact_steps, the
+ * verified rel of the returned weights).  Blocks until done.               */
 int sos_net_solve(sos_plan_t plan, int n, int m, float* d_At, float* d_Bt, void* d_state, const double* d_p,
                   const sos_adam_t* adam, const sos_solve_opts_t* opts, int train_first, sos_result_t* h_res,
                   void* stream);

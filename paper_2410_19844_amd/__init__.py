@@ -321,10 +321,10 @@ class Net:
         return loss
 
     def solve(self, p, adam: Adam, tol=1e-8, max_steps=10000, check_every=10, ladder=True, switch_rel=3e-6,
-              lr_exact=0.0, single_backward=True, train_first=True, stream=None):
+              lr_exact=0.0, single_backward=True, train_first=True, rollback_ratio=0.0, stream=None):
         self.plan._p(p)
-        opts = _SolveOpts(tol, max_steps, check_every, 1 if ladder else 0, 0, 0.0, switch_rel, lr_exact, 0.0,
-                          1 if single_backward else 0, 0, 0.0)
+        opts = _SolveOpts(tol, max_steps, check_every, 1 if ladder else 0, 0, 0.0, switch_rel, lr_exact,
+                          rollback_ratio, 1 if single_backward else 0, 0, 0.0)
         res = _Result()
         _check(_lib.sos_net_solve(self.plan._h, self.n, self.m, _ptr(self.At), _ptr(self.Bt), _ptr(self.state),
                                   _ptr(p), ctypes.byref(adam.c()), ctypes.byref(opts), 1 if train_first else 0,

@@ -516,7 +516,9 @@ int sos_loss_batch(const sos_plan_t* plans, const void* const* d_W, const double
 
 namespace {
 struct NetLayout {
-  size_t rowpair, rowmap, mA, vA, mB, vB, W, P, gW, dA, dB, dAz, bytes;
+  size_t rowpair, rowmap, mA, vA, mB, vB, W, P, gW, dA, dB, dAz;
+  size_t snapA[2], snapB[2];  // sos_net_solve: the best weights and the snapshot of a check step
+  size_t bytes;
 };
 
 NetLayout net_layout(const sos_plan_s* p, int n, int m) {
@@ -537,6 +539,10 @@ NetLayout net_layout(const sos_plan_s* p, int n, int m) {
   L.dA = take(nm * 4);
   L.dB = take(nm * k * 4);
   L.dAz = take((size_t)n * nm * we);
+  for (int q = 0; q < 2; ++q) {
+    L.snapA[q] = take(nm * 4);
+    L.snapB[q] = take(nm * k * 4);
+  }
   L.bytes = off;
   return L;
 }
@@ -657,8 +663,9 @@ int sos_net_solve(sos_plan_t p, int n, int m, float* d_At, float* d_Bt, void* d_
   if (int rc = net_check(p, n, m, "sos_net_solve")) return rc;
   if (int rc = check_adam(adam, "sos_net_solve")) return rc;
   if (!d_At || !d_Bt || !d_state || !d_p || !o || !res) return set_error(SOS_EINVAL, "sos_net_solve: NULL argument");
-  if (o->max_steps < 0 || o->check_every < 1 || !(o->tol >= 0) || !(o->lr_exact >= 0))
-    return set_error(SOS_EINVAL, "sos_net_solve: needs max_steps >= 0, check_every >= 1, tol and lr_exact >= 0");
+  if (o->max_steps < 0 || o->check_every < 1 || !(o->tol >= 0) || !(o->lr_exact >= 0) || !(o->rollback_ratio >= 0))
+    return set_error(SOS_EINVAL, "sos_net_solve: needs max_steps >= 0, check_every >= 1, tol, lr_exact and "
+                                 "rollback_ratio >= 0");
   hipStream_t s = (hipStream_t)stream;
   std::memset(res, 0, sizeof(*res));
   const NetLayout L = net_layout(p, n, m);
@@ -673,31 +680,59 @@ int sos_net_solve(sos_plan_t p, int n, int m, float* d_At, float* d_Bt, void* d_
   const double pnorm = pn2 > 0 ? std::sqrt(pn2) : 1.0;
   sos_adam_t h = *adam;
   const bool can_ladder = o->ladder != 0;
+  const int64_t nm = (int64_t)n * m;
+  const size_t abytes = (size_t)nm * 4, bbytes = (size_t)nm * p->k * 4;
+  // best weights (as measured at a check) and the snapshot of the weights a
+  // check step starts from; the two swap roles when the snapshot is better
+  int best = 0;
+  bool have_best = false;
   int phase = 0;
   int64_t t = 0, exact_steps = 0;
-  double loss = 0, best = std::numeric_limits<double>::infinity();
+  double loss = 0, best_rel = std::numeric_limits<double>::infinity();
   bool done = false;
+  auto verify = [&](int which, double* vrel) -> int {
+    void* W = st + L.W;
+    const float* A = which < 0 ? d_At : (const float*)(st + L.snapA[which]);
+    const float* B = which < 0 ? d_Bt : (const float*)(st + L.snapB[which]);
+    if (int rc = net_forward_W(p, n, m, A, B, st, L, W, s)) return rc;
+    return sos_verify(p, W, d_p, vrel, nullptr, stream);
+  };
   while (t < o->max_steps && !done) {
     ++t;
+    const bool check = t % o->check_every == 0 || t == o->max_steps;
+    if (check) {  // the loss this step reports belongs to the weights it starts from
+      SOS_HIP(hipMemcpyAsync(st + L.snapA[1 - best], d_At, abytes, hipMemcpyDeviceToDevice, s), "net: snapshot A");
+      SOS_HIP(hipMemcpyAsync(st + L.snapB[1 - best], d_Bt, bbytes, hipMemcpyDeviceToDevice, s), "net: snapshot B");
+    }
     const int flags = (phase ? SOS_FLAG_EXACT_FORWARD : 0) | (o->single_backward ? SOS_FLAG_SINGLE_BACKWARD : 0);
     if (int rc = net_step(p, n, m, d_At, d_Bt, st, L, t, d_p, h, sc + 0, flags, train_first != 0, s)) return rc;
     if (phase) ++exact_steps;
-    if (t % o->check_every && t != o->max_steps) continue;
+    if (!check) continue;
     SOS_HIP(hipMemcpyAsync(&loss, sc + 0, 8, hipMemcpyDeviceToHost, s), "sos_net_solve: loss");
     SOS_HIP(hipStreamSynchronize(s), "sos_net_solve");
-    const double rel = std::sqrt(std::max(loss, 0.0)) / pnorm;
-    if (!std::isfinite(rel)) return set_error(SOS_ENUMERIC, "sos_net_solve: loss is not finite");
-    best = std::min(best, rel);
+    const double rel = std::isfinite(loss) ? std::sqrt(std::max(loss, 0.0)) / pnorm
+                                           : std::numeric_limits<double>::infinity();
+    if (!std::isfinite(rel) && !have_best) return set_error(SOS_ENUMERIC, "sos_net_solve: loss is not finite");
+    if (rel < best_rel) {
+      best_rel = rel;
+      best = 1 - best;
+      have_best = true;
+    }
+    if (!std::isfinite(rel) || (o->rollback_ratio > 0 && rel > o->rollback_ratio * best_rel)) {
+      // diverging: back to the best weights with half the step size
+      SOS_HIP(hipMemcpyAsync(d_At, st + L.snapA[best], abytes, hipMemcpyDeviceToDevice, s), "net: rollback A");
+      SOS_HIP(hipMemcpyAsync(d_Bt, st + L.snapB[best], bbytes, hipMemcpyDeviceToDevice, s), "net: rollback B");
+      h.lr *= 0.5;
+      continue;
+    }
     if (can_ladder && phase == 0 && rel <= o->switch_rel) {
       phase = 1;
       if (o->lr_exact > 0) h.lr = o->lr_exact;
     }
     if (rel <= o->tol) {
-      // certify the current weights: W = net(A, B), FP64 forward
-      void* W = st + L.W;
-      if (int rc = net_forward_W(p, n, m, d_At, d_Bt, st, L, W, s)) return rc;
+      // certify the best weights: W = net(A, B), FP64 forward
       double vrel = 0;
-      if (int rc = sos_verify(p, W, d_p, &vrel, nullptr, stream)) return rc;
+      if (int rc = verify(best, &vrel)) return rc;
       if (vrel <= o->tol) done = true;
       else if (can_ladder && phase == 0) {
         phase = 1;
@@ -705,15 +740,17 @@ int sos_net_solve(sos_plan_t p, int n, int m, float* d_At, float* d_Bt, void* d_
       }
     }
   }
-  void* W = st + L.W;
-  if (int rc = net_forward_W(p, n, m, d_At, d_Bt, st, L, W, s)) return rc;
+  if (have_best) {  // return the best weights
+    SOS_HIP(hipMemcpyAsync(d_At, st + L.snapA[best], abytes, hipMemcpyDeviceToDevice, s), "net: best A");
+    SOS_HIP(hipMemcpyAsync(d_Bt, st + L.snapB[best], bbytes, hipMemcpyDeviceToDevice, s), "net: best B");
+  }
   double vrel = 0;
-  if (int rc = sos_verify(p, W, d_p, &vrel, nullptr, stream)) return rc;
+  if (int rc = verify(-1, &vrel)) return rc;
   res->steps = t;
   res->exact_steps = exact_steps;
   res->loss = loss;
   res->rel = vrel;
-  res->best_rel = best;
+  res->best_rel = best_rel;
   res->phase = phase ? 2 : 0;
   res->status = vrel <= o->tol ? SOS_OK : SOS_NOT_CONVERGED;
   return res->status;
