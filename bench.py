@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--net-case", choices=("one", "many", "uniform"), default="one",
                     help="net: one x_i^4 coefficient set to --net-big, every x_i^4 and x_i^2 x_j^2 raised by "
                          "U[0, --net-big], or no perturbation")
+    ap.add_argument("--net-seeds", type=int, default=1, help="net: problems (seeds) per arm")
     ap.add_argument("--net-rollback", type=float, default=0.0,
                     help="net: restore the best weights and halve the step size when a check's residual exceeds "
                          "this multiple of the best (0: plain Adam)")
@@ -243,9 +244,12 @@ def net_mode(a, S, torch):
     The network ||B Z A x||^2 (k = N) is trained by Adam from a seeded random
     start to an FP64-verified relative residual of tol, three ways: A = I
     fixed (m = n), A general (m = n, trained), A of size 2n x n (trained).
-    FP64 plan: W = net(A, B) is formed from exact products.  Reported: the
-    time, the steps, the final verified residual and the smallest residual
-    seen at a check (the paper's measure of success is the minimal error).
+    FP64 plan: W = net(A, B) is formed from exact products.  Reported per arm:
+    the time, the steps, the final verified residual and the smallest
+    residual seen at a check (the paper's measure of success is the minimal
+    error).  With --net-seeds K > 1, K problems (B0, the perturbation and the
+    starts all drawn from seed-dependent streams) and a summary per arm:
+    certified count, median time of the certified runs, median best residual.
     """
     import numpy as np
 
@@ -256,50 +260,65 @@ def net_mode(a, S, torch):
     N = plan0.N
     ex = plan0.exponents(1).astype(np.int64)                  # coefficient monomials of the plan (n - 1, 2)
     ex = np.hstack([ex, 4 - ex.sum(1, keepdims=True)])        # as quartic forms in n variables (x_n = 1)
-    B0 = torch.tensor(uniform((N, N), 0, -N ** -0.5, N ** -0.5), dtype=torch.float32, device=dev)
-    pl0 = S.Plan(n - 1, 2, N, "fp32")
-    zeros = torch.zeros(pl0.M, dtype=torch.float64, device=dev)
-    _, _, p = pl0.loss_grad(B0, zeros, grad=False, want_r=True, exact=True)
-    del pl0, B0
-    rng = np.random.default_rng(12)
-    if a.net_case == "one":
-        i = int(rng.integers(n))
-        pos = np.flatnonzero(ex[:, i] == 4)
-        p[torch.as_tensor(pos, device=dev)] = a.net_big / N
-        what = f"c(x_{i + 1}^4) = {a.net_big:g}/N"
-    elif a.net_case == "many":
-        pos = np.flatnonzero((ex == 4).any(1) | ((ex == 2).sum(1) == 2))
-        add = rng.uniform(0, a.net_big, len(pos)) / N
-        p[torch.as_tensor(pos, device=dev)] += torch.as_tensor(add, device=dev)
-        what = f"c(x_i^4), c(x_i^2 x_j^2) += U[0, {a.net_big:g}]/N"
-    else:
-        what = "uniform coefficients"
     lr = a.lr if a.lr is not None else 3e-3
-    out = {}
-    for label, m, train_first in (("A=I", n, False), ("A general", n, True), ("A 2n x n", 2 * n, True)):
-        Bt = torch.tensor(uniform((n * m, N), 1, -N ** -0.5, N ** -0.5), dtype=torch.float32, device=dev)
-        if train_first:
-            # entries of variance 1/m, so that P = A^T B has the scale it has for A = I
-            At = torch.tensor(uniform((n, m), 2, -(3 / m) ** 0.5, (3 / m) ** 0.5), dtype=torch.float32,
-                              device=dev)
+    arms = (("A=I", n, False), ("A general", n, True), ("A 2n x n", 2 * n, True))
+    runs = {label: [] for label, _, _ in arms}
+    for sd in range(a.net_seeds):
+        base = 100 * sd                                       # seed 0 reproduces the single-problem run
+        B0 = torch.tensor(uniform((N, N), base, -N ** -0.5, N ** -0.5), dtype=torch.float32, device=dev)
+        pl0 = S.Plan(n - 1, 2, N, "fp32")
+        zeros = torch.zeros(pl0.M, dtype=torch.float64, device=dev)
+        _, _, p = pl0.loss_grad(B0, zeros, grad=False, want_r=True, exact=True)
+        del pl0, B0
+        rng = np.random.default_rng(12 + base)
+        if a.net_case == "one":
+            i = int(rng.integers(n))
+            pos = np.flatnonzero(ex[:, i] == 4)
+            p[torch.as_tensor(pos, device=dev)] = a.net_big / N
+            what = f"c(x_i^4) = {a.net_big:g}/N for a random i" if a.net_seeds > 1 else \
+                f"c(x_{i + 1}^4) = {a.net_big:g}/N"
+        elif a.net_case == "many":
+            pos = np.flatnonzero((ex == 4).any(1) | ((ex == 2).sum(1) == 2))
+            add = rng.uniform(0, a.net_big, len(pos)) / N
+            p[torch.as_tensor(pos, device=dev)] += torch.as_tensor(add, device=dev)
+            what = f"c(x_i^4), c(x_i^2 x_j^2) += U[0, {a.net_big:g}]/N"
         else:
-            At = torch.eye(n, m, dtype=torch.float32, device=dev)
-        net = S.Net(n, m, N, "fp64", At=At, Bt=Bt)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = net.solve(p, S.Adam(lr=lr), tol=a.tol, max_steps=a.max_steps, check_every=50, ladder=False,
-                        single_backward=False, train_first=train_first, rollback_ratio=a.net_rollback)
-        torch.cuda.synchronize()
-        out[label] = {"seconds": round(time.perf_counter() - t0, 3), "steps": res["steps"], "rel": res["rel"],
-                      "best_rel": res["best_rel"],
-                      "status": "certified" if res["status"] == 0 else "not certified"}
-        del net
+            what = "uniform coefficients"
+        for label, m, train_first in arms:
+            Bt = torch.tensor(uniform((n * m, N), base + 1, -N ** -0.5, N ** -0.5), dtype=torch.float32, device=dev)
+            if train_first:
+                # entries of variance 1/m, so that P = A^T B has the scale it has for A = I
+                At = torch.tensor(uniform((n, m), base + 2, -(3 / m) ** 0.5, (3 / m) ** 0.5), dtype=torch.float32,
+                                  device=dev)
+            else:
+                At = torch.eye(n, m, dtype=torch.float32, device=dev)
+            net = S.Net(n, m, N, "fp64", At=At, Bt=Bt)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = net.solve(p, S.Adam(lr=lr), tol=a.tol, max_steps=a.max_steps, check_every=50, ladder=False,
+                            single_backward=False, train_first=train_first, rollback_ratio=a.net_rollback)
+            torch.cuda.synchronize()
+            runs[label].append({"seconds": round(time.perf_counter() - t0, 3), "steps": res["steps"],
+                                "rel": res["rel"], "best_rel": res["best_rel"],
+                                "status": "certified" if res["status"] == 0 else "not certified"})
+            del net
+        print(f"seed {sd}: " + ", ".join(f"{k}: {v[-1]['status']}" for k, v in runs.items()),
+              file=sys.stderr, flush=True)
+    if a.net_seeds == 1:
+        out = {k: v[0] for k, v in runs.items()}
+    else:
+        out = {}
+        for k, v in runs.items():
+            ok = [r["seconds"] for r in v if r["status"] == "certified"]
+            out[k] = {"certified": f"{len(ok)}/{len(v)}",
+                      "median_seconds_certified": float(np.median(ok)) if ok else None,
+                      "median_best_rel": float(np.median([r["best_rel"] for r in v])), "runs": v}
     print(json.dumps({"metric": f"network time-to-rel-residual {a.tol:g}, quartic forms in {n} variables",
                       "unit": "s", "n_gpus": 1, "data": "synthetic",
                       "config": {"workload": f"forms n={n}: plan ({n - 1}, 2) N={N}, network k={N}, "
                                              f"p = m_2^T B0 B0^T m_2 (B0 uniform), {what}",
                                  "precision": "fp64", "lr": lr, "max_steps": a.max_steps,
-                                 "rollback_ratio": a.net_rollback},
+                                 "rollback_ratio": a.net_rollback, "seeds": a.net_seeds},
                       "results": out}), flush=True)
 
 
