@@ -527,8 +527,8 @@ template <int MODE>
 __global__ __launch_bounds__(256) void k_gather_sym(RankTab rk, const float* __restrict__ r32, int N, int64_t Np,
                                                     int64_t ld, int T2, int64_t nup, void* R_hi, void* R_lo) {
   __shared__ float V[64][65];
-  __shared__ int32_t Tab[kStageTabMax];            // field terms (dense) or binomials (sparse)
   __shared__ uint32_t Cj[64 * kMaxWords];          // codes of the tile's 64 columns
+  extern __shared__ int32_t Tab[];                 // field terms (dense) or binomials (sparse): ntab entries
   const int64_t ps = panel_stride(ld / kBlkK, 2);
   const int il = threadIdx.x >> 2, jc = (threadIdx.x & 3) * 16;
   const int64_t b = blockIdx.x;
@@ -761,12 +761,15 @@ hipError_t launch_gather(const sos_plan_s* p, bool split, hipStream_t s) {
   const int64_t nup = (int64_t)T2 * (T2 + 1) / 2;
   const int64_t blocks = nup + (p->Np - p->Np2) / 64 * T2;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  // the table is sized to the plan (1 KB for dense codes), so more blocks fit a CU
+  const size_t tab = (size_t)rk.ntab * 4;
+  if (rk.ntab > kStageTabMax) return hipErrorInvalidValue;
   if (p->prec == SOS_FP32)
-    k_gather_sym<1><<<(unsigned)blocks, 256, 0, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, T2, nup, Rh, Rl);
+    k_gather_sym<1><<<(unsigned)blocks, 256, tab, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, T2, nup, Rh, Rl);
   else if (split)
-    k_gather_sym<2><<<(unsigned)blocks, 256, 0, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, T2, nup, Rh, Rl);
+    k_gather_sym<2><<<(unsigned)blocks, 256, tab, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, T2, nup, Rh, Rl);
   else
-    k_gather_sym<3><<<(unsigned)blocks, 256, 0, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, T2, nup, Rh, Rl);
+    k_gather_sym<3><<<(unsigned)blocks, 256, tab, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, T2, nup, Rh, Rl);
   return hipGetLastError();
 }
 
