@@ -5,7 +5,8 @@ L(W) = ||coeff(m_d^T W W^T m_d) - p||^2 from its own starting W) until its
 FP64-verified relative residual ||r|| / ||p|| reaches ``tol`` (verdict
 "sos": the returned W is the certificate, eq. basicsos), its best residual
 stops improving (``stall_checks`` checks in a row without a factor
-``stall_ratio``), or its step budget runs out (verdict "not certified").
+``stall_ratio``), its step budget runs out, or its loss turns non-finite
+(verdict "not certified").
 
 The server keeps every active request's W, Adam state and plan workspace
 resident on the GPU.  Each iteration advances all active requests by
@@ -50,7 +51,7 @@ class Request:
 class Result:
     id: int
     verdict: str                 # "sos" or "not certified"
-    reason: str                  # "certified", "stalled", "budget"
+    reason: str                  # "certified", "stalled", "budget", "nonfinite"
     rel: float                   # FP64-verified ||r|| / ||p|| of W (certificate) or best seen
     steps: int
     arrival: float
@@ -192,9 +193,12 @@ class Server:
             L = losses[:len(active)].cpu().numpy()        # one device-to-host copy per check
             done, cand = [], []
             for a, x in zip(active, L):
-                rel = math.sqrt(max(float(x), 0.0)) / a.pnorm if a.pnorm > 0 else math.sqrt(max(float(x), 0.0))
-                if not math.isfinite(rel):
-                    rel = math.inf
+                x = float(x)
+                if not math.isfinite(x):
+                    # the loss went NaN or infinite: nothing can be certified from here
+                    done.append((a, "nonfinite"))
+                    continue
+                rel = math.sqrt(max(x, 0.0)) / a.pnorm if a.pnorm > 0 else math.sqrt(max(x, 0.0))
                 if rel <= self.tol:
                     cand.append(a)
                     continue
