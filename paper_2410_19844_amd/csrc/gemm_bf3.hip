@@ -31,7 +31,9 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int TM = 256;
 constexpr int BK = 16;            // K per slot (one MFMA k-step, one block of the blocked layout)
 constexpr int WM = 128;           // rows of the output tile per wave
-constexpr int WN = 128;           // columns of the output tile per wave
+constexpr int WN = 64;            // columns of the output tile per wave: 8 waves of 128 x 64, two per SIMD
+                                  // (128 accumulator registers each), so one wave's MFMAs cover the
+                                  // other's waits
 constexpr int BI = WM / 32, BJ = WN / 32;     // 32 x 32 MFMA blocks per wave
 constexpr int WGN = TM / WN;                  // waves along the column direction
 constexpr int NWAVES = (TM / WM) * WGN;
@@ -453,11 +455,12 @@ __global__ __launch_bounds__(NT) void k_rw_adam_bf3(RwAdamArgs a) {
     // takes its elements 8 at a time, and the loads of the next 8 are issued
     // before the current 8 are computed, so HBM latency overlaps the work.
     constexpr int PER = QROWS * TM / NT;
-    float wv[2][8], mv[2][8], vv[2][8];
+    constexpr int EB = NWAVES > 4 ? 4 : 8;   // elements per fetch batch (register budget at 8 waves)
+    float wv[2][EB], mv[2][EB], vv[2][EB];
     auto fetch = [&](int b8, int buf) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = threadIdx.x + NT * (8 * b8 + u);
+      for (int u = 0; u < EB; ++u) {
+        const int e = threadIdx.x + NT * (EB * b8 + u);
         const int64_t i = (int64_t)I * TM + qq * QROWS + e / TM, l = (int64_t)L * TM + e % TM;
         wv[buf][u] = mv[buf][u] = vv[buf][u] = 0.f;
         if (i < r.N && l < r.k) {
@@ -470,12 +473,12 @@ __global__ __launch_bounds__(NT) void k_rw_adam_bf3(RwAdamArgs a) {
     };
     fetch(0, 0);
 #pragma unroll
-    for (int b8 = 0; b8 < PER / 8; ++b8) {
+    for (int b8 = 0; b8 < PER / EB; ++b8) {
       const int buf = b8 & 1;
-      if (b8 + 1 < PER / 8) fetch(b8 + 1, buf ^ 1);
+      if (b8 + 1 < PER / EB) fetch(b8 + 1, buf ^ 1);
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = threadIdx.x + NT * (8 * b8 + u);
+      for (int u = 0; u < EB; ++u) {
+        const int e = threadIdx.x + NT * (EB * b8 + u);
         const int64_t i = (int64_t)I * TM + qq * QROWS + e / TM, l = (int64_t)L * TM + e % TM;
         float w = 0.f;
         if (i < r.N && l < r.k) {

@@ -16,8 +16,10 @@ RES = os.path.join(os.path.dirname(__file__), "..", "paper_2410_19844_amd", "_bu
 
 # kernel name fragment -> largest scratch allowed (bytes per lane)
 EPILOGUE_SPILLS = {
-    "k_gram_bf3": 128,   # accumulators of the second row half, kept across the first half's scatter
-    "k_rw_bf3": 128,     # the same in the unfused R W epilogue
+    "k_gram_bf3": 128,     # accumulators of the second row half, kept across the first half's scatter
+    "k_rw_bf3": 128,       # the same in the unfused R W epilogue
+    "k_rw_adam_bf3": 64,   # a few W / m / v addresses in the Adam epilogue (two waves per SIMD leave
+                           # 256 registers per wave)
 }
 
 HOT = ["k_gram_bf3", "k_rw_adam_bf3", "k_gram_x64", "k_gather_sym", "k_gramINS_4MF32", "k_gramINS_4MF64",
