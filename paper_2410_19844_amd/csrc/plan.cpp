@@ -174,20 +174,9 @@ int plan_create(int n, int d, int rank, int prec, sos_plan_s** out) {
   p->Kp2 = round_up(rank, kPadRows);
   const size_t wel = (prec == SOS_FP64) ? 8 : 4;          // W / gradient element
   const size_t oel = (prec == SOS_FP64) ? 8 : (prec == SOS_FP32 ? 4 : 2);  // operand element
-  // Upper-triangle tiles of 256 rows, ordered by 8 x 8 super-blocks so that a
-  // run of consecutive tiles shares at most 16 operand panels.
-  {
-    const int T = (int)(p->Np / 256), SB = 8;
-    for (int P = 0; P * SB < T; ++P)
-      for (int Q = P; Q * SB < T; ++Q)
-        for (int J = Q * SB; J < std::min(T, (Q + 1) * SB); ++J)
-          for (int I = P * SB; I < std::min(T, (P + 1) * SB); ++I)
-            if (I <= J) {
-              p->tile_list.push_back(I);
-              p->tile_list.push_back(J);
-            }
-    p->ntiles256 = (int)(p->tile_list.size() / 2);
-  }
+  // upper-triangle tiles of 256 rows in the gram's locality order
+  sos::gram_tile_order((int)(p->Np / 256), p->tile_list);
+  p->ntiles256 = (int)(p->tile_list.size() / 2);
   Layout& L = p->lay;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = round_up(off + bytes, 256); return o; };

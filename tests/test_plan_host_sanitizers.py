@@ -38,5 +38,5 @@ def test_plan_builder_under_sanitizers(tmp_path):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
     run = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
     assert run.returncode == 0, (run.stdout + run.stderr)[-3000:]
-    assert "bad ranks 0" in run.stdout
+    assert "bad ranks 0 bad tiles 0" in run.stdout
     assert "ERROR: AddressSanitizer" not in run.stderr and "runtime error" not in run.stderr
