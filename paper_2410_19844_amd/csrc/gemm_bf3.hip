@@ -291,6 +291,13 @@ __device__ __forceinline__ int xcd_order(int b, int nb) {
   return (xcd < rem) ? xcd * (q + 1) + local : rem * (q + 1) + (xcd - rem) * q + local;
 }
 
+// Tile-rows per group in the R W GEMMs' order (column-major inside a group).
+// Each XCD runs a contiguous run of about 32 tiles, so a group of 6 keeps
+// them on about 11 operand panels.  At n = 12, d = 6 (73 x 73 tiles) groups
+// of 6 read ~29 GB per fused R W + Adam against ~34 GB for 8 and ran 1%
+// faster; 4 read as little but ran as 8, and 12 or 16 ran 2-4% slower.
+constexpr int kRwGroup = 6;
+
 
 struct GramArgs {
   Operands o;
@@ -358,8 +365,8 @@ __global__ __launch_bounds__(NT) void k_rw_bf3(RwArgs a) {
   SOS_BF3_BUFFERS;
   const int nb = a.TI * a.TL;
   const int v = xcd_order(blockIdx.x, nb);
-  // grouped order: 8 tile-rows at a time, column-major inside the group
-  constexpr int GROUP = 8;
+  // grouped order: kRwGroup tile-rows at a time, column-major inside the group
+  constexpr int GROUP = kRwGroup;
   const int per_group = GROUP * a.TL;
   const int gidx = v / per_group, first = gidx * GROUP;
   const int rows = min(GROUP, a.TI - first);
@@ -421,7 +428,7 @@ __global__ __launch_bounds__(NT) void k_rw_adam_bf3(RwAdamArgs a) {
   const RwArgs& r = a.rw;
   const int nb = r.TI * r.TL;
   const int v = xcd_order(blockIdx.x, nb);
-  constexpr int GROUP = 8;
+  constexpr int GROUP = kRwGroup;
   const int per_group = GROUP * r.TL;
   const int gidx = v / per_group, first = gidx * GROUP;
   const int rows = min(GROUP, r.TI - first);
