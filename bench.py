@@ -34,8 +34,11 @@ sys.path.insert(0, ROOT)
 
 PEAKS_TFLOPS = {"bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6}
 # Adam step sizes (bulk, exact-forward finisher) per workload, chosen by a
-# short sweep of time to 1e-8 and then frozen
-LR_DEFAULTS = {"n12d6": (3e-3, 1e-3), "q100": (3e-3, 3e-3)}
+# short sweep of time to 1e-8 and then frozen.  The q100 finisher takes the
+# middle of the range (1.5e-3 to 2.5e-3) where the step count does not move
+# when the rounding order of the forward's sums changes; at 3e-3 it swings
+# between about 500 and 2200 steps.
+LR_DEFAULTS = {"n12d6": (3e-3, 1e-3), "q100": (3e-3, 2e-3)}
 DTYPE = {"bf16x3": "bf16", "fp32": "fp32", "fp64": "fp64"}
 
 
