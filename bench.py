@@ -3,7 +3,16 @@
 Default: one Adam step of the whole path (split, gram-scatter forward, loss,
 R gather, R W backward, Adam) at n=12, d=6 (N = 18,564 basis monomials,
 M = 2,704,156 coefficients, rank k = N), split-bf16 contractions, FP32
-master W, FP64 residual.  Prints one JSON line.
+master W, FP64 residual.  Prints one JSON line.  Besides the step rate of
+the timed configuration (split-bf16 forward, one-product backward fused with
+Adam), the default line carries, each measured outside the timed region:
+  split_backward   ms per step with the three-product (hi/lo) backward;
+  ttt              time to an FP64-verified relative residual of 1e-8 from
+                   the same start, mixed ladder and plain FP32 form;
+  serving          a 1024-request serving stream: closed-loop solves/s and
+                   Poisson p50 / p99 latency;
+  cpu_baseline     the FP64 oracle on a row sample of one step.
+(--no-ttt, --no-serve, --no-cpu-baseline skip them.)
 
   python bench.py [--steps K] [--warmup W] [--precision bf16x3|fp32|fp64]
                   [--workload n12d6|n10d5|n6d4|q100] [--exact] [--no-cpu-baseline]
@@ -51,6 +60,10 @@ def parse():
     ap.add_argument("--workload", default="n12d6")
     ap.add_argument("--exact", action="store_true", help="FP64 forward (the finishing phase)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ttt", action="store_true", help="step mode: skip the time-to-target runs")
+    ap.add_argument("--no-serve", action="store_true", help="step mode: skip the serving stream")
+    ap.add_argument("--serve-requests", type=int, default=1024,
+                    help="step mode: requests of the serving stream in the default line")
     ap.add_argument("--cpu-rows", type=int, default=12288,
                     help="rows of one step the oracle baseline times (about 10-30 s of host work)")
     ap.add_argument("--mode", default="step", choices=["step", "ttt", "serve", "net"])
@@ -151,9 +164,11 @@ def cpu_baseline(c, rows):
     from workloads import gaussian
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        blas = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        threads = max([i.get("num_threads", 1) for i in blas] or [1])
+        blas_name = ",".join(sorted({f"{i.get('internal_api')} {i.get('version')}" for i in blas}))
     except Exception:
-        threads = os.cpu_count()
+        threads, blas_name = os.cpu_count(), "unknown"
     rng = np.random.default_rng(7)
     sel = np.sort(rng.choice(c.N, size=rows, replace=False))
     W = gaussian((c.N, c.rank), 1, c.w_std)
@@ -170,7 +185,21 @@ def cpu_baseline(c, rows):
     dt = time.perf_counter() - t0
     return {"value": (rows / c.N) / dt, "unit": "steps/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{rows} of {c.N} rows of one step (gram-scatter rows, 4RW rows, Adam rows), "
-                      f"{dt:.1f} s, scaled by rows/N"}
+                      f"{dt:.1f} s, scaled by rows/N; FP64 NumPy, the Gram rows by one BLAS matmul "
+                      f"(the oracle's formula G = W W^T applied to the sampled rows)",
+            "os_cpu_count": os.cpu_count(), "cpu_model": cpu_model(), "blas": blas_name,
+            "blas_threads": int(threads)}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def serve_requests(S, torch, count):
@@ -191,10 +220,13 @@ def serve_requests(S, torch, count):
     return out
 
 
-def serve_mode(a, S, torch):
+def serve_measure(a, S, torch, count):
+    """The serving stream of `count` requests: closed loop (all queued at
+    t = 0: saturation solves/s), then Poisson arrivals at 0.8 x that rate
+    (p50 / p99 latency)."""
     from paper_2410_19844_amd import serve
     import dataclasses
-    reqs = serve_requests(S, torch, a.requests)
+    reqs = serve_requests(S, torch, count)
     mk = lambda: serve.Server(hbm_budget=int(a.hbm_budget_gib * (1 << 30)), max_active=a.slots,
                               check_every=50, tol=1e-6, max_steps=20000, stall_checks=10, stall_ratio=0.5)
     at0 = lambda rs: [dataclasses.replace(r, arrival=0.0) for r in rs]
@@ -219,20 +251,54 @@ def serve_mode(a, S, torch):
     for r in res:
         verdicts[f"{r.verdict}/{r.reason}"] = verdicts.get(f"{r.verdict}/{r.reason}", 0) + 1
     labels = {"sos": sum(1 for q in reqs if q.label == "sos"), "non-sos": sum(1 for q in reqs if q.label != "sos")}
+    return {"solves_per_s": sat, "requests": len(reqs), "labels": labels,
+            "closed_loop": {"solves_per_s": sat, "wall_s": wall, "grouped_steps": srv.iterations * 50,
+                            "request_steps": int(steps.sum()), "peak_active": srv.peak_active,
+                            "peak_bytes": srv.peak_bytes, "verdicts": verdicts},
+            "poisson": {"rate_per_s": rate, "solves_per_s": len(res2) / wall2, "wall_s": wall2,
+                        "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                        "mean_ms": 1e3 * float(lat.mean()), "peak_active": srv2.peak_active},
+            "config": {"workload": f"serving stream: {len(reqs)} requests (seed 12345), n 3..8, d 2..4, rank 2N",
+                       "slots": a.slots, "hbm_budget_gib": a.hbm_budget_gib, "check_every": 50,
+                       "max_steps": 20000, "tol": 1e-6, "stall": "10 checks without halving", "lr": 3e-2}}
+
+
+def serve_mode(a, S, torch):
+    m = serve_measure(a, S, torch, a.requests)
     out = {"metric": "serving solves/s (SOS checks, n 3..8, d 2..4, rank 2N, FP64-verified tol 1e-6)",
-           "value": sat, "unit": "solves/s", "n_gpus": 1, "steps": int(steps.sum()), "warmup": 1,
+           "value": m["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+           "steps": m["closed_loop"]["request_steps"], "warmup": 1,
            "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "fp32+fp64-forward", "data": "synthetic",
-           "config": {"workload": f"serving stream: {len(reqs)} requests (seed 12345), {labels}",
-                      "slots": a.slots, "hbm_budget_gib": a.hbm_budget_gib, "check_every": 50,
-                      "max_steps": 20000, "stall": "10 checks without halving", "lr": 3e-2},
-           "closed_loop": {"solves_per_s": sat, "wall_s": wall, "grouped_steps": srv.iterations * 50,
-                           "request_steps": int(steps.sum()), "peak_active": srv.peak_active,
-                           "peak_bytes": srv.peak_bytes, "verdicts": verdicts},
-           "poisson": {"rate_per_s": rate, "solves_per_s": len(res2) / wall2, "wall_s": wall2,
-                       "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
-                       "mean_ms": 1e3 * float(lat.mean()), "peak_active": srv2.peak_active}}
+           "config": dict(m["config"], workload=m["config"]["workload"] + f", {m['labels']}"),
+           "closed_loop": m["closed_loop"], "poisson": m["poisson"]}
     print(json.dumps(out), flush=True)
+
+
+def ttt_run(S, torch, a, c, W_host, p, precision, single_backward):
+    """sos_solve from W_host to an FP64-verified ||r|| / ||p|| <= a.tol: the
+    ladder (the plan's fast forward, then the exact FP64 forward) with the
+    workload's step sizes.  Returns the result with its wall time."""
+    lr_bulk, lr_fin = LR_DEFAULTS.get(c.name, (3e-3, 1e-3))
+    lr = a.lr if a.lr is not None else lr_bulk
+    lr_exact = a.lr_exact if a.lr_exact is not None else lr_fin
+    switch_rel = a.switch_rel if a.switch_rel is not None else {"bf16x3": 3e-6, "fp32": 1e-6, "fp64": 0.0}[precision]
+    mid_rel = a.mid_rel if a.mid_rel is not None else 0.0
+    pl = S.Plan(c.n, c.d, c.rank, precision)
+    wdt = torch.float64 if precision == "fp64" else torch.float32
+    W = torch.tensor(W_host, dtype=wdt, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = pl.solve(W, p, S.Adam(lr=lr), tol=a.tol, max_steps=a.max_steps, check_every=10, ladder=True,
+                   stall_checks=6, stall_ratio=0.8, switch_rel=switch_rel, lr_exact=lr_exact,
+                   rollback_ratio=10.0, single_backward=single_backward, mid_rel=mid_rel)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del pl, W
+    torch.cuda.empty_cache()
+    return dict(res, seconds=dt, precision=precision, lr=lr, lr_exact=lr_exact, switch_rel=switch_rel,
+                mid_rel=mid_rel, single_backward=single_backward, tol=a.tol,
+                certified=res["status"] == S.OK)
 
 
 def net_mode(a, S, torch):
@@ -341,38 +407,30 @@ def main():
         net_mode(a, S, torch)
         return
     c, W, p = make_inputs(S, torch, a.workload, a.precision, a.rank)
-    pl = S.Plan(c.n, c.d, c.rank, a.precision)
-    lr_bulk, lr_fin = LR_DEFAULTS.get(a.workload, (3e-3, 1e-3))
-    lr = a.lr if a.lr is not None else lr_bulk
-    if a.lr_exact is None:
-        a.lr_exact = lr_fin
-    if a.switch_rel is None:
-        a.switch_rel = {"bf16x3": 3e-6, "fp32": 1e-6, "fp64": 0.0}[a.precision]
-    adam = S.Adam(lr=lr)
-    stream = torch.cuda.current_stream()
     a.single_backward = a.precision == "bf16x3" and not a.split_backward
-    flags = (S.FLAG_EXACT_FORWARD if a.exact else 0) | (S.FLAG_SINGLE_BACKWARD if a.single_backward else 0)
 
     if a.mode == "ttt":
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        res = pl.solve(W, p, adam, tol=a.tol, max_steps=a.max_steps, check_every=10, ladder=True,
-                       stall_checks=6, stall_ratio=0.8, switch_rel=a.switch_rel, lr_exact=a.lr_exact,
-                       rollback_ratio=10.0, single_backward=a.single_backward,
-                       mid_rel=a.mid_rel if a.mid_rel is not None else 0.0)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        res = ttt_run(S, torch, a, c, W.cpu(), p, a.precision, a.single_backward)
+        dt = res["seconds"]
         out = {"metric": f"time-to-rel-residual {a.tol:g} at n={c.n} d={c.d}", "value": dt, "unit": "s",
                "n_gpus": 1, "steps": res["steps"], "warmup": 0, "ms_per_step": 1e3 * dt / max(res["steps"], 1),
                "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
                "dtype": DTYPE[a.precision], "data": "synthetic",
                "config": {"workload": f"{c.name}: n={c.n} d={c.d} N={c.N} M={c.M} rank={c.rank}",
-                          "precision": a.precision, "lr": lr, "lr_exact": a.lr_exact,
-                          "switch_rel": a.switch_rel, "mid_rel": a.mid_rel, "tol": a.tol,
+                          "precision": a.precision, "lr": res["lr"], "lr_exact": res["lr_exact"],
+                          "switch_rel": res["switch_rel"], "mid_rel": res["mid_rel"], "tol": a.tol,
                           "single_backward": a.single_backward},
                "result": res}
         print(json.dumps(out), flush=True)
         return
+
+    W_start = W.cpu() if not a.no_ttt else None       # the common start of the time-to-target runs
+    pl = S.Plan(c.n, c.d, c.rank, a.precision)
+    lr_bulk, _ = LR_DEFAULTS.get(a.workload, (3e-3, 1e-3))
+    lr = a.lr if a.lr is not None else lr_bulk
+    adam = S.Adam(lr=lr)
+    stream = torch.cuda.current_stream()
+    flags = (S.FLAG_EXACT_FORWARD if a.exact else 0) | (S.FLAG_SINGLE_BACKWARD if a.single_backward else 0)
 
     if a.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -423,7 +481,10 @@ def main():
                                + (f"U[-{c.w0_std:.4g},{c.w0_std:.4g}]; " if c.w0_uniform else f"N(0,{c.w0_std:.4g}^2); ")
                                + f"W N(0,{c.w_std:.4g}^2)",
                    "precision": a.precision, "exact_forward": a.exact, "lr": lr,
-                   "single_backward": a.single_backward},
+                   "single_backward": a.single_backward,
+                   "step": ("split-bf16 (hi/lo, three products) forward; one-product bf16 backward (hi*hi) with "
+                            "Adam in its epilogue; FP64 residual and loss")
+                   if (a.precision == "bf16x3" and a.single_backward and not a.exact) else None},
         "roofline": {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1)",
@@ -433,6 +494,50 @@ def main():
         "kernels_ms_per_step": {name: kern[name][0] / a.steps for name in kern},
         "loss": float(loss.item()),
     }
+    if a.precision == "bf16x3" and a.single_backward and not a.exact:
+        # the same step with the three-product (hi/lo) backward: separate R W GEMM, then Adam
+        st2 = pl.new_state()
+        fl2 = 0
+        for t in range(1, 3):
+            pl.step(W, st2, t, p, adam, loss=loss, flags=fl2)
+        torch.cuda.synchronize()
+        pl.timing(True)
+        nsb = max(3, a.steps // 4)
+        ev0.record(stream)
+        for t in range(3, 3 + nsb):
+            pl.step(W, st2, t, p, adam, loss=loss, flags=fl2)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        kern2 = pl.timing_read()
+        pl.timing(False)
+        out["split_backward"] = {"ms_per_step": ev0.elapsed_time(ev1) / nsb, "steps": nsb,
+                                 "kernels_ms_per_step": {q: kern2[q][0] / nsb for q in kern2},
+                                 "rw_frac_of_peak_executed": 3 * flops["rw"] / (kern2["rw"][0] / nsb * 1e-3) / 1e12
+                                 / PEAKS_TFLOPS["bf16x3"]}
+        del st2
+    del pl, st, W
+    torch.cuda.empty_cache()
+    if not a.no_ttt:
+        out["ttt"] = {}
+        for name, prec, single in (("mixed", "bf16x3", True), ("fp32", "fp32", False)):
+            r = ttt_run(S, torch, a, c, W_start, p, prec, single)
+            out["ttt"][name] = {q: r[q] for q in ("seconds", "steps", "exact_steps", "rel", "best_rel", "certified",
+                                                  "precision", "lr", "lr_exact", "switch_rel", "single_backward",
+                                                  "tol")}
+            print(f"ttt {name}: {r['seconds']:.2f} s, {r['steps']} steps ({r['exact_steps']} exact), "
+                  f"rel {r['rel']:.3g}", file=sys.stderr, flush=True)
+        m, f = out["ttt"]["mixed"], out["ttt"]["fp32"]
+        out["ttt"]["mixed_over_fp32_speedup"] = f["seconds"] / m["seconds"] if m["certified"] else None
+    del W_start, p
+    torch.cuda.empty_cache()
+    if not a.no_serve:
+        m = serve_measure(a, S, torch, a.serve_requests)
+        out["serving"] = {"solves_per_s": m["solves_per_s"], "requests": m["requests"],
+                          "p50_ms": m["poisson"]["p50_ms"], "p99_ms": m["poisson"]["p99_ms"],
+                          "poisson_rate_per_s": m["poisson"]["rate_per_s"],
+                          "verdicts": m["closed_loop"]["verdicts"], "config": m["config"]}
+        print(f"serving: {m['solves_per_s']:.1f} solves/s, p99 {m['poisson']['p99_ms']:.0f} ms",
+              file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, a.cpu_rows)
     print(json.dumps(out), flush=True)

@@ -124,7 +124,11 @@ typedef struct {
                             switch_rel (0: switch on a stall only)          */
   double lr_exact;       /* Adam step size in the exact phase (0: adam->lr) */
   double rollback_ratio; /* rel > rollback_ratio * best rel: restore the best
-                            W and halve the step size (0: off)              */
+                            W, zero the Adam moments (the bias correction
+                            restarts) and halve the step size (0: off).  A
+                            non-finite loss after a finite check always rolls
+                            back this way; before any finite check it ends
+                            the solve with SOS_ENUMERIC                     */
   int32_t single_backward; /* 1: steps use SOS_FLAG_SINGLE_BACKWARD         */
   int32_t reserved;
   double mid_rel;        /* SOS_BF16X3 ladder with a middle rung: after the
@@ -217,7 +221,8 @@ int sos_verify(sos_plan_t plan, const void* d_W, const double* d_p, double* h_re
 
 /* Serving: one Adam step (Section 3 loop body) for `count` independent small
  * problems in one set of grouped launches.  plans[q] must be bound SOS_FP32
- * plans with N <= SOS_BATCH_MAX_N and distinct workspaces; d_W[q] (N x k
+ * plans with N <= SOS_BATCH_MAX_N and distinct workspaces (SOS_EINVAL when
+ * two entries share one); d_W[q] (N x k
  * FP32, row-major), d_state[q] (sos_plan_query's state_bytes; m and v as in
  * sos_step), t[q] (1-based Adam step count) and d_p[q] (M FP64) as in
  * sos_step.  d_losses[q] (device) receives L of problem q at the W before
@@ -293,9 +298,10 @@ int sos_net_step(sos_plan_t plan, int n, int m, float* d_At, float* d_Bt, void* 
  * rel <= switch_rel, then the exact forward with step size lr_exact).  As in
  * sos_solve, success is judged on the best weights seen at a check, which
  * are returned in d_At, d_Bt; a check whose rel exceeds rollback_ratio times
- * the best restores the best weights and halves the step size (0: off).  The
- * Adam moments are zeroed first; d_state holds two extra copies of the
- * weights for this.  h_res as for sos_solve (steps, exact_steps, the
+ * the best (or is not finite, after a finite one) restores the best weights,
+ * zeroes the Adam moments and halves the step size (0: off).  The Adam
+ * moments are zeroed first; d_state holds two extra copies of the weights
+ * for the rollback.  h_res as for sos_solve (steps, exact_steps, the
  * verified rel of the returned weights).  Blocks until done.               */
 int sos_net_solve(sos_plan_t plan, int n, int m, float* d_At, float* d_Bt, void* d_state, const double* d_p,
                   const sos_adam_t* adam, const sos_solve_opts_t* opts, int train_first, sos_result_t* h_res,

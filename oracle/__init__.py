@@ -33,4 +33,9 @@ from .sos import (  # noqa: F401
     sample_gradient_rows,
 )
 from .convex import psd_distance  # noqa: F401
-from .network import network_factor, network_loss_grad, network_quartic_coefficients  # noqa: F401
+from .network import (  # noqa: F401
+    network_chain,
+    network_factor,
+    network_loss_grad,
+    network_quartic_coefficients,
+)

@@ -90,12 +90,24 @@ def network_loss_grad(A: np.ndarray, B: np.ndarray, p: np.ndarray):
     gradient dL/dW = 4 R W at that row, for both orders of (a, c).
     """
     from .sos import loss_grad, pair_ranks
+    W = network_factor(A, B)
+    n = np.asarray(A).shape[1]
+    L, gW, _ = loss_grad(W, p, n, 2, pair_ranks(n, 2))
+    dA, dB = network_chain(A, B, gW)
+    return L, dA, dB
+
+
+def network_chain(A: np.ndarray, B: np.ndarray, gW: np.ndarray):
+    """dL/dA and dL/dB from dL/dW (rows of the degree-<=2 basis in n
+    variables) by the chain rule through W = network_factor(A, B): the row of
+    x_a x_c holds P[l,a,c] + P[l,c,a] (a != c) or P[l,a,a], so
+    dL/dP[l,a,c] = gW[row of x_a x_c, l] for both orders of (a, c), and
+    P[l,a,c] = sum_b B[l, a m + b] A[b, c]."""
     A = np.asarray(A, float)
     B = np.asarray(B, float)
+    gW = np.asarray(gW, float)
     m, n = A.shape
     k = B.shape[0]
-    W = network_factor(A, B)
-    L, gW, _ = loss_grad(W, p, n, 2, pair_ranks(n, 2))
     idx = MonomialIndex(n, 2)
     dP = np.zeros((k, n, n))
     for a in range(n):
@@ -110,4 +122,4 @@ def network_loss_grad(A: np.ndarray, B: np.ndarray, p: np.ndarray):
         blk = B[:, a * m:(a + 1) * m]            # k x m
         dB[:, a * m:(a + 1) * m] = dP[:, a, :] @ A.T
         dA += blk.T @ dP[:, a, :]
-    return L, dA, dB
+    return dA, dB

@@ -366,14 +366,16 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
     best_rel = ref_rel = inf;  // values of the more accurate forward from here on
   };
   bool w_moved = true;  // W changed outside a step (start, rollback): operand copies must be rebuilt
+  int64_t t_adam = 0;   // Adam's step count since the moments were last zeroed
   while (t < o->max_steps && !done) {
     ++t;
+    ++t_adam;
     const bool check = (t % o->check_every == 0) || t == o->max_steps;
     if (check) SOS_HIP(hipMemcpyAsync(cand, d_W, wbytes, hipMemcpyDeviceToDevice, s), "sos_solve: snapshot");
     const int flags = (phase == 2 ? SOS_FLAG_EXACT_FORWARD : phase == 1 ? SOS_FLAG_FP32_FORWARD : 0) |
                       (o->single_backward ? SOS_FLAG_SINGLE_BACKWARD : 0) |
                       (w_moved ? 0 : SOS_FLAG_COPIES_VALID);
-    int rc = run_step(p, d_W, st, t, d_p, h, sc + 0, flags, s);
+    int rc = run_step(p, d_W, st, t_adam, d_p, h, sc + 0, flags, s);
     if (rc) return rc;
     w_moved = false;
     if (phase == 2) ++exact_steps;
@@ -394,8 +396,13 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
       have_best = true;
     }
     if (have_best && (!std::isfinite(rel) || (o->rollback_ratio > 0 && rel > o->rollback_ratio * best_rel))) {
-      // diverging: back to the best iterate with half the step size
+      // diverging: back to the best iterate with half the step size and a
+      // fresh start of Adam.  The moments belong to the diverging iterates
+      // (after a non-finite loss they hold its NaN or Inf gradient), so they
+      // are zeroed and the bias correction restarts.
       SOS_HIP(hipMemcpyAsync(d_W, best, wbytes, hipMemcpyDeviceToDevice, s), "sos_solve: rollback");
+      SOS_HIP(hipMemsetAsync(st, 0, 2 * slot, s), "sos_solve: zero moments");
+      t_adam = 0;
       w_moved = true;
       h.lr *= 0.5;
       stall = 0;
@@ -446,6 +453,13 @@ static int check_batch(const sos_plan_t* plans, const void* const* W, const doub
       return set_error(SOS_ERANGE, std::string(what) + ": plan has N > SOS_BATCH_MAX_N");
     if (!W[q] || !d_p[q]) return set_error(SOS_EINVAL, std::string(what) + ": NULL W or p");
   }
+  // every problem writes its residual, partial sums and loss partials into its
+  // plan's workspace, so two problems of one call must not share one
+  std::vector<const char*> ws(count);
+  for (int q = 0; q < count; ++q) ws[q] = plans[q]->ws;
+  std::sort(ws.begin(), ws.end());
+  if (std::adjacent_find(ws.begin(), ws.end()) != ws.end())
+    return set_error(SOS_EINVAL, std::string(what) + ": two problems share one plan workspace");
   return SOS_OK;
 }
 
@@ -690,6 +704,7 @@ int sos_net_solve(sos_plan_t p, int n, int m, float* d_At, float* d_Bt, void* d_
   int64_t t = 0, exact_steps = 0;
   double loss = 0, best_rel = std::numeric_limits<double>::infinity();
   bool done = false;
+  int64_t t_adam = 0;  // Adam's step count since the moments were last zeroed
   auto verify = [&](int which, double* vrel) -> int {
     void* W = st + L.W;
     const float* A = which < 0 ? d_At : (const float*)(st + L.snapA[which]);
@@ -699,13 +714,15 @@ int sos_net_solve(sos_plan_t p, int n, int m, float* d_At, float* d_Bt, void* d_
   };
   while (t < o->max_steps && !done) {
     ++t;
+    ++t_adam;
     const bool check = t % o->check_every == 0 || t == o->max_steps;
     if (check) {  // the loss this step reports belongs to the weights it starts from
       SOS_HIP(hipMemcpyAsync(st + L.snapA[1 - best], d_At, abytes, hipMemcpyDeviceToDevice, s), "net: snapshot A");
       SOS_HIP(hipMemcpyAsync(st + L.snapB[1 - best], d_Bt, bbytes, hipMemcpyDeviceToDevice, s), "net: snapshot B");
     }
     const int flags = (phase ? SOS_FLAG_EXACT_FORWARD : 0) | (o->single_backward ? SOS_FLAG_SINGLE_BACKWARD : 0);
-    if (int rc = net_step(p, n, m, d_At, d_Bt, st, L, t, d_p, h, sc + 0, flags, train_first != 0, s)) return rc;
+    if (int rc = net_step(p, n, m, d_At, d_Bt, st, L, t_adam, d_p, h, sc + 0, flags, train_first != 0, s))
+      return rc;
     if (phase) ++exact_steps;
     if (!check) continue;
     SOS_HIP(hipMemcpyAsync(&loss, sc + 0, 8, hipMemcpyDeviceToHost, s), "sos_net_solve: loss");
@@ -719,9 +736,13 @@ int sos_net_solve(sos_plan_t p, int n, int m, float* d_At, float* d_Bt, void* d_
       have_best = true;
     }
     if (!std::isfinite(rel) || (o->rollback_ratio > 0 && rel > o->rollback_ratio * best_rel)) {
-      // diverging: back to the best weights with half the step size
+      // diverging: back to the best weights with half the step size and
+      // zeroed Adam moments (they hold the diverging iterates' gradients)
       SOS_HIP(hipMemcpyAsync(d_At, st + L.snapA[best], abytes, hipMemcpyDeviceToDevice, s), "net: rollback A");
       SOS_HIP(hipMemcpyAsync(d_Bt, st + L.snapB[best], bbytes, hipMemcpyDeviceToDevice, s), "net: rollback B");
+      SOS_HIP(hipMemsetAsync(st + L.mA, 0, L.mB - L.mA, s), "net: zero moments of A");
+      SOS_HIP(hipMemsetAsync(st + L.mB, 0, L.W - L.mB, s), "net: zero moments of B");
+      t_adam = 0;
       h.lr *= 0.5;
       continue;
     }

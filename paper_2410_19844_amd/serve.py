@@ -90,7 +90,7 @@ class _Active:
         self.W = req.W_init.clone()
         self.state = torch.zeros(self.plan.state_bytes // 2, dtype=torch.uint8, device=self.W.device)
         self.t = 0
-        self.pnorm = math.sqrt(float(torch.dot(req.p, req.p)))
+        self.pnorm = math.nan     # ||p||, set by the server's first grouped call after admission
         self.best = math.inf      # best relative residual read so far
         self.anchor = math.inf    # residual at the last drop by the stall ratio
         self.since = 0            # checks since that drop
@@ -149,6 +149,20 @@ class Server:
                 self._T[q] = a.t
             _check(_lib.sos_step_batch(self._P, self._W, self._S, self._T, self._p, adam, lp, self._n, s))
 
+    def _pnorms(self, items, losses):
+        """||p|| of newly admitted requests from the library's own FP64 sum of
+        squares: the grouped certificate at W = 0 is ||coeff(0) - p||^2."""
+        for q0 in range(0, len(items), len(losses)):
+            part = items[q0:q0 + len(losses)]
+            zero = [torch.zeros_like(a.W) for a in part]
+            n = len(part)
+            P = (ctypes.c_void_p * n)(*[a.plan._h for a in part])
+            W = (ctypes.c_void_p * n)(*[z.data_ptr() for z in zero])
+            p = (ctypes.c_void_p * n)(*[a.req.p.data_ptr() for a in part])
+            _check(_lib.sos_loss_batch(P, W, p, ctypes.c_void_p(losses.data_ptr()), n, _stream(self.stream)))
+            for a, x in zip(part, losses[:n].cpu().numpy()):
+                a.pnorm = math.sqrt(max(float(x), 0.0))
+
     def _certify(self, items, losses):
         n = len(items)
         P = (ctypes.c_void_p * n)(*[a.plan._h for a in items])
@@ -171,6 +185,7 @@ class Server:
         changed = True
         while pending or active:
             now = time.perf_counter() - t0
+            admitted = []
             while pending and pending[0].arrival <= now and len(active) < self.max_active:
                 need = footprint(pending[0].n, pending[0].d, pending[0].rank)
                 if need > self.hbm_budget:
@@ -178,8 +193,11 @@ class Server:
                 if used + need > self.hbm_budget:
                     break
                 active.append(_Active(pending.popleft(), now))
+                admitted.append(active[-1])
                 used += active[-1].bytes
                 changed = True
+            if admitted:
+                self._pnorms(admitted, losses)
             self.peak_bytes = max(self.peak_bytes, used)
             self.peak_active = max(self.peak_active, len(active))
             if not active:

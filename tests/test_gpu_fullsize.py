@@ -6,10 +6,19 @@ backward), through the C ABI.
   ones: x1^12, with one pair, and the constant, with one pair), each summed
   pair by pair by the oracle, against c = r + p from the fast forward
   (split-bf16 bound) and from the exact forward (1e-10).
-* Gradient: the oracle cannot form a full gradient row at this size in
-  reasonable time (every row needs ~18,564 coefficients, each from ~127
-  pair dot products of length 18,564), so the gradient is checked through
-  two properties that hold at any size:
+* Gradient rows, element by element: the oracle forms the whole residual
+  once (its own pair map, a plain matmul for W W^T, a bincount over the
+  ordered pairs; about a minute of host time), then sampled rows
+  4 r[rank(i, .)] W, including the ragged last tile rows (18,432 .. 18,563:
+  the 73rd row of 256-row tiles, the last group of the backward's tile
+  order).  Bounds: the backward's own (single product 2^-7 + 2^-16 +
+  gamma(N) + u, split 3.1 2^-16 + gamma(3N) + u) relative to
+  gabs = 4 |R| |W|, plus the forward's error (relative to coeff(|W||W|^T))
+  carried through 4 |dR| |W|.
+* The fused step (backward GEMM with Adam in its epilogue, the timed path)
+  against the unfused gradient and the Adam formula, and the operand
+  copies its epilogue leaves against freshly prepared ones.
+* Also two properties that hold at any size:
     - the directional derivative along g: L(W + hU) - L(W - hU) (exact FP64
       forward, with the FP32-rounded perturbations measured exactly) against
       <g, Wp - Wm>; L is quartic along the line, so the central difference
@@ -116,3 +125,92 @@ def test_fullsize_pair_ranks_sample(full):
     want = O.pair_ranks(c.n, c.d, rows=rows)
     got = ranks[torch.as_tensor(rows, device=ranks.device)].cpu().numpy()
     assert np.array_equal(got, want)
+
+
+@pytest.fixture(scope="module")
+def oracle_r(full, pair_ranks_n12d6):
+    c = full["c"]
+    W64 = full["W"].double().cpu().numpy()
+    pr = pair_ranks_n12d6
+    r = O.residual(W64, full["p"], c.n, c.d, pr)
+    cabs = O.coefficients_abs(W64, c.n, c.d, pr)
+    return dict(W64=W64, pr=pr, r=r, cabs=cabs)
+
+
+def gradient_rows():
+    N = CONFIGS["n12d6"].N
+    rng = np.random.default_rng(33)
+    last = np.array([N - 132, N - 131, N - 67, N - 2, N - 1])        # the 73rd tile row (18,432 ..)
+    edges = np.array([0, 1, 255, 256, 18431])                         # tile-row boundaries
+    return np.unique(np.concatenate([edges, last, rng.choice(N - 132, 14, replace=False)]))
+
+
+@pytest.mark.parametrize("exact,single", [(False, True), (True, True), (True, False)])
+def test_fullsize_gradient_rows(full, oracle_r, exact, single):
+    c, pl, W, pd = full["c"], full["pl"], full["W"], full["pd"]
+    if not exact and single:
+        g = full["g"]
+    else:
+        _, g, _ = pl.loss_grad(W, pd, grad=True, exact=exact, single_backward=single)
+    rows = gradient_rows()
+    g = g[torch.as_tensor(rows, device=W.device)].double().cpu().numpy()
+    W64, pr, r, cabs = oracle_r["W64"], oracle_r["pr"], oracle_r["r"], oracle_r["cabs"]
+    P = pr[rows]
+    want = 4.0 * (r[P] @ W64)
+    Wa = np.abs(W64)
+    tol_b = (2.0 ** -7 + 2.0 ** -16 + gamma(c.N) + U32) if single else (3.1 * 2.0 ** -16 + gamma(3 * c.N) + U32)
+    tol_f = 1e-10 if exact else 3.1 * 2.0 ** -16 + gamma(3 * c.rank) + U32
+    bound = tol_b * 4.0 * (np.abs(r[P]) @ Wa) + 4.0 * ((tol_f * cabs)[P] @ Wa) + 1e-30
+    worst = np.abs(g - want) / bound
+    assert worst.max() <= 1.0, f"max |err|/bound {worst.max():.3g} at row {rows[np.argmax(worst.max(1))]}"
+    # the errors are far inside the worst-case bound: a wrong tile would show as O(1) relative error
+    rel = np.linalg.norm(g - want, axis=1) / np.linalg.norm(want, axis=1)
+    assert rel.max() <= (2e-2 if single else 1e-4), rel.max()
+
+
+def test_fullsize_fused_step_matches_unfused(full):
+    """sos_step with the single-product backward runs R W with Adam in the
+    GEMM epilogue (the timed step).  From zero moments at t = 1 its moments
+    and update must be those of the unfused gradient of sos_loss_grad put
+    through the Adam formula (with the kernel's FP32 constants); the next
+    step, reusing the operand copies that epilogue wrote, must see the loss
+    of freshly prepared copies of the updated W."""
+    c, pl, W, pd = full["c"], full["pl"], full["W"], full["pd"]
+    N, k = c.N, c.rank
+    f32 = lambda x: float(np.float32(x))
+    b1, b2, lr, eps = f32(0.9), f32(0.999), f32(1e-3), f32(1e-8)
+    bc1, bc2 = f32(1 - 0.9), f32(1 - 0.999)
+    Wa = W.clone()
+    st = pl.new_state()
+    adam = S.Adam(lr=1e-3)
+    L1 = pl.step(Wa, st, 1, pd, adam, flags=S.FLAG_SINGLE_BACKWARD).item()
+    torch.cuda.synchronize()
+    assert abs(L1 - full["L_fast"]) <= 1e-12 * full["L_fast"]
+    slot = pl.state_bytes // 4
+    m = st[: N * k * 4].view(torch.float32).reshape(N, k).double()
+    v = st[slot: slot + N * k * 4].view(torch.float32).reshape(N, k).double()
+    g = full["g"].double()
+    # same tiles on the same copies: the fused GEMM's gradient is the unfused one
+    m_want = (1 - b1) * g
+    v_want = (1 - b2) * g * g
+    assert bool(((m - m_want).abs() <= 2.0 ** -23 * m_want.abs()).all()), "first moment"
+    assert bool(((v - v_want).abs() <= 2.0 ** -22 * v_want + 1e-40).all()), "second moment"
+    upd = lr * (m_want / bc1) / (torch.sqrt(v_want / bc2) + eps)
+    want = W.double() - upd
+    diff = (Wa.double() - want).abs()
+    assert bool((diff <= 2.0 ** -21 * upd.abs() + 2.0 ** -23 * want.abs()).all()), float(diff.max())
+    # the copies the epilogue left (split forward copy, transposed copy) against freshly prepared ones
+    W1 = Wa.clone()
+    m1 = m.clone()
+    L2 = pl.step(Wa, st, 2, pd, adam, flags=S.FLAG_SINGLE_BACKWARD | S.FLAG_COPIES_VALID).item()
+    torch.cuda.synchronize()
+    m2 = st[: N * k * 4].view(torch.float32).reshape(N, k).double()
+    L_ref, g_ref, _ = pl.loss_grad(W1, pd, grad=True, single_backward=True)
+    # both forwards add the same products, in a different atomic order
+    assert abs(L2 - L_ref.item()) <= 1e-12 * L_ref.item(), (L2, L_ref.item())
+    # the second gradient, read back from the first moment, read the transposed copy the
+    # epilogue wrote; R may differ in a last bit where the two forwards' r round differently
+    g2 = (m2 - b1 * m1) / (1 - b1)
+    gr = g_ref.double()
+    rel = (g2 - gr).norm(dim=1) / gr.norm(dim=1)
+    assert float(rel.max()) <= 1e-4, float(rel.max())

@@ -67,6 +67,44 @@ def test_net_weights_and_coefficients(n, m, k):
     assert np.all(np.abs(c - c_o) <= 2 * (2 * m + 2) * U32 * cabs + 1e-12 * np.abs(c_o).max())
 
 
+def net_grad_bounds(A, B, p_o, prec, exact, m):
+    """Element-wise bounds on the GPU's dL/dA and dL/dB, carried through the
+    chain the library computes, with absolute values (the oracle's own chain
+    rule applied to |A|, |B| and non-negative error terms):
+      W = net(A, B):  |dW| <= eW Wabs, Wabs = net(|A|, |B|);
+      forward:        |dc| <= (ef + 2 eW + eW^2) coeff(Wabs Wabs^T);
+      backward:       |d(4 R W)| <= (eb + eW + us) 4 (|r| + |dc|)[R] Wabs + 4 |dc|[R] Wabs
+                      (us: the rounding of dL/dW to the plan's W type);
+      dL/dB = dP A^T over n terms, dL/dA = sum B^T dP over n k terms, rounded to FP32.
+    ef, eb: the forward's and backward's bounds relative to coeff(|W||W|^T)
+    and 4 |R| |W| (FP32: gamma(K+1) + u; split bf16: 3.1 2^-16 + gamma(3K) + u;
+    FP64 products summed in FP64: 1e-12)."""
+    n = A.shape[1]
+    k = B.shape[0]
+    pr = O.pair_ranks(n, 2)
+    Wabs = O.network_factor(np.abs(A), np.abs(B))
+    r = O.residual(O.network_factor(A, B), p_o, n, 2, pr)
+    N = Wabs.shape[0]
+    if prec == "fp64":
+        eW, us = (2 * m + 2) * 2.0 ** -53, 0.0
+        ef = eb = 1e-12
+    else:
+        eW, us = (2 * m + 2) * U32, U32
+        if prec == "fp32" or exact:
+            ef = 1e-12 if exact else gamma(k + 1) + U32
+        else:
+            ef = 3.1 * 2.0 ** -16 + gamma(3 * k) + U32
+        eb = gamma(N + 1) + U32 if prec == "fp32" else 3.1 * 2.0 ** -16 + gamma(3 * N) + U32
+    dc = (ef + 2 * eW + eW * eW) * O.coefficients(Wabs, n, 2, pr)
+    gabs = 4.0 * ((np.abs(r) + dc)[pr] @ Wabs)
+    gerr = (eb + eW + us) * gabs + 4.0 * (dc[pr] @ Wabs)
+    dA_abs, dB_abs = O.network_chain(np.abs(A), np.abs(B), gabs)
+    dA_err, dB_err = O.network_chain(np.abs(A), np.abs(B), gerr)
+    bB = gamma(n) * dB_abs + (1 + gamma(n)) * dB_err + U32 * (dB_abs + dB_err)
+    bA = gamma(n * k) * dA_abs + (1 + gamma(n * k)) * dA_err + U32 * (dA_abs + dA_err)
+    return bA, bB
+
+
 @pytest.mark.parametrize("prec,flags", [("fp32", 0), ("bf16x3", 0), ("bf16x3", 1), ("fp64", 0)])
 def test_net_gradient_matches_oracle(prec, flags):
     n, m, k = 5, 6, 15
@@ -80,12 +118,17 @@ def test_net_gradient_matches_oracle(prec, flags):
     L_o, dA_o, dB_o = O.network_loss_grad(A, B, p_o)
     # FP32 weights and W (rounding ~1e-7), FP32 or split-bf16 (~2^-16 per term) contractions
     tol_L = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-5 if flags else 1e-3}[prec]
-    tol_g = {"fp64": 1e-6, "fp32": 1e-4, "bf16x3": 1e-3}[prec]
     assert abs(L.item() - L_o) <= tol_L * L_o
     gA = dA.double().cpu().numpy().T
     gB = dB.double().cpu().numpy().T
-    assert np.linalg.norm(gA - dA_o) <= tol_g * np.linalg.norm(dA_o)
-    assert np.linalg.norm(gB - dB_o) <= tol_g * np.linalg.norm(dB_o)
+    bA, bB = net_grad_bounds(A, B, p_o, prec, bool(flags), m)
+    wA = np.abs(gA - dA_o) / (bA + 1e-300)
+    wB = np.abs(gB - dB_o) / (bB + 1e-300)
+    assert wA.max() <= 1.0, f"dL/dA: max |err|/bound {wA.max():.3g}"
+    assert wB.max() <= 1.0, f"dL/dB: max |err|/bound {wB.max():.3g}"
+    # far inside the worst case: a wrong entry would be an O(1) relative error
+    assert np.linalg.norm(gA - dA_o) <= 1e-2 * np.linalg.norm(dA_o)
+    assert np.linalg.norm(gB - dB_o) <= 1e-2 * np.linalg.norm(dB_o)
 
 
 @pytest.mark.parametrize("train_first", [True, False])

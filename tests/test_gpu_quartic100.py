@@ -3,7 +3,8 @@
 basis: N = 5,050, M = 4,421,275, full rank k = N.  The ranking takes the
 variable-list encoding (n > 16).  The oracle forms the whole coefficient
 vector here (25.5 M pairs, row blocks of 505), so the comparison is
-element by element.
+element by element, for the coefficients and for sampled gradient rows
+(including the ragged last tile row, 4,864 .. 5,049).
 """
 import math
 
@@ -46,7 +47,7 @@ def case():
         pr = O.pair_ranks_sparse(n, d, rows=rows, basis=basis, cidx=cidx)
         c += np.bincount(pr.ravel(), weights=G[rows].ravel(), minlength=M)
         cabs += np.bincount(pr.ravel(), weights=Ga[rows].ravel(), minlength=M)
-    return dict(n=n, d=d, N=N, M=M, k=k, Wd=Wd, p=p, c=c, cabs=cabs)
+    return dict(n=n, d=d, N=N, M=M, k=k, Wd=Wd, W64=W64, p=p, c=c, cabs=cabs, basis=basis, cidx=cidx)
 
 
 @pytest.mark.parametrize("prec,exact", [("bf16x3", False), ("bf16x3", True), ("fp32", False)])
@@ -63,3 +64,30 @@ def test_quartic100_coefficients(case, prec, exact):
     want_L = float(np.sum((case["c"] - case["p"]) ** 2))
     dc = tol * case["cabs"]
     assert abs(L.item() - want_L) <= 2 * np.sum(np.abs(case["c"] - case["p"]) * dc) + np.sum(dc * dc) + 1e-12 * want_L
+
+
+@pytest.mark.parametrize("prec,exact,single", [("bf16x3", False, True), ("bf16x3", True, False), ("fp32", False, False)])
+def test_quartic100_gradient_rows(case, prec, exact, single):
+    """Rows of 4 R W against the oracle's r (bound: the backward's own error
+    relative to 4 |R| |W|, plus the forward's carried through 4 |dR| |W|)."""
+    n, d, N, K = case["n"], case["d"], case["N"], case["k"]
+    pl = S.Plan(n, d, K, prec)
+    pd = torch.tensor(case["p"], dtype=torch.float64, device="cuda")
+    _, g, _ = pl.loss_grad(case["Wd"], pd, grad=True, exact=exact, single_backward=single)
+    rng = np.random.default_rng(57)
+    rows = np.unique(np.concatenate([[0, 255, 256, 4863, 4864, 4865, N - 2, N - 1],
+                                     rng.choice(N, 12, replace=False)]))
+    got = g[torch.as_tensor(rows, device="cuda")].double().cpu().numpy()
+    P = O.pair_ranks_sparse(n, d, rows=rows, basis=case["basis"], cidx=case["cidx"])
+    r = case["c"] - case["p"]
+    W64 = case["W64"]
+    want = 4.0 * (r[P] @ W64)
+    Wa = np.abs(W64)
+    if prec == "fp32":
+        tol_f, tol_b = gamma(K + 1) + U32, gamma(N + 1) + U32
+    else:
+        tol_f = 1e-10 if exact else 3.1 * 2.0 ** -16 + gamma(3 * K) + U32
+        tol_b = (2.0 ** -7 + 2.0 ** -16 + gamma(N) + U32) if single else (3.1 * 2.0 ** -16 + gamma(3 * N) + U32)
+    bound = tol_b * 4.0 * (np.abs(r[P]) @ Wa) + 4.0 * ((tol_f * case["cabs"])[P] @ Wa) + 1e-30
+    worst = np.abs(got - want) / bound
+    assert worst.max() <= 1.0, f"max |err|/bound {worst.max():.3g} at row {rows[np.argmax(worst.max(1))]}"

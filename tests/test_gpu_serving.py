@@ -259,3 +259,20 @@ def test_server_admission_respects_budget():
     assert srv.peak_bytes <= budget
     with pytest.raises(ValueError):
         serve.Server(hbm_budget=fps[0] - 1).run(reqs[:1])
+
+
+def test_step_batch_rejects_a_shared_workspace():
+    """Problems of one grouped call write into their plans' workspaces; one
+    plan passed twice is refused before anything is enqueued."""
+    plans, Ws, _, ps, _ = make_mix([(3, 2, 20), (3, 2, 20)])
+    st = [plans[0].new_state(), plans[0].new_state()]
+    losses = torch.zeros(2, dtype=torch.float64, device=dev())
+    W_before = Ws[0].clone()
+    with pytest.raises(S.SosError) as e:
+        S.step_batch([plans[0], plans[0]], Ws, st, [1, 1], ps, S.Adam(lr=1e-2), losses)
+    assert e.value.code == S.EINVAL and "share" in str(e.value)
+    with pytest.raises(S.SosError):
+        S.loss_batch([plans[0], plans[0]], Ws, ps, losses)
+    torch.cuda.synchronize()
+    assert torch.equal(Ws[0], W_before)
+    S.step_batch(plans, Ws, st, [1, 1], ps, S.Adam(lr=1e-2), losses)   # distinct workspaces: accepted

@@ -24,7 +24,7 @@ S = pytest.importorskip("paper_2410_19844_amd")
 pytestmark = pytest.mark.gpu
 
 
-def test_fullsize_solve_certified_by_the_oracle():
+def test_fullsize_solve_certified_by_the_oracle(pair_ranks_n12d6):
     c = CONFIGS["n12d6"]
     dev = torch.device("cuda")
     W0_32 = c.W0().astype(np.float32)
@@ -44,7 +44,7 @@ def test_fullsize_solve_certified_by_the_oracle():
     del pl, W, p
     torch.cuda.empty_cache()
 
-    pr = O.pair_ranks(c.n, c.d)
+    pr = pair_ranks_n12d6
     p_o = O.coefficients(W0_32.astype(np.float64), c.n, c.d, pr)
     r_o = O.residual(Wf, p_o, c.n, c.d, pr)
     rel_o = float(np.linalg.norm(r_o) / np.linalg.norm(p_o))
