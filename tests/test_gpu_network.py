@@ -23,6 +23,11 @@ pytestmark = pytest.mark.gpu
 U32 = 2.0 ** -24
 
 
+def gamma(n):
+    """Higham's bound on n FP32 roundings: n u / (1 - n u)."""
+    return n * U32 / (1 - n * U32)
+
+
 def dehom_maps(n):
     """Positions, in the oracle's n-variable indexes, of the plan (n-1, 2)'s
     basis rows (degree-2 forms) and coefficients (degree-4 forms)."""
