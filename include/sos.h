@@ -192,6 +192,28 @@ int sos_pair_ranks(sos_plan_t plan, int32_t* d_out, void* stream);
 int sos_loss_grad(sos_plan_t plan, const void* d_W, const double* d_p, double* d_loss,
                   void* d_grad, double* d_r, int flags, void* stream);
 
+/* Size of the library's static device workspace behind
+ * sos_loss_grad_noalloc: 64 MiB per GPU, held from the library's first use
+ * of a GPU until the process ends.  It covers every plan of the serving
+ * sizes (n <= 8, d <= 4, rank 2N: at most 23 MiB, any precision).        */
+#define SOS_NOALLOC_MAX_WS (64u << 20)
+
+/* sos_loss_grad for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Arguments, flags and results are those of sos_loss_grad (the caller still
+ * passes W, p and the outputs), but the plan must be UNBOUND: the call uses
+ * the library's static workspace on the stream's GPU instead of one from
+ * sos_plan_bind, uploads the plan's ranking tables into it, and leaves the
+ * plan unbound again on return.  It calls no hipMalloc, hipFree or other
+ * allocating routine (kernel timing from sos_timing is not recorded).
+ * Every call on one GPU shares that GPU's workspace, which keeps the last
+ * call's contents; the call writes every region before reading it.  Calls
+ * that overlap on one GPU (other streams, other threads) race: order them.
+ * Errors as sos_loss_grad, plus SOS_EINVAL for a bound plan and SOS_ERANGE
+ * when the plan's ws_bytes (sos_plan_query) exceeds SOS_NOALLOC_MAX_WS.   */
+int sos_loss_grad_noalloc(sos_plan_t plan, const void* d_W, const double* d_p, double* d_loss,
+                          void* d_grad, double* d_r, int flags, void* stream);
+
 /* One Adam step at iteration t (1-based): computes the loss and gradient
  * at W (written to d_loss), then updates W, m, v in place.
  *   d_state: state_bytes from sos_plan_query; zero it before t = 1.

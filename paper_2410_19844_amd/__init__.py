@@ -69,6 +69,7 @@ def _load():
         "sos_exponents": (I, [P, I, V]),
         "sos_pair_ranks": (I, [P, V, V]),
         "sos_loss_grad": (I, [P, V, V, V, V, V, I, V]),
+        "sos_loss_grad_noalloc": (I, [P, V, V, V, V, V, I, V]),
         "sos_step": (I, [P, V, V, I64, V, ctypes.POINTER(_Adam), V, I, V]),
         "sos_solve": (I, [P, V, V, V, ctypes.POINTER(_Adam), ctypes.POINTER(_SolveOpts),
                           ctypes.POINTER(_Result), V]),
@@ -95,7 +96,7 @@ def _load():
 
 _lib = _load()
 EXPORTS = ("sos_plan", "sos_plan_query", "sos_plan_bind", "sos_plan_destroy", "sos_exponents",
-           "sos_pair_ranks", "sos_loss_grad", "sos_step", "sos_solve", "sos_verify",
+           "sos_pair_ranks", "sos_loss_grad", "sos_loss_grad_noalloc", "sos_step", "sos_solve", "sos_verify",
            "sos_step_batch", "sos_loss_batch", "sos_net_query", "sos_net_weights", "sos_net_grad", "sos_net_step",
            "sos_net_solve", "sos_timing", "sos_timing_read", "sos_last_error")
 KERNEL_CLASSES = ("prep", "init_r", "gram", "loss", "gather", "rw", "adam")
@@ -136,9 +137,12 @@ def sos_plan(n: int, d: int, rank: int, precision="fp32"):
 
 
 class Plan:
-    """A bound plan: host tables plus a device workspace owned by this object."""
+    """A bound plan: host tables plus a device workspace owned by this object.
 
-    def __init__(self, n: int, d: int, rank: int, precision="fp32", device="cuda", stream=None):
+    With bind=False no workspace is allocated and the plan stays unbound: only
+    ``loss_grad_noalloc`` (the library's static workspace) can run it."""
+
+    def __init__(self, n: int, d: int, rank: int, precision="fp32", device="cuda", stream=None, bind=True):
         self.n, self.d, self.rank = n, d, rank
         self.prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self._h = sos_plan(n, d, rank, self.prec)
@@ -150,7 +154,7 @@ class Plan:
         self.wdtype = torch.float64 if self.prec == FP64 else torch.float32
         self.device = torch.device(device)
         self.ws = None
-        if self.device.type == "cuda":
+        if self.device.type == "cuda" and bind:
             self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
             off = (-self.ws.data_ptr()) % 256
             self._ws_view = self.ws[off:off + self.ws_bytes]
@@ -202,6 +206,18 @@ class Plan:
                                   (FLAG_EXACT_FORWARD if exact else 0) |
                                   (FLAG_SINGLE_BACKWARD if single_backward else 0) |
                                   (FLAG_FP32_FORWARD if fp32_forward else 0), _stream(stream)))
+        return loss, g, r
+
+    def loss_grad_noalloc(self, W, p, loss, g=None, r=None, exact=False, single_backward=False,
+                          fp32_forward=False, stream=None):
+        """sos_loss_grad_noalloc on an unbound plan (bind=False): the outputs
+        (loss, and g and r when given) are caller tensors, so the call makes
+        no device allocation at all."""
+        self._w(W), self._p(p)
+        _check(_lib.sos_loss_grad_noalloc(self._h, _ptr(W), _ptr(p), _ptr(loss), _ptr(g), _ptr(r),
+                                          (FLAG_EXACT_FORWARD if exact else 0) |
+                                          (FLAG_SINGLE_BACKWARD if single_backward else 0) |
+                                          (FLAG_FP32_FORWARD if fp32_forward else 0), _stream(stream)))
         return loss, g, r
 
     def step(self, W, state, t, p, adam: Adam, loss=None, flags=0, stream=None):

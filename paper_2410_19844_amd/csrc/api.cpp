@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <utility>
 
@@ -322,6 +323,103 @@ int sos_verify(sos_plan_t p, const void* d_W, const double* d_p, double* h_rel, 
   SOS_HIP(hipStreamSynchronize(s), "sos_verify");
   const double np = std::sqrt(h[1]);
   *h_rel = std::sqrt(h[0]) / (np > 0 ? np : 1.0);
+  return SOS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free loss and gradient: the workspace is the library's own
+// static device array instead of caller memory.
+// ---------------------------------------------------------------------------
+namespace sos {
+
+// One copy per GPU, alive until the process ends.  In host code the name is
+// only a stand-in for the symbol: kernels and copies get the device address
+// that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) char scratch[SOS_NOALLOC_MAX_WS];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_at[kMaxDevices];
+
+// Device address of `scratch` on the device that runs `stream` (looked up once
+// per device, with that device current).
+static int scratch_for_stream(hipStream_t s, char** out) {
+  int cur = 0, dev = 0;
+  SOS_HIP(hipGetDevice(&cur), "sos_loss_grad_noalloc: current device");
+  dev = cur;
+  if (s) SOS_HIP(hipStreamGetDevice(s, &dev), "sos_loss_grad_noalloc: device of the stream");
+  if (dev < 0 || dev >= kMaxDevices) return set_error(SOS_ERANGE, "sos_loss_grad_noalloc: device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_at[dev]) {
+    if (dev != cur) SOS_HIP(hipSetDevice(dev), "sos_loss_grad_noalloc: select the stream's device");
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (dev != cur) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return hip_error(e, "sos_loss_grad_noalloc: address of the static workspace");
+    if (!ptr) return set_error(SOS_EHIP, "sos_loss_grad_noalloc: static workspace has no device address");
+    g_scratch_at[dev] = ptr;
+  }
+  *out = (char*)g_scratch_at[dev];
+  return SOS_OK;
+}
+
+// Points an unbound plan at the static workspace for one call and detaches it
+// again on every return path; event timing stays off meanwhile (it would
+// create HIP events).
+struct ScratchBinding {
+  sos_plan_s* p;
+  bool timing;
+  ScratchBinding(sos_plan_s* p_, char* base) : p(p_), timing(p_->timing) {
+    p->ws = base;
+    p->ws_size = SOS_NOALLOC_MAX_WS;
+    p->bound = true;
+    p->timing = false;
+  }
+  ~ScratchBinding() {
+    p->ws = nullptr;
+    p->ws_size = 0;
+    p->bound = false;
+    p->copies_valid = false;
+    p->timing = timing;
+  }
+};
+
+}  // namespace sos
+
+extern "C" {
+
+int sos_loss_grad_noalloc(sos_plan_t p, const void* d_W, const double* d_p, double* d_loss, void* d_grad,
+                          double* d_r, int flags, void* stream) {
+  if (!p) return set_error(SOS_EINVAL, "sos_loss_grad_noalloc: plan is NULL");
+  if (p->bound)
+    return set_error(SOS_EINVAL, "sos_loss_grad_noalloc: plan is bound to a workspace (use sos_loss_grad)");
+  if (!d_W || !d_p || !d_loss)
+    return set_error(SOS_EINVAL, "sos_loss_grad_noalloc: d_W, d_p and d_loss are required");
+  if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_SINGLE_BACKWARD | SOS_FLAG_FP32_FORWARD))
+    return set_error(SOS_EINVAL, "sos_loss_grad_noalloc: unknown flags");
+  if (p->lay.bytes > (size_t)SOS_NOALLOC_MAX_WS)
+    return set_error(SOS_ERANGE, "sos_loss_grad_noalloc: the plan needs a workspace of " +
+                                     std::to_string(p->lay.bytes) + " bytes, above the static " +
+                                     std::to_string((size_t)SOS_NOALLOC_MAX_WS) + " (use sos_loss_grad)");
+  hipStream_t s = (hipStream_t)stream;
+  char* base = nullptr;
+  if (int rc = scratch_for_stream(s, &base)) return rc;
+  ScratchBinding bind(p, base);
+  // the ranking tables and the tile list, as sos_plan_bind uploads them; every
+  // other region the kernels read is written earlier in the same call
+  SOS_HIP(hipMemcpyAsync(p->ws + p->lay.codes, p->codes.data(), p->codes.size() * 4, hipMemcpyHostToDevice, s),
+          "sos_loss_grad_noalloc: codes");
+  SOS_HIP(hipMemcpyAsync(p->ws + p->lay.tables, p->tables.data(), p->tables.size() * 4, hipMemcpyHostToDevice, s),
+          "sos_loss_grad_noalloc: tables");
+  SOS_HIP(hipMemcpyAsync(p->ws + p->lay.tiles, p->tile_list.data(), p->tile_list.size() * 4, hipMemcpyHostToDevice,
+                         s), "sos_loss_grad_noalloc: tiles");
+  int rc = run_forward(p, d_W, d_p, flags, d_loss, d_grad != nullptr, s);
+  if (rc) return rc;
+  if (d_grad && (rc = run_backward(p, d_grad, (flags & SOS_FLAG_SINGLE_BACKWARD) == 0, s))) return rc;
+  if (d_r)
+    SOS_HIP(hipMemcpyAsync(d_r, p->ws + p->lay.r, p->M * 8, hipMemcpyDeviceToDevice, s), "sos_loss_grad_noalloc: r");
   return SOS_OK;
 }
 

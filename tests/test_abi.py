@@ -109,3 +109,23 @@ def test_adam_argument_errors():
     # unbound check happens first; the Adam check is exercised on the GPU tests
     assert S._lib.sos_step(h2, z, z, 1, z, ctypes.byref(bad.c()), z, 0, z) == -1
     S._lib.sos_plan_destroy(h2)
+
+
+def test_noalloc_argument_errors():
+    """sos_loss_grad_noalloc checks its arguments before touching a GPU."""
+    z = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced: every check below fails first
+    assert S._lib.sos_loss_grad_noalloc(z, fake, fake, fake, z, z, 0, z) == -1
+    h = S.sos_plan(3, 2, 5, "fp32")
+    assert S._lib.sos_loss_grad_noalloc(h, z, fake, fake, z, z, 0, z) == -1
+    assert S._lib.sos_loss_grad_noalloc(h, fake, fake, fake, z, z, 64, z) == -1
+    assert b"flags" in S._lib.sos_last_error()
+    S._lib.sos_plan_destroy(h)
+    # (10, 5) at full rank needs ~213 MiB of workspace, above the static 64 MiB
+    big = S.sos_plan(10, 5, 3003, "bf16x3")
+    ws = ctypes.c_size_t()
+    S._lib.sos_plan_query(big, None, None, ctypes.byref(ws), None)
+    assert ws.value > 64 << 20
+    assert S._lib.sos_loss_grad_noalloc(big, fake, fake, fake, z, z, 0, z) == -2
+    assert b"static" in S._lib.sos_last_error()
+    S._lib.sos_plan_destroy(big)
