@@ -41,7 +41,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAKS_TFLOPS = {"bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6}
+PEAKS_TFLOPS = {"bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6, "int8": 5000.0}
 # Adam step sizes (bulk, exact-forward finisher) per workload, chosen by a
 # short sweep of time to 1e-8 and then frozen.  The q100 finisher takes the
 # middle of the range (1.5e-3 to 2.5e-3) where the step count does not move
@@ -59,6 +59,10 @@ def parse():
     ap.add_argument("--precision", default="bf16x3", choices=list(PEAKS_TFLOPS))
     ap.add_argument("--workload", default="n12d6")
     ap.add_argument("--exact", action="store_true", help="FP64 forward (the finishing phase)")
+    ap.add_argument("--ozaki", action="store_true",
+                    help="FP64-accurate forward from int8 slices (Ozaki splitting) instead of the fast one")
+    ap.add_argument("--finisher", choices=("fp64", "ozaki"), default=None,
+                    help="ttt: forward of the exact phase (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttt", action="store_true", help="step mode: skip the time-to-target runs")
     ap.add_argument("--no-serve", action="store_true", help="step mode: skip the serving stream")
@@ -275,10 +279,12 @@ def serve_mode(a, S, torch):
     print(json.dumps(out), flush=True)
 
 
-def ttt_run(S, torch, a, c, W_host, p, precision, single_backward):
+def ttt_run(S, torch, a, c, W_host, p, precision, single_backward, finisher=None):
     """sos_solve from W_host to an FP64-verified ||r|| / ||p|| <= a.tol: the
-    ladder (the plan's fast forward, then the exact FP64 forward) with the
-    workload's step sizes.  Returns the result with its wall time."""
+    ladder (the plan's fast forward, then an FP64-accurate forward: FP64 MFMA,
+    or int8 slices with finisher "ozaki") with the workload's step sizes.
+    Returns the result with its wall time."""
+    finisher = finisher or a.finisher or "fp64"
     lr_bulk, lr_fin = LR_DEFAULTS.get(c.name, (3e-3, 1e-3))
     lr = a.lr if a.lr is not None else lr_bulk
     lr_exact = a.lr_exact if a.lr_exact is not None else lr_fin
@@ -291,13 +297,14 @@ def ttt_run(S, torch, a, c, W_host, p, precision, single_backward):
     t0 = time.perf_counter()
     res = pl.solve(W, p, S.Adam(lr=lr), tol=a.tol, max_steps=a.max_steps, check_every=10, ladder=True,
                    stall_checks=6, stall_ratio=0.8, switch_rel=switch_rel, lr_exact=lr_exact,
-                   rollback_ratio=10.0, single_backward=single_backward, mid_rel=mid_rel)
+                   rollback_ratio=10.0, single_backward=single_backward, mid_rel=mid_rel,
+                   finisher=finisher if precision != "fp64" else "fp64")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     del pl, W
     torch.cuda.empty_cache()
     return dict(res, seconds=dt, precision=precision, lr=lr, lr_exact=lr_exact, switch_rel=switch_rel,
-                mid_rel=mid_rel, single_backward=single_backward, tol=a.tol,
+                mid_rel=mid_rel, single_backward=single_backward, tol=a.tol, finisher=finisher,
                 certified=res["status"] == S.OK)
 
 
@@ -430,7 +437,8 @@ def main():
     lr = a.lr if a.lr is not None else lr_bulk
     adam = S.Adam(lr=lr)
     stream = torch.cuda.current_stream()
-    flags = (S.FLAG_EXACT_FORWARD if a.exact else 0) | (S.FLAG_SINGLE_BACKWARD if a.single_backward else 0)
+    flags = ((S.FLAG_EXACT_FORWARD if a.exact else 0) | (S.FLAG_OZAKI_FORWARD if a.ozaki else 0)
+             | (S.FLAG_SINGLE_BACKWARD if a.single_backward else 0))
 
     if a.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -462,11 +470,13 @@ def main():
     dom = max(("gram", "rw"), key=lambda q: per_launch[q])
     if a.exact and dom == "gram":
         peak = PEAKS_TFLOPS["fp64"]
+    elif a.ozaki and not a.exact and dom == "gram":
+        peak = PEAKS_TFLOPS["int8"]
     else:
         peak = PEAKS_TFLOPS[a.precision]
     achieved = flops[dom] / (per_launch[dom] * 1e-3) / 1e12
     traffic = None
-    if c.name == "n12d6" and a.precision == "bf16x3" and a.single_backward:
+    if c.name == "n12d6" and a.precision == "bf16x3" and a.single_backward and not a.ozaki:
         key = {("gram", False): "step:k_gram_bf3", ("gram", True): "exact:k_gram_x64",
                ("rw", False): "step:k_rw_adam_bf3", ("rw", True): "step:k_rw_adam_bf3"}[(dom, a.exact)]
         traffic = measured_traffic(key)
@@ -474,27 +484,29 @@ def main():
         "metric": f"grad steps/s at n={c.n} d={c.d}", "value": 1e3 / ms_step, "unit": "steps/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": DTYPE[a.precision] if not a.exact else DTYPE[a.precision] + "+fp64-forward",
+        "dtype": DTYPE[a.precision] + ("+fp64-forward" if a.exact else "+int8-forward" if a.ozaki else ""),
         "data": "synthetic",
         "config": {"workload": f"{c.name}: n={c.n} d={c.d} N={c.N} M={c.M} rank={c.rank}; "
                                f"p=coeff(W0 W0^T), W0 {c.N}x{c.w0_rank} "
                                + (f"U[-{c.w0_std:.4g},{c.w0_std:.4g}]; " if c.w0_uniform else f"N(0,{c.w0_std:.4g}^2); ")
                                + f"W N(0,{c.w_std:.4g}^2)",
-                   "precision": a.precision, "exact_forward": a.exact, "lr": lr,
+                   "precision": a.precision, "exact_forward": a.exact, "ozaki_forward": a.ozaki, "lr": lr,
                    "single_backward": a.single_backward,
                    "step": ("split-bf16 (hi/lo, three products) forward; one-product bf16 backward (hi*hi) with "
                             "Adam in its epilogue; FP64 residual and loss")
-                   if (a.precision == "bf16x3" and a.single_backward and not a.exact) else None},
+                   if (a.precision == "bf16x3" and a.single_backward and not a.exact and not a.ozaki) else None},
         "roofline": {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1)",
                      "algorithmic_flops": flops[dom], "avg_ms": per_launch[dom],
-                     "executed_mfma_factor": (1 if (dom == "rw" and a.single_backward) else 3)
-                     if (a.precision == "bf16x3" and not (a.exact and dom == "gram")) else 1},
+                     "executed_mfma_factor": (21 if (a.ozaki and not a.exact and dom == "gram") else
+                                              (1 if (dom == "rw" and a.single_backward) else 3)
+                                              if (a.precision == "bf16x3" and not (a.exact and dom == "gram"))
+                                              else 1)},
         "kernels_ms_per_step": {name: kern[name][0] / a.steps for name in kern},
         "loss": float(loss.item()),
     }
-    if a.precision == "bf16x3" and a.single_backward and not a.exact:
+    if a.precision == "bf16x3" and a.single_backward and not a.exact and not a.ozaki:
         # the same step with the three-product (hi/lo) backward: separate R W GEMM, then Adam
         st2 = pl.new_state()
         fl2 = 0
@@ -519,11 +531,12 @@ def main():
     torch.cuda.empty_cache()
     if not a.no_ttt:
         out["ttt"] = {}
-        for name, prec, single in (("mixed", "bf16x3", True), ("fp32", "fp32", False)):
-            r = ttt_run(S, torch, a, c, W_start, p, prec, single)
+        for name, prec, single, fin in (("mixed", "bf16x3", True, "fp64"), ("mixed_ozaki", "bf16x3", True, "ozaki"),
+                                        ("fp32", "fp32", False, "fp64")):
+            r = ttt_run(S, torch, a, c, W_start, p, prec, single, fin)
             out["ttt"][name] = {q: r[q] for q in ("seconds", "steps", "exact_steps", "rel", "best_rel", "certified",
                                                   "precision", "lr", "lr_exact", "switch_rel", "single_backward",
-                                                  "tol")}
+                                                  "tol", "finisher")}
             print(f"ttt {name}: {r['seconds']:.2f} s, {r['steps']} steps ({r['exact_steps']} exact), "
                   f"rel {r['rel']:.3g}", file=sys.stderr, flush=True)
         m, f = out["ttt"]["mixed"], out["ttt"]["fp32"]

@@ -97,6 +97,18 @@ enum sos_flags {
    * the split-bf16 forward and the FP64 one in accuracy and cost).
    * SOS_FLAG_EXACT_FORWARD takes precedence.                              */
   SOS_FLAG_FP32_FORWARD = 8,
+  /* SOS_FP32 and SOS_BF16X3 plans: an FP64-accurate forward from int8
+   * MFMA (Ozaki splitting, Ozaki-Ogita-Oishi-Rump 2012).  Each row of W is
+   * scaled by a power of two and cut into 6 signed 7-bit digit slices; the
+   * slice products of levels s + t < 6 are summed exactly in int32, the
+   * levels combined in FP64.  Per Gram entry the error is at most
+   * 7.05 * 2^-42 * rank * 2^(e_i + e_j), 2^e_i being the least power of two
+   * above row i's largest magnitude (plus FP64 rounding), so it reaches the
+   * residuals the exact forward reaches, on matrix cores of twice the BF16
+   * rate.  SOS_ERANGE when rank exceeds 87,360 (the int32 level sums would
+   * overflow); SOS_EINVAL for SOS_FP64 plans.  SOS_FLAG_EXACT_FORWARD takes
+   * precedence.  sos_verify keeps the FP64-MFMA forward.                  */
+  SOS_FLAG_OZAKI_FORWARD = 16,
 };
 
 /* Adam hyper-parameters (Kingma and Ba; the paper's optimiser, Section 3). */
@@ -130,7 +142,9 @@ typedef struct {
                             back this way; before any finite check it ends
                             the solve with SOS_ENUMERIC                     */
   int32_t single_backward; /* 1: steps use SOS_FLAG_SINGLE_BACKWARD         */
-  int32_t reserved;
+  int32_t finisher;      /* forward of the exact phase: 0 FP64 MFMA
+                            (SOS_FLAG_EXACT_FORWARD), 1 int8 slices
+                            (SOS_FLAG_OZAKI_FORWARD)                        */
   double mid_rel;        /* SOS_BF16X3 ladder with a middle rung: after the
                             fast phase, steps use SOS_FLAG_FP32_FORWARD until
                             rel <= mid_rel (or a stall), then the exact

@@ -24,6 +24,7 @@ FLAG_EXACT_FORWARD = 1
 FLAG_COPIES_VALID = 2
 FLAG_SINGLE_BACKWARD = 4
 FLAG_FP32_FORWARD = 8
+FLAG_OZAKI_FORWARD = 16
 OK, NOT_CONVERGED = 0, 1
 EINVAL, ERANGE, ENOMEM, EHIP, ENUMERIC = -1, -2, -3, -4, -5
 
@@ -45,7 +46,7 @@ class _SolveOpts(ctypes.Structure):
                 ("stall_checks", ctypes.c_int32), ("stall_ratio", ctypes.c_double),
                 ("switch_rel", ctypes.c_double), ("lr_exact", ctypes.c_double),
                 ("rollback_ratio", ctypes.c_double), ("single_backward", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("mid_rel", ctypes.c_double)]
+                ("finisher", ctypes.c_int32), ("mid_rel", ctypes.c_double)]
 
 
 class _Result(ctypes.Structure):
@@ -197,7 +198,7 @@ class Plan:
         return out
 
     def loss_grad(self, W, p, grad=True, want_r=False, exact=False, single_backward=False,
-                  fp32_forward=False, stream=None):
+                  fp32_forward=False, ozaki=False, stream=None):
         self._w(W), self._p(p)
         loss = torch.empty(1, dtype=torch.float64, device=self.device)
         g = torch.empty_like(W) if grad else None
@@ -205,11 +206,12 @@ class Plan:
         _check(_lib.sos_loss_grad(self._h, _ptr(W), _ptr(p), _ptr(loss), _ptr(g), _ptr(r),
                                   (FLAG_EXACT_FORWARD if exact else 0) |
                                   (FLAG_SINGLE_BACKWARD if single_backward else 0) |
-                                  (FLAG_FP32_FORWARD if fp32_forward else 0), _stream(stream)))
+                                  (FLAG_FP32_FORWARD if fp32_forward else 0) |
+                                  (FLAG_OZAKI_FORWARD if ozaki else 0), _stream(stream)))
         return loss, g, r
 
     def loss_grad_noalloc(self, W, p, loss, g=None, r=None, exact=False, single_backward=False,
-                          fp32_forward=False, stream=None):
+                          fp32_forward=False, ozaki=False, stream=None):
         """sos_loss_grad_noalloc on an unbound plan (bind=False): the outputs
         (loss, and g and r when given) are caller tensors, so the call makes
         no device allocation at all."""
@@ -217,7 +219,8 @@ class Plan:
         _check(_lib.sos_loss_grad_noalloc(self._h, _ptr(W), _ptr(p), _ptr(loss), _ptr(g), _ptr(r),
                                           (FLAG_EXACT_FORWARD if exact else 0) |
                                           (FLAG_SINGLE_BACKWARD if single_backward else 0) |
-                                          (FLAG_FP32_FORWARD if fp32_forward else 0), _stream(stream)))
+                                          (FLAG_FP32_FORWARD if fp32_forward else 0) |
+                                          (FLAG_OZAKI_FORWARD if ozaki else 0), _stream(stream)))
         return loss, g, r
 
     def step(self, W, state, t, p, adam: Adam, loss=None, flags=0, stream=None):
@@ -248,12 +251,14 @@ class Plan:
 
     def solve(self, W, p, adam: Adam, tol=1e-8, max_steps=10000, check_every=50, ladder=True,
               stall_checks=4, stall_ratio=0.7, switch_rel=0.0, lr_exact=0.0, rollback_ratio=0.0,
-              single_backward=False, mid_rel=0.0, state=None, stream=None):
-        """sos_solve: Adam to an FP64-verified ||r||/||p|| <= tol; W ends as the best iterate."""
+              single_backward=False, mid_rel=0.0, finisher="fp64", state=None, stream=None):
+        """sos_solve: Adam to an FP64-verified ||r||/||p|| <= tol; W ends as the best iterate.
+        finisher: forward of the exact phase, "fp64" (FP64 MFMA) or "ozaki" (int8 slices)."""
         self._w(W), self._p(p)
         state = self.new_state() if state is None else state
+        fin = {"fp64": 0, "ozaki": 1}[finisher]
         opts = _SolveOpts(tol, max_steps, check_every, 1 if ladder else 0, stall_checks, stall_ratio,
-                          switch_rel, lr_exact, rollback_ratio, 1 if single_backward else 0, 0, mid_rel)
+                          switch_rel, lr_exact, rollback_ratio, 1 if single_backward else 0, fin, mid_rel)
         res = _Result()
         _check(_lib.sos_solve(self._h, _ptr(W), _ptr(state), _ptr(p), ctypes.byref(adam.c()),
                               ctypes.byref(opts), ctypes.byref(res), _stream(stream)),

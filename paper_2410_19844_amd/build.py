@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsos.so")
-SOURCES = ["kernels.hip", "gemm_bf3.hip", "gemm_x64.hip", "batch.hip", "net.hip", "api.cpp", "plan.cpp"]
+SOURCES = ["kernels.hip", "gemm_bf3.hip", "gemm_x64.hip", "gemm_i8.hip", "batch.hip", "net.hip", "api.cpp", "plan.cpp"]
 
 # -packed-fp32-ops: never emit packed FP32 VALU instructions (they have given
 # silent wrong results on this hardware); hipcc's host pass warns that it does

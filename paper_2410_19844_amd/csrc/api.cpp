@@ -86,6 +86,7 @@ static double* scal(const sos_plan_s* p) { return (double*)(p->ws + p->lay.scal)
 static int fwd_mode(const sos_plan_s* p, int flags) {
   if (p->prec == SOS_FP64) return kFwdFast;
   if (flags & SOS_FLAG_EXACT_FORWARD) return kFwdExact;
+  if (flags & SOS_FLAG_OZAKI_FORWARD) return kFwdOzaki;
   if ((flags & SOS_FLAG_FP32_FORWARD) && p->prec == SOS_BF16X3) return kFwdF32;
   return kFwdFast;
 }
@@ -107,6 +108,8 @@ static int run_forward(sos_plan_s* p, const void* W, const double* d_p, int flag
     p->copies_valid = false;
     p->t_cur = 0;  // the preparation writes the transposed copy into t_hi
   }
+  // the int8 slices need the row maxima of W, so no GEMM epilogue leaves them: built every time
+  if (mode == kFwdOzaki) TIMED(SOS_K_PREP, launch_oz_slices(p, (const float*)W, s), "Ozaki slices");
   TIMED(SOS_K_INIT, launch_init_r(p, d_p, s), "init_r");
   TIMED(SOS_K_GRAM, launch_gram(p, mode, s), "gram");
   float* r32 = (grad && p->prec != SOS_FP64) ? (float*)(p->ws + p->lay.r32) : nullptr;
@@ -128,7 +131,7 @@ static int run_step(sos_plan_s* p, void* W, void* state, int64_t t, const double
                     const sos_adam_t& h, double* d_loss, int flags, hipStream_t s) {
   const int mode = fwd_mode(p, flags);
   const bool single = (flags & SOS_FLAG_SINGLE_BACKWARD) != 0;
-  const bool fuse = p->prec == SOS_BF16X3 && single && (mode == kFwdFast || mode == kFwdExact);
+  const bool fuse = p->prec == SOS_BF16X3 && single && (mode == kFwdFast || mode == kFwdExact || mode == kFwdOzaki);
   const bool reuse = fuse && (flags & SOS_FLAG_COPIES_VALID) && p->copies_valid && p->copies_W == W &&
                      p->copies_mode == mode;
   int rc = run_forward(p, W, d_p, flags, d_loss, true, s, reuse);
@@ -136,7 +139,7 @@ static int run_step(sos_plan_s* p, void* W, void* state, int64_t t, const double
   char* st = (char*)state;
   if (fuse) {
     TIMED(SOS_K_GATHER, launch_gather(p, false, s), "gather");
-    TIMED(SOS_K_RW, launch_rw_adam_bf3(p, W, st, st + slot_bytes(p), t, h, mode == kFwdExact, s),
+    TIMED(SOS_K_RW, launch_rw_adam_bf3(p, W, st, st + slot_bytes(p), t, h, mode, s),
           "backward + Adam");
     p->t_cur ^= 1;
     p->copies_valid = true;
@@ -148,6 +151,17 @@ static int run_step(sos_plan_s* p, void* W, void* state, int64_t t, const double
   rc = run_backward(p, g, !single, s);
   if (rc) return rc;
   TIMED(SOS_K_ADAM, launch_adam(p, W, st, st + slot_bytes(p), g, t, h, s), "adam");
+  return SOS_OK;
+}
+
+// The Ozaki forward needs an FP32 master W and a K extent whose level sums stay exact in int32.
+static int check_ozaki(const sos_plan_s* p, int flags, const char* fn) {
+  if (!(flags & SOS_FLAG_OZAKI_FORWARD) || (flags & SOS_FLAG_EXACT_FORWARD)) return SOS_OK;
+  if (p->prec == SOS_FP64)
+    return set_error(SOS_EINVAL, std::string(fn) + ": SOS_FLAG_OZAKI_FORWARD needs an FP32 or split plan");
+  if (!ozaki_supported(p))
+    return set_error(SOS_ERANGE, std::string(fn) + ": SOS_FLAG_OZAKI_FORWARD needs rank <= " +
+                                     std::to_string(kOzMaxK / kPadK * kPadK));
   return SOS_OK;
 }
 
@@ -286,8 +300,10 @@ int sos_loss_grad(sos_plan_t p, const void* d_W, const double* d_p, double* d_lo
                   double* d_r, int flags, void* stream) {
   if (int rc = check_bound(p, "sos_loss_grad")) return rc;
   if (!d_W || !d_p || !d_loss) return set_error(SOS_EINVAL, "sos_loss_grad: d_W, d_p and d_loss are required");
-  if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_SINGLE_BACKWARD | SOS_FLAG_FP32_FORWARD))
+  if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_SINGLE_BACKWARD | SOS_FLAG_FP32_FORWARD |
+                     SOS_FLAG_OZAKI_FORWARD))
     return set_error(SOS_EINVAL, "sos_loss_grad: unknown flags");
+  if (int rc = check_ozaki(p, flags, "sos_loss_grad")) return rc;
   hipStream_t s = (hipStream_t)stream;
   int rc = run_forward(p, d_W, d_p, flags, d_loss, d_grad != nullptr, s);
   if (rc) return rc;
@@ -304,8 +320,9 @@ int sos_step(sos_plan_t p, void* d_W, void* d_state, int64_t t, const double* d_
   if (!d_W || !d_state || !d_p || !d_loss) return set_error(SOS_EINVAL, "sos_step: NULL device pointer");
   if (t < 1) return set_error(SOS_EINVAL, "sos_step: t is 1-based");
   if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_COPIES_VALID | SOS_FLAG_SINGLE_BACKWARD |
-                     SOS_FLAG_FP32_FORWARD))
+                     SOS_FLAG_FP32_FORWARD | SOS_FLAG_OZAKI_FORWARD))
     return set_error(SOS_EINVAL, "sos_step: unknown flags");
+  if (int rc = check_ozaki(p, flags, "sos_step")) return rc;
   return run_step(p, d_W, d_state, t, d_p, *adam, d_loss, flags, (hipStream_t)stream);
 }
 
@@ -397,8 +414,10 @@ int sos_loss_grad_noalloc(sos_plan_t p, const void* d_W, const double* d_p, doub
     return set_error(SOS_EINVAL, "sos_loss_grad_noalloc: plan is bound to a workspace (use sos_loss_grad)");
   if (!d_W || !d_p || !d_loss)
     return set_error(SOS_EINVAL, "sos_loss_grad_noalloc: d_W, d_p and d_loss are required");
-  if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_SINGLE_BACKWARD | SOS_FLAG_FP32_FORWARD))
+  if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_SINGLE_BACKWARD | SOS_FLAG_FP32_FORWARD |
+                     SOS_FLAG_OZAKI_FORWARD))
     return set_error(SOS_EINVAL, "sos_loss_grad_noalloc: unknown flags");
+  if (int rc = check_ozaki(p, flags, "sos_loss_grad_noalloc")) return rc;
   if (p->lay.bytes > (size_t)SOS_NOALLOC_MAX_WS)
     return set_error(SOS_ERANGE, "sos_loss_grad_noalloc: the plan needs a workspace of " +
                                      std::to_string(p->lay.bytes) + " bytes, above the static " +
@@ -432,6 +451,9 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
       !(o->rollback_ratio >= 0) || o->stall_checks < 0)
     return set_error(SOS_EINVAL, "sos_solve: needs max_steps >= 0, check_every >= 1, tol, lr_exact, "
                                  "rollback_ratio >= 0 and stall_checks >= 0");
+  if (o->finisher != 0 && o->finisher != 1) return set_error(SOS_EINVAL, "sos_solve: finisher must be 0 or 1");
+  if (o->finisher && o->ladder)
+    if (int rc = check_ozaki(p, SOS_FLAG_OZAKI_FORWARD, "sos_solve")) return rc;
   hipStream_t s = (hipStream_t)stream;
   std::memset(res, 0, sizeof(*res));
   const size_t slot = slot_bytes(p), wbytes = (size_t)p->N * p->k * w_elem(p);
@@ -470,7 +492,8 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
     ++t_adam;
     const bool check = (t % o->check_every == 0) || t == o->max_steps;
     if (check) SOS_HIP(hipMemcpyAsync(cand, d_W, wbytes, hipMemcpyDeviceToDevice, s), "sos_solve: snapshot");
-    const int flags = (phase == 2 ? SOS_FLAG_EXACT_FORWARD : phase == 1 ? SOS_FLAG_FP32_FORWARD : 0) |
+    const int exact_flag = o->finisher ? SOS_FLAG_OZAKI_FORWARD : SOS_FLAG_EXACT_FORWARD;
+    const int flags = (phase == 2 ? exact_flag : phase == 1 ? SOS_FLAG_FP32_FORWARD : 0) |
                       (o->single_backward ? SOS_FLAG_SINGLE_BACKWARD : 0) |
                       (w_moved ? 0 : SOS_FLAG_COPIES_VALID);
     int rc = run_step(p, d_W, st, t_adam, d_p, h, sc + 0, flags, s);

@@ -418,6 +418,7 @@ struct RwAdamArgs {
   __bf16* a_hi;       // next forward, split copy (fast forward), or nullptr
   __bf16* a_lo;
   float* x_f32;       // next forward, FP32 blocked copy (exact forward), or nullptr
+                      // (both nullptr: the next forward builds its own operands)
   __bf16* t_next;     // next backward: transposed copy
   int64_t aps, xps, tps;         // panel strides of those layouts
   int64_t Np, Kp, Np2, Kp2;
@@ -501,7 +502,7 @@ __global__ __launch_bounds__(NT) void k_rw_adam_bf3(RwAdamArgs a) {
         if (i < a.Np && l < a.Kp) {
           if (a.x_f32) {
             a.x_f32[blk_off(i, l, a.xps)] = w;
-          } else {
+          } else if (a.a_hi) {
             const __bf16 h = (__bf16)w;
             const int64_t ob = blk_off(i, l, a.aps);
             a.a_hi[ob] = h;
@@ -575,7 +576,7 @@ hipError_t launch_rw_bf3(const sos_plan_s* p, void* g, bool split, hipStream_t s
 namespace sos {
 
 hipError_t launch_rw_adam_bf3(const sos_plan_s* p, void* W, void* m, void* v, int64_t t, const sos_adam_t& h,
-                              bool exact_next, hipStream_t s) {
+                              int next_mode, hipStream_t s) {
   bf3::RwAdamArgs a;
   bf3::RwArgs& r = a.rw;
   char* ws = p->ws;
@@ -601,9 +602,9 @@ hipError_t launch_rw_adam_bf3(const sos_plan_s* p, void* W, void* m, void* v, in
   a.eps = (float)h.eps;
   a.bc1 = (float)(1.0 - pow(h.beta1, (double)t));
   a.bc2 = (float)(1.0 - pow(h.beta2, (double)t));
-  a.a_hi = exact_next ? nullptr : (__bf16*)(ws + p->lay.a_hi);
-  a.a_lo = exact_next ? nullptr : (__bf16*)(ws + p->lay.a_lo);
-  a.x_f32 = exact_next ? (float*)(ws + p->lay.x_f32) : nullptr;
+  a.a_hi = next_mode == kFwdFast ? (__bf16*)(ws + p->lay.a_hi) : nullptr;
+  a.a_lo = next_mode == kFwdFast ? (__bf16*)(ws + p->lay.a_lo) : nullptr;
+  a.x_f32 = next_mode == kFwdExact ? (float*)(ws + p->lay.x_f32) : nullptr;
   a.t_next = (__bf16*)(ws + t_write);
   a.aps = panel_stride(p->Kp / kBlkK, 2);
   a.xps = panel_stride(p->Kp / kBlkK, 4);

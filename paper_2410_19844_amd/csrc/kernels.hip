@@ -723,6 +723,7 @@ hipError_t launch_gram(const sos_plan_s* p, int mode, hipStream_t s) {
   // FP32 padded row-major copy of W: a_hi in FP32 plans, a_f32 in split plans
   const void* w32 = (p->prec == SOS_FP32) ? ws + p->lay.a_hi : ws + p->lay.a_f32;
   if (mode == kFwdExact) return launch_gram_x64(p, s);
+  if (mode == kFwdOzaki) return launch_gram_i8(p, s);
   if (mode == kFwdF32 || p->prec == SOS_FP32) return gram_launch<MF32>(p, w32, nullptr, s);
   return launch_gram_bf3(p, s);
 }

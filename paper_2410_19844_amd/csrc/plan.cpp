@@ -202,6 +202,12 @@ int plan_create(int n, int d, int rank, int prec, sos_plan_s** out) {
   if (prec == SOS_BF16X3) L.a_f32 = take((size_t)p->Np * p->Kp * 4);
   if (prec != SOS_FP64) L.x_f32 = take((size_t)(p->Np / kBlkRows) * panel_stride(p->Kp / kBlkK, 4) * 4);
   L.g = take((size_t)N * rank * wel);
+  if (prec != SOS_FP64) {  // Ozaki-split forward: int8 slices, row exponents and scales
+    L.oz_slice = (size_t)(p->Np / kBlkRows) * oz_panel_stride(p->Kp);
+    L.oz = take(L.oz_slice * kOzSlices);
+    L.oz_exp = take((size_t)N * 4);
+    L.oz_scale = take((size_t)N * 8);
+  }
   // Grouped serving path: the coefficient of monomial m sums the Gram entries
   // of its pairs (i <= j, alpha_i + alpha_j = m) in one fixed order (i, then
   // j, ascending), so a problem's forward is deterministic.  The pair lists

@@ -40,6 +40,25 @@ constexpr int kBlkRows = 256;
 constexpr int kBlkK = 16;
 constexpr int kPanelPadBytes = 4096;
 
+// Ozaki-split forward (an FP64-accurate Gram from int8 MFMA): each row i of
+// the FP32 W is scaled by 2^-e_i, e_i the least power of two above the row's
+// largest magnitude, and cut into kOzSlices signed digits of 7 bits
+// (|digit| <= 64), most significant first.  The slices are int8 arrays in a
+// panel-blocked layout like the bf16 operands: rows in panels of 256, K in
+// blocks of 64, block (panel, kb) = 256 rows x 64 bytes contiguous (16 KB).
+// A slice product summed over K is exact in int32 while
+// kOzSlices * Kp * 64^2 < 2^31 (the level sums below add up to kOzSlices
+// products), i.e. for K extents below 87,381.
+constexpr int kOzSlices = 6;
+constexpr int kOzBK = 64;
+__host__ __device__ inline int64_t oz_panel_stride(int64_t Kp) {  // bytes
+  return (Kp / kOzBK) * kBlkRows * kOzBK + kPanelPadBytes;
+}
+__host__ __device__ inline int64_t oz_off(int64_t row, int64_t k, int64_t pstride) {
+  return (row / kBlkRows) * pstride + ((k / kOzBK) * kBlkRows + row % kBlkRows) * kOzBK + k % kOzBK;
+}
+constexpr int64_t kOzMaxK = ((int64_t(1) << 31) - 1) / (kOzSlices * 64 * 64);
+
 // Grouped serving kernels: the contraction length a block covers, and the
 // number of such slices (each with its own partial result) for length len.
 constexpr int kBatchSlice = 256;    // K slices of the Gram
@@ -182,6 +201,10 @@ struct Layout {
   size_t a_f32 = 0;              // FP32 padded W (split-precision plans), rows = Np, ld = Kp
   size_t x_f32 = 0;              // FP32 W, panel-blocked (exact forward), rows = Np, K extent Kp
   size_t g = 0;                  // gradient scratch, N x k in W's type
+  size_t oz = 0;                 // Ozaki slices: kOzSlices arrays of oz_slice bytes (FP32-master plans)
+  size_t oz_slice = 0;           // bytes per slice array: (Np / 256) panels of oz_panel_stride(Kp)
+  size_t oz_exp = 0;             // N int32: row exponents e_i
+  size_t oz_scale = 0;           // N doubles: 2^(e_i - 6), NaN for a row holding a non-finite entry
   // grouped (serving) path, FP32 plans with N <= SOS_BATCH_MAX_N only
   size_t bG = 0;                 // FP64 partial Gram per K slice: batch_slices(k) x P, entries in pair-list order
   size_t pair_pos = 0;           // N x N int32: position of pair (min(i,j), max(i,j)) in the pair lists
@@ -311,18 +334,24 @@ hipError_t launch_prep(const sos_plan_s* p, const void* W, const PrepNeeds& need
 hipError_t launch_init_r(const sos_plan_s* p, const double* d_p, hipStream_t s);
 hipError_t launch_sumsq(const sos_plan_s* p, const double* x, int64_t M, double* out, hipStream_t s,
                         float* x32 = nullptr);
-enum { kFwdFast = 0, kFwdF32 = 1, kFwdExact = 2 };
+enum { kFwdFast = 0, kFwdF32 = 1, kFwdExact = 2, kFwdOzaki = 3 };
 hipError_t launch_gram(const sos_plan_s* p, int mode, hipStream_t s);
 hipError_t launch_gather(const sos_plan_s* p, bool split, hipStream_t s);
 hipError_t launch_rw(const sos_plan_s* p, void* g, bool split, hipStream_t s);
 hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s);
 hipError_t launch_gram_x64(const sos_plan_s* p, hipStream_t s);
+// Ozaki-split forward (gemm_i8.hip): row exponents and int8 slices of W, then the gram
+hipError_t launch_oz_slices(const sos_plan_s* p, const float* W, hipStream_t s);
+hipError_t launch_gram_i8(const sos_plan_s* p, hipStream_t s);
+inline bool ozaki_supported(const sos_plan_s* p) { return p->prec != SOS_FP64 && p->Kp <= kOzMaxK; }
 hipError_t launch_rw_bf3(const sos_plan_s* p, void* g, bool split, hipStream_t s);
 hipError_t launch_adam(const sos_plan_s* p, void* W, void* m, void* v, const void* g, int64_t t,
                        const sos_adam_t& h, hipStream_t s);
 // single-product backward with Adam and the next step's copies in the epilogue
+// next_mode: the forward mode of the next step (kFwdFast: write the split copy,
+// kFwdExact: the FP32 blocked copy, otherwise no forward copy)
 hipError_t launch_rw_adam_bf3(const sos_plan_s* p, void* W, void* m, void* v, int64_t t, const sos_adam_t& h,
-                              bool exact_next, hipStream_t s);
+                              int next_mode, hipStream_t s);
 // two-layer network (net.hip)
 // fp64: P, W and dW are double (FP64 plans), else float
 hipError_t launch_net_forward(bool fp64, int n, int m, int k, int N, const float* At, const float* Bt, void* P,
