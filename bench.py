@@ -41,14 +41,15 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAKS_TFLOPS = {"bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6, "int8": 5000.0}
+PEAKS_TFLOPS = {"bf16x3": 2500.0, "fp16x3": 2500.0, "fp32": 157.3, "fp64": 78.6, "int8": 5000.0}
+SPLIT = ("bf16x3", "fp16x3")   # split 16-bit operand plans
 # Adam step sizes (bulk, exact-forward finisher) per workload, chosen by a
 # short sweep of time to 1e-8 and then frozen.  The q100 finisher takes the
 # middle of the range (1.5e-3 to 2.5e-3) where the step count does not move
 # when the rounding order of the forward's sums changes; at 3e-3 it swings
 # between about 500 and 2200 steps.
 LR_DEFAULTS = {"n12d6": (3e-3, 1e-3), "q100": (3e-3, 2e-3)}
-DTYPE = {"bf16x3": "bf16", "fp32": "fp32", "fp64": "fp64"}
+DTYPE = {"bf16x3": "bf16", "fp16x3": "fp16", "fp32": "fp32", "fp64": "fp64"}
 
 
 def parse():
@@ -61,6 +62,10 @@ def parse():
     ap.add_argument("--exact", action="store_true", help="FP64 forward (the finishing phase)")
     ap.add_argument("--ozaki", action="store_true",
                     help="FP64-accurate forward from int8 slices (Ozaki splitting) instead of the fast one")
+    ap.add_argument("--unfused-scatter", action="store_true",
+                    help="step: the gram stores its tiles and a separate kernel scatters them (measures the scatter)")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="step: FP32/FP64 plans, the forward sums each coefficient in a fixed order (no atomics)")
     ap.add_argument("--finisher", choices=("fp64", "ozaki"), default=None,
                     help="ttt: forward of the exact phase (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -288,7 +293,7 @@ def ttt_run(S, torch, a, c, W_host, p, precision, single_backward, finisher=None
     lr_bulk, lr_fin = LR_DEFAULTS.get(c.name, (3e-3, 1e-3))
     lr = a.lr if a.lr is not None else lr_bulk
     lr_exact = a.lr_exact if a.lr_exact is not None else lr_fin
-    switch_rel = a.switch_rel if a.switch_rel is not None else {"bf16x3": 3e-6, "fp32": 1e-6, "fp64": 0.0}[precision]
+    switch_rel = a.switch_rel if a.switch_rel is not None else {"bf16x3": 3e-6, "fp16x3": 3e-6, "fp32": 1e-6, "fp64": 0.0}[precision]
     mid_rel = a.mid_rel if a.mid_rel is not None else 0.0
     pl = S.Plan(c.n, c.d, c.rank, precision)
     wdt = torch.float64 if precision == "fp64" else torch.float32
@@ -414,7 +419,7 @@ def main():
         net_mode(a, S, torch)
         return
     c, W, p = make_inputs(S, torch, a.workload, a.precision, a.rank)
-    a.single_backward = a.precision == "bf16x3" and not a.split_backward
+    a.single_backward = a.precision in SPLIT and not a.split_backward
 
     if a.mode == "ttt":
         res = ttt_run(S, torch, a, c, W.cpu(), p, a.precision, a.single_backward)
@@ -438,7 +443,9 @@ def main():
     adam = S.Adam(lr=lr)
     stream = torch.cuda.current_stream()
     flags = ((S.FLAG_EXACT_FORWARD if a.exact else 0) | (S.FLAG_OZAKI_FORWARD if a.ozaki else 0)
-             | (S.FLAG_SINGLE_BACKWARD if a.single_backward else 0))
+             | (S.FLAG_SINGLE_BACKWARD if a.single_backward else 0)
+             | (S.FLAG_UNFUSED_SCATTER if a.unfused_scatter else 0)
+             | (S.FLAG_DETERMINISTIC if a.deterministic else 0))
 
     if a.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -476,7 +483,7 @@ def main():
         peak = PEAKS_TFLOPS[a.precision]
     achieved = flops[dom] / (per_launch[dom] * 1e-3) / 1e12
     traffic = None
-    if c.name == "n12d6" and a.precision == "bf16x3" and a.single_backward and not a.ozaki:
+    if c.name == "n12d6" and a.precision == "bf16x3" and a.single_backward and not (a.ozaki or a.unfused_scatter):
         key = {("gram", False): "step:k_gram_bf3", ("gram", True): "exact:k_gram_x64",
                ("rw", False): "step:k_rw_adam_bf3", ("rw", True): "step:k_rw_adam_bf3"}[(dom, a.exact)]
         traffic = measured_traffic(key)
@@ -494,19 +501,34 @@ def main():
                    "single_backward": a.single_backward,
                    "step": ("split-bf16 (hi/lo, three products) forward; one-product bf16 backward (hi*hi) with "
                             "Adam in its epilogue; FP64 residual and loss")
-                   if (a.precision == "bf16x3" and a.single_backward and not a.exact and not a.ozaki) else None},
+                   if (a.precision in SPLIT and a.single_backward and not a.exact and not a.ozaki) else None},
         "roofline": {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1)",
                      "algorithmic_flops": flops[dom], "avg_ms": per_launch[dom],
                      "executed_mfma_factor": (21 if (a.ozaki and not a.exact and dom == "gram") else
                                               (1 if (dom == "rw" and a.single_backward) else 3)
-                                              if (a.precision == "bf16x3" and not (a.exact and dom == "gram"))
+                                              if (a.precision in SPLIT and not (a.exact and dom == "gram"))
                                               else 1)},
         "kernels_ms_per_step": {name: kern[name][0] / a.steps for name in kern},
         "loss": float(loss.item()),
     }
-    if a.precision == "bf16x3" and a.single_backward and not a.exact and not a.ozaki:
+    # HBM-bound kernels against the 8 TB/s peak, algorithmic bytes per launch:
+    # the gather writes R (N^2 operand elements) and reads r32 (M floats); the
+    # unfused scatter reads the N (N + 1) / 2 stored FP32 Gram entries and
+    # reads and writes r (M doubles)
+    hbm = {}
+    if kern["gather"][1] and a.precision != "fp64":
+        nbytes = float(N) * N * (2 if a.precision in SPLIT else 4) * (1 if a.single_backward or a.precision not in SPLIT else 2) + 4.0 * c.M
+        ms = kern["gather"][0] / kern["gather"][1]
+        hbm["gather"] = {"bytes": nbytes, "avg_ms": ms, "GB_s": nbytes / ms / 1e6, "frac": nbytes / ms / 1e6 / 8000.0}
+    if kern["scatter"][1]:
+        nbytes = 4.0 * N * (N + 1) / 2 + 16.0 * c.M
+        ms = kern["scatter"][0] / kern["scatter"][1]
+        hbm["scatter"] = {"bytes": nbytes, "avg_ms": ms, "GB_s": nbytes / ms / 1e6, "frac": nbytes / ms / 1e6 / 8000.0}
+    if hbm:
+        out["hbm"] = dict(hbm, peak_GB_s=8000.0)
+    if a.precision in SPLIT and a.single_backward and not (a.exact or a.ozaki or a.unfused_scatter):
         # the same step with the three-product (hi/lo) backward: separate R W GEMM, then Adam
         st2 = pl.new_state()
         fl2 = 0
@@ -525,7 +547,7 @@ def main():
         out["split_backward"] = {"ms_per_step": ev0.elapsed_time(ev1) / nsb, "steps": nsb,
                                  "kernels_ms_per_step": {q: kern2[q][0] / nsb for q in kern2},
                                  "rw_frac_of_peak_executed": 3 * flops["rw"] / (kern2["rw"][0] / nsb * 1e-3) / 1e12
-                                 / PEAKS_TFLOPS["bf16x3"]}
+                                 / PEAKS_TFLOPS[a.precision]}
         del st2
     del pl, st, W
     torch.cuda.empty_cache()

@@ -62,6 +62,16 @@ enum sos_precision {
   SOS_BF16X3 = 2,  /* W float master; each operand split into bf16 hi + lo,
                       three bf16 MFMA products (hi*hi + hi*lo + lo*hi) with
                       FP32 accumulation                                    */
+  SOS_FP16X3 = 3,  /* as SOS_BF16X3 with fp16 halves (11 significant bits
+                      each against bf16's 8, at the same MFMA rate).  fp16
+                      has a narrow exponent range, so the W copies are
+                      scaled by 2^sW (2^sW max|W| < 2^12, set when the
+                      copies are built from W and kept by the fused steps:
+                      W may grow 16x before the copies overflow) and R by
+                      2^sR (2^sR max|r| < 2^14, every step); the GEMM
+                      epilogues divide the powers of two out exactly.
+                      Halves below fp16's normal range keep an absolute
+                      error of 2^-25 in scaled units.                      */
 };
 
 enum sos_status {
@@ -88,13 +98,14 @@ enum sos_flags {
    * forward mode skips rebuilding them.  Ignored whenever the library holds
    * no such copies (other modes, another call on the plan in between).    */
   SOS_FLAG_COPIES_VALID = 2,
-  /* SOS_BF16X3 only: the backward takes one bf16 product per element pair
-   * (hi * hi) instead of three.  The gradient 4 R W then carries a relative
-   * error of about 2^-8 per term; it still vanishes where R does (at an
-   * exact fit), so the fixed point is unchanged.  Ignored for other modes. */
+  /* SOS_BF16X3 and SOS_FP16X3: the backward takes one 16-bit product per
+   * element pair (hi * hi) instead of three.  The gradient 4 R W then
+   * carries a relative error of about 2^-8 (bf16) or 2^-11 (fp16) per term;
+   * it still vanishes where R does (at an exact fit), so the fixed point is
+   * unchanged.  Ignored for other modes.                                   */
   SOS_FLAG_SINGLE_BACKWARD = 4,
-  /* SOS_BF16X3 only: forward with FP32 MFMA on the FP32 master W (between
-   * the split-bf16 forward and the FP64 one in accuracy and cost).
+  /* SOS_BF16X3 and SOS_FP16X3: forward with FP32 MFMA on the FP32 master W
+   * (between the split forward and the FP64 one in accuracy and cost).
    * SOS_FLAG_EXACT_FORWARD takes precedence.                              */
   SOS_FLAG_FP32_FORWARD = 8,
   /* SOS_FP32 and SOS_BF16X3 plans: an FP64-accurate forward from int8
@@ -109,6 +120,21 @@ enum sos_flags {
    * overflow); SOS_EINVAL for SOS_FP64 plans.  SOS_FLAG_EXACT_FORWARD takes
    * precedence.  sos_verify keeps the FP64-MFMA forward.                  */
   SOS_FLAG_OZAKI_FORWARD = 16,
+  /* SOS_FP32 and SOS_FP64 plans with N <= SOS_BATCH_MAX_N, the plan's own
+   * forward only: instead of adding each Gram entry into r by FP64 atomics
+   * (whose order varies from run to run), the gram stores its tiles (one
+   * copy per contraction slice) and each coefficient then sums its pairs in
+   * the plan's fixed pair order.  Results then depend on W and p alone:
+   * repeated runs, and a run resumed from a checkpoint, follow the same
+   * trajectory bit for bit.  SOS_EINVAL for other plans or with
+   * SOS_FLAG_EXACT_FORWARD / SOS_FLAG_OZAKI_FORWARD on an FP32 plan.      */
+  SOS_FLAG_DETERMINISTIC = 32,
+  /* SOS_BF16X3 plans, fast forward, a measurement variant: the gram stores
+   * its FP32 tiles (256 x 256 per upper tile, in the workspace) instead of
+   * scattering them in its epilogue, and a separate kernel (timing class
+   * SOS_K_SCATTER) ranks and adds them into r.  Same result as the fused
+   * forward up to the order of the FP64 additions; slower.                */
+  SOS_FLAG_UNFUSED_SCATTER = 64,
 };
 
 /* Adam hyper-parameters (Kingma and Ba; the paper's optimiser, Section 3). */
@@ -149,6 +175,9 @@ typedef struct {
                             fast phase, steps use SOS_FLAG_FP32_FORWARD until
                             rel <= mid_rel (or a stall), then the exact
                             forward (0: no middle rung)                     */
+  int32_t step_flags;    /* SOS_FLAG_DETERMINISTIC or 0: added to the steps
+                            of the plan's own forward                       */
+  int32_t reserved;
 } sos_solve_opts_t;
 
 typedef struct {
@@ -352,7 +381,8 @@ enum sos_kernel_class {
   SOS_K_GATHER = 4,  /* R from r                                          */
   SOS_K_RW = 5,      /* R W backward                                      */
   SOS_K_ADAM = 6,    /* Adam update                                       */
-  SOS_K_COUNT = 7
+  SOS_K_SCATTER = 7, /* scatter of stored Gram tiles (SOS_FLAG_UNFUSED_SCATTER) */
+  SOS_K_COUNT = 8
 };
 
 /* Per-kernel timing with HIP events around this plan's launches (tracing

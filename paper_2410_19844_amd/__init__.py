@@ -18,13 +18,15 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libsos.so")
 
-FP64, FP32, BF16X3 = 0, 1, 2
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+FP64, FP32, BF16X3, FP16X3 = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3}
 FLAG_EXACT_FORWARD = 1
 FLAG_COPIES_VALID = 2
 FLAG_SINGLE_BACKWARD = 4
 FLAG_FP32_FORWARD = 8
 FLAG_OZAKI_FORWARD = 16
+FLAG_DETERMINISTIC = 32
+FLAG_UNFUSED_SCATTER = 64
 OK, NOT_CONVERGED = 0, 1
 EINVAL, ERANGE, ENOMEM, EHIP, ENUMERIC = -1, -2, -3, -4, -5
 
@@ -46,7 +48,8 @@ class _SolveOpts(ctypes.Structure):
                 ("stall_checks", ctypes.c_int32), ("stall_ratio", ctypes.c_double),
                 ("switch_rel", ctypes.c_double), ("lr_exact", ctypes.c_double),
                 ("rollback_ratio", ctypes.c_double), ("single_backward", ctypes.c_int32),
-                ("finisher", ctypes.c_int32), ("mid_rel", ctypes.c_double)]
+                ("finisher", ctypes.c_int32), ("mid_rel", ctypes.c_double),
+                ("step_flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -100,7 +103,7 @@ EXPORTS = ("sos_plan", "sos_plan_query", "sos_plan_bind", "sos_plan_destroy", "s
            "sos_pair_ranks", "sos_loss_grad", "sos_loss_grad_noalloc", "sos_step", "sos_solve", "sos_verify",
            "sos_step_batch", "sos_loss_batch", "sos_net_query", "sos_net_weights", "sos_net_grad", "sos_net_step",
            "sos_net_solve", "sos_timing", "sos_timing_read", "sos_last_error")
-KERNEL_CLASSES = ("prep", "init_r", "gram", "loss", "gather", "rw", "adam")
+KERNEL_CLASSES = ("prep", "init_r", "gram", "loss", "gather", "rw", "adam", "scatter")
 
 
 def _check(rc: int, allow=(OK,)):
@@ -198,7 +201,7 @@ class Plan:
         return out
 
     def loss_grad(self, W, p, grad=True, want_r=False, exact=False, single_backward=False,
-                  fp32_forward=False, ozaki=False, stream=None):
+                  fp32_forward=False, ozaki=False, deterministic=False, unfused_scatter=False, stream=None):
         self._w(W), self._p(p)
         loss = torch.empty(1, dtype=torch.float64, device=self.device)
         g = torch.empty_like(W) if grad else None
@@ -207,7 +210,9 @@ class Plan:
                                   (FLAG_EXACT_FORWARD if exact else 0) |
                                   (FLAG_SINGLE_BACKWARD if single_backward else 0) |
                                   (FLAG_FP32_FORWARD if fp32_forward else 0) |
-                                  (FLAG_OZAKI_FORWARD if ozaki else 0), _stream(stream)))
+                                  (FLAG_OZAKI_FORWARD if ozaki else 0) |
+                                  (FLAG_DETERMINISTIC if deterministic else 0) |
+                                  (FLAG_UNFUSED_SCATTER if unfused_scatter else 0), _stream(stream)))
         return loss, g, r
 
     def loss_grad_noalloc(self, W, p, loss, g=None, r=None, exact=False, single_backward=False,
@@ -251,14 +256,16 @@ class Plan:
 
     def solve(self, W, p, adam: Adam, tol=1e-8, max_steps=10000, check_every=50, ladder=True,
               stall_checks=4, stall_ratio=0.7, switch_rel=0.0, lr_exact=0.0, rollback_ratio=0.0,
-              single_backward=False, mid_rel=0.0, finisher="fp64", state=None, stream=None):
+              single_backward=False, mid_rel=0.0, finisher="fp64", deterministic=False, state=None,
+              stream=None):
         """sos_solve: Adam to an FP64-verified ||r||/||p|| <= tol; W ends as the best iterate.
         finisher: forward of the exact phase, "fp64" (FP64 MFMA) or "ozaki" (int8 slices)."""
         self._w(W), self._p(p)
         state = self.new_state() if state is None else state
         fin = {"fp64": 0, "ozaki": 1}[finisher]
         opts = _SolveOpts(tol, max_steps, check_every, 1 if ladder else 0, stall_checks, stall_ratio,
-                          switch_rel, lr_exact, rollback_ratio, 1 if single_backward else 0, fin, mid_rel)
+                          switch_rel, lr_exact, rollback_ratio, 1 if single_backward else 0, fin, mid_rel,
+                          FLAG_DETERMINISTIC if deterministic else 0, 0)
         res = _Result()
         _check(_lib.sos_solve(self._h, _ptr(W), _ptr(state), _ptr(p), ctypes.byref(adam.c()),
                               ctypes.byref(opts), ctypes.byref(res), _stream(stream)),

@@ -87,7 +87,7 @@ static int fwd_mode(const sos_plan_s* p, int flags) {
   if (p->prec == SOS_FP64) return kFwdFast;
   if (flags & SOS_FLAG_EXACT_FORWARD) return kFwdExact;
   if (flags & SOS_FLAG_OZAKI_FORWARD) return kFwdOzaki;
-  if ((flags & SOS_FLAG_FP32_FORWARD) && p->prec == SOS_BF16X3) return kFwdF32;
+  if ((flags & SOS_FLAG_FP32_FORWARD) && split_plan(p)) return kFwdF32;
   return kFwdFast;
 }
 
@@ -110,8 +110,16 @@ static int run_forward(sos_plan_s* p, const void* W, const double* d_p, int flag
   }
   // the int8 slices need the row maxima of W, so no GEMM epilogue leaves them: built every time
   if (mode == kFwdOzaki) TIMED(SOS_K_PREP, launch_oz_slices(p, (const float*)W, s), "Ozaki slices");
-  TIMED(SOS_K_INIT, launch_init_r(p, d_p, s), "init_r");
-  TIMED(SOS_K_GRAM, launch_gram(p, mode, s), "gram");
+  if ((flags & SOS_FLAG_DETERMINISTIC) && mode == kFwdFast) {
+    TIMED(SOS_K_GRAM, launch_gram_det(p, d_p, s), "gram (deterministic)");
+  } else if ((flags & SOS_FLAG_UNFUSED_SCATTER) && mode == kFwdFast && p->prec == SOS_BF16X3) {
+    TIMED(SOS_K_INIT, launch_init_r(p, d_p, s), "init_r");
+    TIMED(SOS_K_GRAM, launch_gram_bf3(p, s, true), "gram (tiles stored)");
+    TIMED(SOS_K_SCATTER, launch_scatter_tiles(p, s), "scatter");
+  } else {
+    TIMED(SOS_K_INIT, launch_init_r(p, d_p, s), "init_r");
+    TIMED(SOS_K_GRAM, launch_gram(p, mode, s), "gram");
+  }
   float* r32 = (grad && p->prec != SOS_FP64) ? (float*)(p->ws + p->lay.r32) : nullptr;
   TIMED(SOS_K_LOSS, launch_sumsq(p, (const double*)(p->ws + p->lay.r), p->M, d_loss, s, r32), "loss");
   return SOS_OK;
@@ -131,7 +139,7 @@ static int run_step(sos_plan_s* p, void* W, void* state, int64_t t, const double
                     const sos_adam_t& h, double* d_loss, int flags, hipStream_t s) {
   const int mode = fwd_mode(p, flags);
   const bool single = (flags & SOS_FLAG_SINGLE_BACKWARD) != 0;
-  const bool fuse = p->prec == SOS_BF16X3 && single && (mode == kFwdFast || mode == kFwdExact || mode == kFwdOzaki);
+  const bool fuse = split_plan(p) && single && (mode == kFwdFast || mode == kFwdExact || mode == kFwdOzaki);
   const bool reuse = fuse && (flags & SOS_FLAG_COPIES_VALID) && p->copies_valid && p->copies_W == W &&
                      p->copies_mode == mode;
   int rc = run_forward(p, W, d_p, flags, d_loss, true, s, reuse);
@@ -151,6 +159,26 @@ static int run_step(sos_plan_s* p, void* W, void* state, int64_t t, const double
   rc = run_backward(p, g, !single, s);
   if (rc) return rc;
   TIMED(SOS_K_ADAM, launch_adam(p, W, st, st + slot_bytes(p), g, t, h, s), "adam");
+  return SOS_OK;
+}
+
+// The deterministic forward replaces the atomic scatter of the plan's own
+// (fast) forward in FP32 and FP64 plans that carry pair lists.
+static int check_det(const sos_plan_s* p, int flags, const char* fn) {
+  if (!(flags & SOS_FLAG_DETERMINISTIC)) return SOS_OK;
+  if (!p->det_ok)
+    return set_error(SOS_EINVAL, std::string(fn) + ": SOS_FLAG_DETERMINISTIC needs an FP32 or FP64 plan with N <= " +
+                                     std::to_string(SOS_BATCH_MAX_N));
+  if (fwd_mode(p, flags) != kFwdFast)
+    return set_error(SOS_EINVAL, std::string(fn) + ": SOS_FLAG_DETERMINISTIC covers the plan's own forward only");
+  return SOS_OK;
+}
+
+// The unfused scatter is a measurement variant of the split plans' fast forward.
+static int check_unfused(const sos_plan_s* p, int flags, const char* fn) {
+  if (!(flags & SOS_FLAG_UNFUSED_SCATTER)) return SOS_OK;
+  if (p->prec != SOS_BF16X3 || fwd_mode(p, flags) != kFwdFast)
+    return set_error(SOS_EINVAL, std::string(fn) + ": SOS_FLAG_UNFUSED_SCATTER needs a split plan's fast forward");
   return SOS_OK;
 }
 
@@ -250,11 +278,13 @@ int sos_plan_bind(sos_plan_t p, void* d_ws, size_t ws_bytes, void* stream) {
           "sos_plan_bind: tables");
   SOS_HIP(hipMemcpyAsync(p->ws + p->lay.tiles, p->tile_list.data(), p->tile_list.size() * 4, hipMemcpyHostToDevice, s),
           "sos_plan_bind: tiles");
-  if (p->batchable) {
+  if (p->det_ok) {
     SOS_HIP(hipMemcpyAsync(p->ws + p->lay.pair_off, p->pair_off.data(), p->pair_off.size() * 4,
                            hipMemcpyHostToDevice, s), "sos_plan_bind: pair offsets");
     SOS_HIP(hipMemcpyAsync(p->ws + p->lay.pair_idx, p->pair_idx.data(), p->pair_idx.size() * 4,
                            hipMemcpyHostToDevice, s), "sos_plan_bind: pair lists");
+  }
+  if (p->batchable) {
     SOS_HIP(hipMemcpyAsync(p->ws + p->lay.pair_pos, p->pair_pos.data(), p->pair_pos.size() * 4,
                            hipMemcpyHostToDevice, s), "sos_plan_bind: pair positions");
     SOS_HIP(hipMemcpyAsync(p->ws + p->lay.rank_map, p->rank_map.data(), p->rank_map.size() * 4,
@@ -301,9 +331,11 @@ int sos_loss_grad(sos_plan_t p, const void* d_W, const double* d_p, double* d_lo
   if (int rc = check_bound(p, "sos_loss_grad")) return rc;
   if (!d_W || !d_p || !d_loss) return set_error(SOS_EINVAL, "sos_loss_grad: d_W, d_p and d_loss are required");
   if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_SINGLE_BACKWARD | SOS_FLAG_FP32_FORWARD |
-                     SOS_FLAG_OZAKI_FORWARD))
+                     SOS_FLAG_OZAKI_FORWARD | SOS_FLAG_DETERMINISTIC | SOS_FLAG_UNFUSED_SCATTER))
     return set_error(SOS_EINVAL, "sos_loss_grad: unknown flags");
   if (int rc = check_ozaki(p, flags, "sos_loss_grad")) return rc;
+  if (int rc = check_unfused(p, flags, "sos_loss_grad")) return rc;
+  if (int rc = check_det(p, flags, "sos_loss_grad")) return rc;
   hipStream_t s = (hipStream_t)stream;
   int rc = run_forward(p, d_W, d_p, flags, d_loss, d_grad != nullptr, s);
   if (rc) return rc;
@@ -320,9 +352,12 @@ int sos_step(sos_plan_t p, void* d_W, void* d_state, int64_t t, const double* d_
   if (!d_W || !d_state || !d_p || !d_loss) return set_error(SOS_EINVAL, "sos_step: NULL device pointer");
   if (t < 1) return set_error(SOS_EINVAL, "sos_step: t is 1-based");
   if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_COPIES_VALID | SOS_FLAG_SINGLE_BACKWARD |
-                     SOS_FLAG_FP32_FORWARD | SOS_FLAG_OZAKI_FORWARD))
+                     SOS_FLAG_FP32_FORWARD | SOS_FLAG_OZAKI_FORWARD | SOS_FLAG_DETERMINISTIC |
+                     SOS_FLAG_UNFUSED_SCATTER))
     return set_error(SOS_EINVAL, "sos_step: unknown flags");
   if (int rc = check_ozaki(p, flags, "sos_step")) return rc;
+  if (int rc = check_unfused(p, flags, "sos_step")) return rc;
+  if (int rc = check_det(p, flags, "sos_step")) return rc;
   return run_step(p, d_W, d_state, t, d_p, *adam, d_loss, flags, (hipStream_t)stream);
 }
 
@@ -452,6 +487,9 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
     return set_error(SOS_EINVAL, "sos_solve: needs max_steps >= 0, check_every >= 1, tol, lr_exact, "
                                  "rollback_ratio >= 0 and stall_checks >= 0");
   if (o->finisher != 0 && o->finisher != 1) return set_error(SOS_EINVAL, "sos_solve: finisher must be 0 or 1");
+  if (o->step_flags & ~(int)SOS_FLAG_DETERMINISTIC)
+    return set_error(SOS_EINVAL, "sos_solve: step_flags may be SOS_FLAG_DETERMINISTIC");
+  if (int rc = check_det(p, o->step_flags, "sos_solve")) return rc;
   if (o->finisher && o->ladder)
     if (int rc = check_ozaki(p, SOS_FLAG_OZAKI_FORWARD, "sos_solve")) return rc;
   hipStream_t s = (hipStream_t)stream;
@@ -478,7 +516,7 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
   int64_t t = 0, exact_steps = 0;
   double last_loss = 0;
   bool done = false;
-  const bool has_mid = can_ladder && p->prec == SOS_BF16X3 && o->mid_rel > 0;
+  const bool has_mid = can_ladder && split_plan(p) && o->mid_rel > 0;
   auto next_phase = [&]() {
     phase = (phase == 0 && has_mid) ? 1 : 2;
     stall = 0;
@@ -493,7 +531,7 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
     const bool check = (t % o->check_every == 0) || t == o->max_steps;
     if (check) SOS_HIP(hipMemcpyAsync(cand, d_W, wbytes, hipMemcpyDeviceToDevice, s), "sos_solve: snapshot");
     const int exact_flag = o->finisher ? SOS_FLAG_OZAKI_FORWARD : SOS_FLAG_EXACT_FORWARD;
-    const int flags = (phase == 2 ? exact_flag : phase == 1 ? SOS_FLAG_FP32_FORWARD : 0) |
+    const int flags = (phase == 2 ? exact_flag : phase == 1 ? SOS_FLAG_FP32_FORWARD : (o->step_flags & SOS_FLAG_DETERMINISTIC)) |
                       (o->single_backward ? SOS_FLAG_SINGLE_BACKWARD : 0) |
                       (w_moved ? 0 : SOS_FLAG_COPIES_VALID);
     int rc = run_step(p, d_W, st, t_adam, d_p, h, sc + 0, flags, s);

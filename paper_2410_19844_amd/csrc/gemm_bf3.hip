@@ -1,8 +1,12 @@
-// Split-bf16 ("bf16x3") contractions on gfx950 MFMA, 256 x 256 output tiles.
+// Split 16-bit ("bf16x3", "fp16x3") contractions on gfx950 MFMA, 256 x 256
+// output tiles.
 //
-// Every operand w is held as two bf16 arrays, hi = bf16(w) and
-// lo = bf16(w - hi); a product w w' is taken as lo*hi' + hi*lo' + hi*hi' on
-// v_mfma_f32_32x32x16_bf16 with FP32 accumulation (lo*lo' is dropped).
+// Every operand w is held as two 16-bit arrays, hi = round(w) and
+// lo = round(w - hi); a product w w' is taken as lo*hi' + hi*lo' + hi*hi' on
+// v_mfma_f32_32x32x16_bf16 (or _f16) with FP32 accumulation (lo*lo' is
+// dropped).  fp16 operands are scaled by powers of two held in the plan's
+// workspace (W copies by 2^sW, R by 2^sR), which the epilogues divide out
+// exactly.
 //
 // Tile: 256 x 256 outputs per workgroup; each wave owns WM x WN of it
 // (WM / 32 x WN / 32 MFMA blocks of 32 x 32).  K advances through a 4-deep
@@ -26,7 +30,32 @@ namespace sos {
 namespace bf3 {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// One 32 x 32 x 16 product.  The operands travel as 16-bit words whatever
+// their format: bf16 (SOS_BF16X3 plans) or fp16 (SOS_FP16X3 plans, scaled by
+// powers of two so that the lo halves stay in fp16's normal range).
+template <bool F16>
+__device__ __forceinline__ f32x16 mfma16(const bf16x8& a, const bf16x8& b, const f32x16& c) {
+  if constexpr (F16)
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0, 0,
+                                                  0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// A float as the plan's 16-bit operand format, and back.
+template <bool F16>
+__device__ __forceinline__ __bf16 to16(float x) {
+  if constexpr (F16) return __builtin_bit_cast(__bf16, (_Float16)x);
+  else return (__bf16)x;
+}
+template <bool F16>
+__device__ __forceinline__ float from16(__bf16 h) {
+  if constexpr (F16) return (float)__builtin_bit_cast(_Float16, h);
+  else return (float)h;
+}
 
 constexpr int TM = 256;
 constexpr int BK = 16;            // K per slot (one MFMA k-step, one block of the blocked layout)
@@ -168,19 +197,19 @@ __device__ __forceinline__ void load_frag(Frag& f, const char* st, int wm, int w
 }
 
 // MFMAs of A-blocks [b0, b1) against all B-blocks.
-template <bool SPLIT, int b0, int b1>
+template <bool SPLIT, bool F16, int b0, int b1>
 __device__ __forceinline__ void mma_rows(const Frag& f, f32x16 (&acc)[BI][BJ]) {
 #pragma unroll
   for (int bi = b0; bi < b1; ++bi)
 #pragma unroll
     for (int bj = 0; bj < BJ; ++bj) {
       if (SPLIT) {
-        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.al[bi], f.bh[bj], acc[bi][bj], 0, 0, 0);
-        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.ah[bi], f.bl[bj], acc[bi][bj], 0, 0, 0);
-        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.ah[bi], f.bh[bj], acc[bi][bj], 0, 0, 0);
+        acc[bi][bj] = mfma16<F16>(f.al[bi], f.bh[bj], acc[bi][bj]);
+        acc[bi][bj] = mfma16<F16>(f.ah[bi], f.bl[bj], acc[bi][bj]);
+        acc[bi][bj] = mfma16<F16>(f.ah[bi], f.bh[bj], acc[bi][bj]);
       } else {  // two K blocks: slot pairs (hi, hi) and (lo, lo) hold blocks 0 and 1
-        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.ah[bi], f.bh[bj], acc[bi][bj], 0, 0, 0);
-        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.al[bi], f.bl[bj], acc[bi][bj], 0, 0, 0);
+        acc[bi][bj] = mfma16<F16>(f.ah[bi], f.bh[bj], acc[bi][bj]);
+        acc[bi][bj] = mfma16<F16>(f.al[bi], f.bl[bj], acc[bi][bj]);
       }
     }
 }
@@ -192,12 +221,12 @@ __device__ __forceinline__ void mma_rows(const Frag& f, f32x16 (&acc)[BI][BJ]) {
 // issues the loads of stage kt+4 into that buffer and reads the fragments of
 // stage kt+1 into `nxt`; the second half of the MFMAs of stage kt covers the
 // latency of those reads.
-template <bool SPLIT>
+template <bool SPLIT, bool F16>
 __device__ __forceinline__ void pipe_step(Frag& cur, Frag& nxt, char* ring, const RingAddr& ra, const Operands& o,
                                           int64_t kt, int64_t nk, int64_t arow0, int64_t brow0,
                                           f32x16 (&acc)[BI][BJ], int wm, int wn) {
   constexpr int per = 4 * (ROWS_PER_WAVE / 32);  // loads per thread per stage
-  mma_rows<SPLIT, 0, BI / 2>(cur, acc);
+  mma_rows<SPLIT, F16, 0, BI / 2>(cur, acc);
   __builtin_amdgcn_sched_barrier(0);
   if (kt + 1 < nk) {
     // stages issued so far: up to kt + 3; stage kt + 1 must have landed
@@ -209,7 +238,7 @@ __device__ __forceinline__ void pipe_step(Frag& cur, Frag& nxt, char* ring, cons
     load_frag<SPLIT>(nxt, ring + ((kt + 1) % NSTAGE) * STAGE, wm, wn);
   }
   __builtin_amdgcn_sched_barrier(0);
-  mma_rows<SPLIT, BI / 2, BI>(cur, acc);
+  mma_rows<SPLIT, F16, BI / 2, BI>(cur, acc);
 }
 
 // The same step in the steady state (kt + 4 < nk), ordered differently: the
@@ -218,7 +247,7 @@ __device__ __forceinline__ void pipe_step(Frag& cur, Frag& nxt, char* ring, cons
 // of that buffer with stage kt+4, then the MFMAs of stage kt with the
 // fragment reads of stage kt+1 interleaved among them, so that the reads
 // have the whole stage's MFMA time to complete.  No branches.
-template <bool SPLIT>
+template <bool SPLIT, bool F16>
 __device__ __forceinline__ void pipe_step_steady(Frag& cur, Frag& nxt, char* ring, const RingAddr& ra, const Operands& o,
                                                  int64_t kt,
                                                  int64_t arow0, int64_t brow0, f32x16 (&acc)[BI][BJ], int wm,
@@ -231,7 +260,7 @@ __device__ __forceinline__ void pipe_step_steady(Frag& cur, Frag& nxt, char* rin
   issue_stage<SPLIT>(ra, (int)(kt % NSTAGE), o, arow0, brow0, (kt + NSTAGE) * kstage<SPLIT>());
   __builtin_amdgcn_sched_barrier(0);
   load_frag<SPLIT>(nxt, ring + ((kt + 1) % NSTAGE) * STAGE, wm, wn);
-  mma_rows<SPLIT, 0, BI>(cur, acc);
+  mma_rows<SPLIT, F16, 0, BI>(cur, acc);
   // scheduling pattern: RATIO MFMAs (mask 0x008), one LDS read (mask 0x100), ...
 #pragma unroll
   for (int q = 0; q < NREAD; ++q) {
@@ -243,7 +272,7 @@ __device__ __forceinline__ void pipe_step_steady(Frag& cur, Frag& nxt, char* rin
 }
 
 // C(256 x 256) = A[arow0 .. +256) x B[brow0 .. +256)^T over K (K a multiple of the stage K).
-template <bool SPLIT>
+template <bool SPLIT, bool F16>
 __device__ __forceinline__ void tile_gemm(const Operands& o, int64_t K, int64_t arow0, int64_t brow0,
                                           char* ring, f32x16 (&acc)[BI][BJ]) {
   const int wave = threadIdx.x >> 6;
@@ -266,12 +295,12 @@ __device__ __forceinline__ void tile_gemm(const Operands& o, int64_t K, int64_t 
   load_frag<SPLIT>(f0, ring, wm, wn);
   int64_t kt = 0;
   for (; kt + 1 + NSTAGE < nk; kt += 2) {
-    pipe_step_steady<SPLIT>(f0, f1, ring, ra, o, kt, arow0, brow0, acc, wm, wn);
-    pipe_step_steady<SPLIT>(f1, f0, ring, ra, o, kt + 1, arow0, brow0, acc, wm, wn);
+    pipe_step_steady<SPLIT, F16>(f0, f1, ring, ra, o, kt, arow0, brow0, acc, wm, wn);
+    pipe_step_steady<SPLIT, F16>(f1, f0, ring, ra, o, kt + 1, arow0, brow0, acc, wm, wn);
   }
   for (; kt < nk; kt += 2) {
-    pipe_step<SPLIT>(f0, f1, ring, ra, o, kt, nk, arow0, brow0, acc, wm, wn);
-    if (kt + 1 < nk) pipe_step<SPLIT>(f1, f0, ring, ra, o, kt + 1, nk, arow0, brow0, acc, wm, wn);
+    pipe_step<SPLIT, F16>(f0, f1, ring, ra, o, kt, nk, arow0, brow0, acc, wm, wn);
+    if (kt + 1 < nk) pipe_step<SPLIT, F16>(f1, f0, ring, ra, o, kt + 1, nk, arow0, brow0, acc, wm, wn);
   }
 }
 
@@ -306,6 +335,8 @@ struct GramArgs {
   int ntiles, N;
   RankTab rk;
   double* r;
+  float* G;           // unfused variant: tile v stored row-major at G + 65536 v (nullptr: scatter)
+  const int* sx;      // fp16 operands: sx[0] = sW, the W copies hold 2^sW w (bf16: unused)
 };
 
 #define SOS_BF3_BUFFERS \
@@ -316,12 +347,14 @@ struct GramArgs {
 // then every thread takes consecutive elements of the half, ranks each
 // (row, col) pair and adds it into r.  Copying out with compile-time indices
 // keeps the accumulators in registers; the scatter loop indexes LDS instead.
+template <bool F16>
 __global__ __launch_bounds__(NT) void k_gram_bf3(GramArgs g) {
   SOS_BF3_BUFFERS;
   const int v = xcd_order(blockIdx.x, g.ntiles);
   const int2 t = g.tiles[v];
   f32x16 acc[BI][BJ];
-  tile_gemm<true>(g.o, g.K, (int64_t)t.x * TM, (int64_t)t.y * TM, lds, acc);
+  tile_gemm<true, F16>(g.o, g.K, (int64_t)t.x * TM, (int64_t)t.y * TM, lds, acc);
+  const double unscale = F16 ? (double)pow2f(-2 * g.sx[0]) : 1.0;  // exact: a power of two
   const int wave = threadIdx.x >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
   float* half = (float*)lds;  // the whole pipeline ring: 128 KB
@@ -343,12 +376,36 @@ __global__ __launch_bounds__(NT) void k_gram_bf3(GramArgs g) {
           }
     }
     __syncthreads();
+    if (g.G) {  // unfused measurement variant: store the half tile, k_scatter_tiles ranks it
+      float* dst = g.G + (size_t)v * (TM * TM) + hh * HROWS * TM;
+      for (int e = threadIdx.x * 4; e < HROWS * TM; e += NT * 4) *(float4*)(dst + e) = *(const float4*)(half + e);
+      continue;
+    }
     for (int e = threadIdx.x; e < HROWS * TM; e += NT) {
       const int i = t.x * TM + hh * HROWS + e / TM, j = t.y * TM + e % TM;
       if (i < g.N && j < g.N && i <= j) {
-        const double w = (i == j) ? 1.0 : 2.0;
+        const double w = (i == j) ? unscale : 2.0 * unscale;
         unsafeAtomicAdd(g.r + pair_rank(g.rk, i, j), w * (double)half[e]);
       }
+    }
+  }
+}
+
+// The scatter of the unfused variant on its own: quarter tiles (64 x 256) of
+// the stored Gram tiles, read coalesced, each upper-triangle entry ranked and
+// added into r with its weight, as the fused epilogue does.  Measures what
+// the scatter costs outside the GEMM (bytes: the N (N + 1) / 2 FP32 entries
+// read, r updated by atomics).
+__global__ __launch_bounds__(256) void k_scatter_tiles(const float* __restrict__ G, const int2* __restrict__ tiles,
+                                                       int N, RankTab rk, double* __restrict__ r) {
+  const int v = blockIdx.x >> 2, qq = blockIdx.x & 3;
+  const int2 t = tiles[v];
+  const float* src = G + (size_t)v * (TM * TM) + qq * 64 * TM;
+  for (int e = threadIdx.x; e < 64 * TM; e += 256) {
+    const int i = t.x * TM + qq * 64 + e / TM, j = t.y * TM + e % TM;
+    if (i < N && j < N && i <= j) {
+      const double w = (i == j) ? 1.0 : 2.0;
+      unsafeAtomicAdd(r + pair_rank(rk, i, j), w * (double)src[e]);
     }
   }
 }
@@ -358,9 +415,10 @@ struct RwArgs {
   int64_t K;
   int TI, TL, N, k;
   float* g;    // N x k
+  const int* sx;     // fp16 operands: sx[0] = sW (W copies hold 2^sW w), sx[1] = sR (R holds 2^sR r)
 };
 
-template <bool SPLIT>
+template <bool SPLIT, bool F16>
 __global__ __launch_bounds__(NT) void k_rw_bf3(RwArgs a) {
   SOS_BF3_BUFFERS;
   const int nb = a.TI * a.TL;
@@ -373,7 +431,8 @@ __global__ __launch_bounds__(NT) void k_rw_bf3(RwArgs a) {
   const int in = v % per_group;
   const int I = first + in % rows, L = in / rows;
   f32x16 acc[BI][BJ];
-  tile_gemm<SPLIT>(a.o, a.K, (int64_t)I * TM, (int64_t)L * TM, lds, acc);
+  tile_gemm<SPLIT, F16>(a.o, a.K, (int64_t)I * TM, (int64_t)L * TM, lds, acc);
+  const float four = F16 ? pow2f(2 - a.sx[0] - a.sx[1]) : 4.0f;  // 4 times a power of two
   // epilogue through LDS in row-halves (as in k_gram_bf3), then coalesced
   // row-major stores of 4 * acc into g
   const int wave = threadIdx.x >> 6;
@@ -395,7 +454,7 @@ __global__ __launch_bounds__(NT) void k_rw_bf3(RwArgs a) {
     __syncthreads();
     for (int e = threadIdx.x; e < HROWS * TM; e += NT) {
       const int i = I * TM + hh * HROWS + e / TM, l = L * TM + e % TM;
-      if (i < a.N && l < a.k) a.g[(int64_t)i * a.k + l] = 4.0f * half[e];
+      if (i < a.N && l < a.k) a.g[(int64_t)i * a.k + l] = four * half[e];
     }
   }
 }
@@ -424,6 +483,7 @@ struct RwAdamArgs {
   int64_t Np, Kp, Np2, Kp2;
 };
 
+template <bool F16>
 __global__ __launch_bounds__(NT) void k_rw_adam_bf3(RwAdamArgs a) {
   SOS_BF3_BUFFERS;
   const RwArgs& r = a.rw;
@@ -436,7 +496,9 @@ __global__ __launch_bounds__(NT) void k_rw_adam_bf3(RwAdamArgs a) {
   const int in = v % per_group;
   const int I = first + in % rows, L = in / rows;
   f32x16 acc[BI][BJ];
-  tile_gemm<false>(r.o, r.K, (int64_t)I * TM, (int64_t)L * TM, lds, acc);
+  tile_gemm<false, F16>(r.o, r.K, (int64_t)I * TM, (int64_t)L * TM, lds, acc);
+  const float four = F16 ? pow2f(2 - r.sx[0] - r.sx[1]) : 4.0f;  // 4 times a power of two
+  const float wsc = F16 ? pow2f(r.sx[0]) : 1.0f;                  // scale of the next W copies
   const int wave = threadIdx.x >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
   constexpr int QROWS = 64;                            // quarter tiles of 64 x 256
@@ -491,7 +553,7 @@ __global__ __launch_bounds__(NT) void k_rw_adam_bf3(RwAdamArgs a) {
         float w = 0.f;
         if (i < r.N && l < r.k) {
           const int64_t o = i * r.k + l;
-          const float ge = 4.0f * stage[e];
+          const float ge = four * stage[e];
           const float me = a.b1 * mv[buf][u] + (1.f - a.b1) * ge;
           const float ve = a.b2 * vv[buf][u] + (1.f - a.b2) * ge * ge;
           a.m[o] = me;
@@ -503,13 +565,14 @@ __global__ __launch_bounds__(NT) void k_rw_adam_bf3(RwAdamArgs a) {
           if (a.x_f32) {
             a.x_f32[blk_off(i, l, a.xps)] = w;
           } else if (a.a_hi) {
-            const __bf16 h = (__bf16)w;
+            const float ws = w * wsc;
+            const __bf16 h = to16<F16>(ws);
             const int64_t ob = blk_off(i, l, a.aps);
             a.a_hi[ob] = h;
-            a.a_lo[ob] = (__bf16)(w - (float)h);
+            a.a_lo[ob] = to16<F16>(ws - from16<F16>(h));
           }
         }
-        tb[e] = (__bf16)w;
+        tb[e] = to16<F16>(w * wsc);
       }
     }
     __syncthreads();
@@ -531,8 +594,10 @@ __global__ __launch_bounds__(NT) void k_rw_adam_bf3(RwAdamArgs a) {
 
 // Host side -----------------------------------------------------------------
 
-hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s) {
+hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s, bool store) {
   bf3::GramArgs g;
+  const bool f16 = p->prec == SOS_FP16X3;
+  g.sx = scale_exponents(p);
   const char* ws = p->ws;
   g.o.a_hi = g.o.b_hi = (const __bf16*)(ws + p->lay.a_hi);
   g.o.a_lo = g.o.b_lo = (const __bf16*)(ws + p->lay.a_lo);
@@ -543,7 +608,16 @@ hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s) {
   g.N = (int)p->N;
   g.rk = rank_tab(p);
   g.r = (double*)(ws + p->lay.r);
-  bf3::k_gram_bf3<<<g.ntiles, bf3::NT, 0, s>>>(g);
+  g.G = store ? (float*)(ws + p->lay.g) : nullptr;
+  if (f16) bf3::k_gram_bf3<true><<<g.ntiles, bf3::NT, 0, s>>>(g);
+  else bf3::k_gram_bf3<false><<<g.ntiles, bf3::NT, 0, s>>>(g);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_tiles(const sos_plan_s* p, hipStream_t s) {
+  const char* ws = p->ws;
+  bf3::k_scatter_tiles<<<4 * p->ntiles256, 256, 0, s>>>((const float*)(ws + p->lay.g), (const int2*)(ws + p->lay.tiles),
+                                                         (int)p->N, rank_tab(p), (double*)(ws + p->lay.r));
   return hipGetLastError();
 }
 
@@ -566,8 +640,15 @@ hipError_t launch_rw_bf3(const sos_plan_s* p, void* g, bool split, hipStream_t s
   a.N = (int)p->N;
   a.k = p->k;
   a.g = (float*)g;
-  if (split) bf3::k_rw_bf3<true><<<a.TI * a.TL, bf3::NT, 0, s>>>(a);
-  else bf3::k_rw_bf3<false><<<a.TI * a.TL, bf3::NT, 0, s>>>(a);
+  const bool f16 = p->prec == SOS_FP16X3;
+  a.sx = scale_exponents(p);
+  if (f16) {
+    if (split) bf3::k_rw_bf3<true, true><<<a.TI * a.TL, bf3::NT, 0, s>>>(a);
+    else bf3::k_rw_bf3<false, true><<<a.TI * a.TL, bf3::NT, 0, s>>>(a);
+  } else {
+    if (split) bf3::k_rw_bf3<true, false><<<a.TI * a.TL, bf3::NT, 0, s>>>(a);
+    else bf3::k_rw_bf3<false, false><<<a.TI * a.TL, bf3::NT, 0, s>>>(a);
+  }
   return hipGetLastError();
 }
 
@@ -593,6 +674,8 @@ hipError_t launch_rw_adam_bf3(const sos_plan_s* p, void* W, void* m, void* v, in
   r.N = (int)p->N;
   r.k = p->k;
   r.g = nullptr;
+  const bool f16 = p->prec == SOS_FP16X3;
+  r.sx = scale_exponents(p);
   a.W = (float*)W;
   a.m = (float*)m;
   a.v = (float*)v;
@@ -613,7 +696,8 @@ hipError_t launch_rw_adam_bf3(const sos_plan_s* p, void* W, void* m, void* v, in
   a.Kp = p->Kp;
   a.Np2 = p->Np2;
   a.Kp2 = p->Kp2;
-  bf3::k_rw_adam_bf3<<<r.TI * r.TL, bf3::NT, 0, s>>>(a);
+  if (f16) bf3::k_rw_adam_bf3<true><<<r.TI * r.TL, bf3::NT, 0, s>>>(a);
+  else bf3::k_rw_adam_bf3<false><<<r.TI * r.TL, bf3::NT, 0, s>>>(a);
   return hipGetLastError();
 }
 

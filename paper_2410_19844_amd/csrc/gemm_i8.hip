@@ -9,9 +9,9 @@
 // sum over K.  The products of one level l = s + t share the weight
 // 2^-7l, so they are summed in one int32 accumulator (at most S products,
 // exact while S * K * 64^2 < 2^31); levels l < S are kept, the rest dropped.
-// After each level the accumulator is added into an FP64 accumulator with
-// its weight (exact: a 31-bit integer times a power of two), and the tile
-// scatters G_ij = 2^(e_i - 6) 2^(e_j - 6) sum_l 2^-7l T_l,ij into r in FP64.
+// The levels are combined in FP64 with their weights (each term exact: a
+// 31-bit integer times a power of two), and the tile scatters
+// G_ij = 2^(e_i - 6) 2^(e_j - 6) sum_l 2^-7l T_l,ij into r in FP64.
 //
 // Error: per product, the digits left out and the levels dropped amount to
 // at most (S + 1.05) 2^-7S of 2^(e_i + e_j), so |G_ij - G~_ij| <=
@@ -19,14 +19,18 @@
 // Gram entry at S = 6 and Gaussian rows; the errors of individual digits are
 // independent, so the actual error is far below this bound).
 //
-// Kernel shape follows the FP64 gram (gemm_x64.hip): 128 x 256 half tiles of
-// the 256 x 256 upper-triangle tiles per 512-thread workgroup, 8 waves of
-// 64 x 64 (2 x 2 blocks of v_mfma_i32_32x32x32_i8), a 4-deep LDS ring of
-// stages filled by direct global->LDS loads.  A stage is one block of 64 K
-// of one slice pair: 128 A rows and 256 B rows of 64 bytes (24 KB).  The K
-// loop runs over S(S+1)/2 segments, one per slice pair in level order, each
-// the whole K extent.  Registers per lane: 64 int32 level sums and 64 FP64
-// level totals (two waves per SIMD).
+// Kernel: one 256 x 256 upper-triangle tile per 512-thread workgroup, 8 waves
+// of 128 x 64 (4 x 2 blocks of v_mfma_i32_32x32x32_i8, two waves per SIMD),
+// a 4-deep LDS ring of 32 KB stages (256 A rows and 256 B rows of 64 bytes:
+// one block of 64 K of one slice pair) filled by direct global->LDS loads
+// three stages ahead; each k-step's fragments are read from LDS while the
+// previous k-step's MFMAs run.
+// The K loop runs over the S(S+1)/2 slice pairs in level order, each over the
+// whole K extent.  At the end of a level the lanes park their int32 sums in a
+// per-tile level buffer in global memory (contiguous 1 KB stores, 1.25 MB per
+// tile, read back once by the epilogue) instead of keeping FP64 totals in
+// registers: that leaves room for the 128 x 64 wave tile, which reads 6 LDS
+// fragments per 8 MFMAs (64 x 64 would read 4 per 4).
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -43,18 +47,18 @@ typedef int i32x16 __attribute__((ext_vector_type(16)));
 typedef __attribute__((address_space(3))) void* lds_t;
 
 constexpr int S = kOzSlices;
-constexpr int TA = 128;             // A rows per tile (half a 256-row panel)
-constexpr int TB = 256;             // B rows per tile (one panel)
-constexpr int BK = kOzBK;           // K (bytes) per stage
+constexpr int TM = 256;             // tile rows and columns (one panel each)
+constexpr int BK = kOzBK;           // K (bytes) per stage: one block of the slice layout
 constexpr int NT = 512;
 constexpr int NSTAGE = 4;
 constexpr int ROWB = BK;            // 64 bytes per row
-constexpr int ABYTES = TA * ROWB;   // 8 KB
-constexpr int BBYTES = TB * ROWB;   // 16 KB
-constexpr int STAGE = ABYTES + BBYTES;
-constexpr int PANEL = 256;
+constexpr int HALF = TM * ROWB;     // one operand's rows of a stage (16 KB)
+constexpr int STAGE = 2 * HALF;     // A and B (32 KB)
+constexpr int WM = 128, WN = 64;    // wave tile: 4 x 2 blocks of 32 x 32
+constexpr int BI = WM / 32, BJ = WN / 32;
 constexpr int kXcds = 8;
-constexpr int LOADS = 3;            // 24 KB per stage = 24 loads of 1 KB over 8 waves
+constexpr int LOADS = 4;            // 32 KB per stage = 32 loads of 1 KB over 8 waves
+constexpr int kLvlInts = TM * TM;   // one level of one tile in the level buffer
 
 __device__ __forceinline__ int xcd_order(int b, int nb) {
   const int q = nb / kXcds, rem = nb % kXcds;
@@ -72,6 +76,9 @@ __device__ __forceinline__ void dma16(const char* gaddr, unsigned m0) {
                : "memory", "m0");
 }
 
+// Wait until at most n of this wave's vector-memory operations are pending,
+// then barrier.  Vector-memory operations complete in issue order, so the
+// level-buffer stores issued after a stage's loads are waited for too.
 template <int n>
 __device__ __forceinline__ void wait_vm_barrier() {
   __builtin_amdgcn_s_waitcnt((n & 0xF) | ((n >> 4) << 14) | (7 << 4) | (0xF << 8));
@@ -101,51 +108,59 @@ struct Cursor {
   }
 };
 
-// Global address of row r (within the tile's operand) of K block kb.
-__device__ __forceinline__ const char* row_addr(const int8_t* slice, int64_t pstride, int64_t row0, int r,
-                                                int64_t kb) {
-  const int64_t row = row0 + r;
-  return (const char*)(slice + (row / PANEL) * pstride + (kb * PANEL + row % PANEL) * BK);
-}
-
 // LDS slot (l & 3) of row r holds 16-byte chunk (l & 3) ^ ((r >> 2) & 3), so
 // 16 consecutive rows read at one chunk fall in 16 distinct bank groups.
+// Wave w moves rows 64 (w % 4) .. +63 of A (w < 4) or of B (w >= 4), 16 rows
+// (1 KB) per instruction.
 __device__ __forceinline__ void issue_stage(unsigned st_lds, const int8_t* a_slice, const int8_t* b_slice,
                                             int64_t pstride, int64_t arow0, int64_t brow0, int64_t kb) {
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
   const unsigned wave_u = __builtin_amdgcn_readfirstlane((unsigned)wave);
+  const bool is_a = wave < 4;
+  const int8_t* base = is_a ? a_slice + (arow0 / TM) * pstride : b_slice + (brow0 / TM) * pstride;
+  const unsigned m = st_lds + (wave_u < 4 ? 0u : (unsigned)HALF) + (wave_u & 3u) * (64u * ROWB);
 #pragma unroll
   for (int q = 0; q < LOADS; ++q) {
-    const int ins = wave * LOADS + q;  // 0..7: A rows, 8..23: B rows; 16 rows of 64 B each
-    const unsigned ins_u = wave_u * LOADS + q;
-    const int r = (ins < 8 ? ins : ins - 8) * 16 + (l >> 2);
+    const int r = (wave & 3) * 64 + q * 16 + (l >> 2);
     const int chunk = (l & 3) ^ ((r >> 2) & 3);
-    const char* g = (ins < 8) ? row_addr(a_slice, pstride, arow0, r, kb) : row_addr(b_slice, pstride, brow0, r, kb);
-    const unsigned m0 = st_lds + (ins_u < 8 ? 0u : (unsigned)ABYTES) + (ins_u < 8 ? ins_u : ins_u - 8) * 1024u;
-    dma16(g + chunk * 16, m0);
+    dma16((const char*)(base + (kb * TM + r) * BK + chunk * 16), m + q * 1024u);
   }
 }
 
-// One stage: two k-steps of 32, each four MFMAs (2 x 2 blocks of 32 x 32).
-// Lane l supplies row l % 32 of a block and bytes 16 (l / 32) .. +15 of the
-// k-step, for both operands alike.
-__device__ __forceinline__ void mma_stage(const char* st, int wm, int wn, i32x16 (&acc)[2][2]) {
+// Fragments of one k-step of 32: per lane one 16 bytes per 32-row block of
+// A and of B (row l % 32 of the block, bytes 16 (l / 32) .. +15 of the
+// k-step, for both operands alike).
+struct Frag {
+  i32x4 a[BI], b[BJ];
+};
+
+__device__ __forceinline__ void read_frag(Frag& f, const char* st, int ks, int wm, int wn) {
   const int l = threadIdx.x & 63;
+  const int off = (l & 31) * ROWB + (((2 * ks + (l >> 5)) ^ ((l >> 2) & 3)) << 4);
 #pragma unroll
-  for (int ks = 0; ks < 2; ++ks) {
-    const int off = (l & 31) * ROWB + (((2 * ks + (l >> 5)) ^ ((l >> 2) & 3)) << 4);
-    i32x4 a[2], b[2];
+  for (int q = 0; q < BI; ++q) f.a[q] = *(const i32x4*)(st + (wm * WM + q * 32) * ROWB + off);
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      a[q] = *(const i32x4*)(st + (wm * 64 + q * 32) * ROWB + off);
-      b[q] = *(const i32x4*)(st + ABYTES + (wn * 64 + q * 32) * ROWB + off);
-    }
+  for (int q = 0; q < BJ; ++q) f.b[q] = *(const i32x4*)(st + HALF + (wn * WN + q * 32) * ROWB + off);
+}
+
+__device__ __forceinline__ void mma_frag(const Frag& f, i32x16 (&acc)[BI][BJ]) {
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+  for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-        acc[bi][bj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+    for (int bj = 0; bj < BJ; ++bj)
+      acc[bi][bj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a[bi], f.b[bj], acc[bi][bj], 0, 0, 0);
+}
+
+// Interleave: one MFMA, one LDS read, ... so that the reads of the next
+// fragments run under the current MFMAs (masks: 0x008 MFMA, 0x100 LDS read).
+__device__ __forceinline__ void interleave_reads() {
+  constexpr int NMFMA = BI * BJ, NREAD = BI + BJ;
+#pragma unroll
+  for (int q = 0; q < NREAD; ++q) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
   }
+  __builtin_amdgcn_sched_group_barrier(0x008, NMFMA - NREAD, 0);
 }
 
 struct Args {
@@ -156,80 +171,133 @@ struct Args {
   const int2* tiles;      // 256 x 256 upper-triangle tile list
   int ntiles, N;
   const double* scale;    // 2^(e_i - 6) per row (NaN: the row holds a non-finite entry)
+  int* lvl;               // level buffer: per tile, levels 0 .. S-2 of its int32 sums
   RankTab rk;
   double* r;
 };
 
+// Accumulator registers (bi, bj, 4 g .. 4 g + 3) of lane l sit at ints
+// 4 (((bi BJ + bj) 4 + g) 64 + l) of the wave's 8192-int share of a level, as
+// one 4-int vector: one 1 KB contiguous store per (bi, bj, g) across the wave.
+// lane_off = wave 8192 + 4 l; the offsets of (bi, bj, g) are constants.
+__device__ __forceinline__ int lvl_const(int bi, int bj, int g) { return ((bi * BJ + bj) * 4 + g) * 256; }
+
+// Park the accumulators at `base` (this tile's level buffer for one level).
+// The empty asm keeps the per-lane offset from being hoisted into 32
+// precomputed addresses that would stay live through the K loop.
+__device__ __forceinline__ void park_level(int* base, int lane_off, i32x16 (&acc)[BI][BJ]) {
+  asm volatile("" : "+v"(lane_off));
+#pragma unroll
+  for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < BJ; ++bj) {
+#pragma unroll
+      for (int gq = 0; gq < 4; ++gq) {
+        const i32x4 x = {acc[bi][bj][4 * gq], acc[bi][bj][4 * gq + 1], acc[bi][bj][4 * gq + 2],
+                         acc[bi][bj][4 * gq + 3]};
+        *(i32x4*)(base + lane_off + lvl_const(bi, bj, gq)) = x;
+      }
+      acc[bi][bj] = i32x16{};
+    }
+}
+
 __global__ __launch_bounds__(NT) void k_gram_i8(Args g) {
   __shared__ __attribute__((aligned(16))) char ring[NSTAGE * STAGE];
-  const int v = xcd_order(blockIdx.x, 2 * g.ntiles);
-  const int2 t = g.tiles[v >> 1];
-  const int half = v & 1;
-  const int64_t arow0 = (int64_t)t.x * PANEL + half * TA, brow0 = (int64_t)t.y * PANEL;
+  const int v = xcd_order(blockIdx.x, g.ntiles);
+  const int2 t = g.tiles[v];
+  const int64_t arow0 = (int64_t)t.x * TM, brow0 = (int64_t)t.y * TM;
   const int wave = threadIdx.x >> 6;
-  const int wm = wave >> 2, wn = wave & 3;  // 2 x 4 waves of 64 x 64
-  i32x16 acc[2][2];
-  double tot[2][2][16];
+  const int wm = wave >> 2, wn = wave & 3;  // 2 x 4 waves of 128 x 64
+  i32x16 acc[BI][BJ];
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-      acc[bi][bj] = i32x16{};
-#pragma unroll
-      for (int q = 0; q < 16; ++q) tot[bi][bj][q] = 0.0;
-    }
+    for (int bj = 0; bj < BJ; ++bj) acc[bi][bj] = i32x16{};
   const int64_t nkb = g.nkb;
   const int64_t nv = (int64_t)(S * (S + 1) / 2) * nkb;  // stages over all segments
   const unsigned ring_lds = __builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)(lds_t)ring);
+  int* const lvl_tile = g.lvl + (int64_t)v * (S - 1) * kLvlInts;
+  const int lane_off = wave * (kLvlInts / 8) + 4 * (threadIdx.x & 63);
   Cursor in, cu;  // next stage to issue, stage to compute
-  for (int s = 0; s < NSTAGE - 1; ++s) {
-    if (s < nv) {
-      issue_stage(ring_lds + s * STAGE, g.oz + in.s * g.slice_bytes, g.oz + in.t * g.slice_bytes, g.pstride, arow0,
+  // Software pipeline: the ring holds four stages, loads run three stages
+  // ahead, and the fragments of each k-step are read from LDS while the
+  // MFMAs of the previous k-step run.  Entering iteration vt, the fragments
+  // of (vt, k-step 0) are in registers.
+  for (int q = 0; q < NSTAGE; ++q) {
+    if (q < nv) {
+      issue_stage(ring_lds + q * STAGE, g.oz + in.s * g.slice_bytes, g.oz + in.t * g.slice_bytes, g.pstride, arow0,
                   brow0, in.kb);
       in.advance(nkb);
     }
   }
-  double weight = 1.0;  // 2^-7 lvl of the level being summed
+  // stage 0 must have landed; stages 1 .. 3 may be in flight
+  if (nv >= 4) wait_vm_barrier<3 * LOADS>();
+  else if (nv == 3) wait_vm_barrier<2 * LOADS>();
+  else if (nv == 2) wait_vm_barrier<LOADS>();
+  else wait_vm_barrier<0>();
+  Frag f0, f1;
+  read_frag(f0, ring, 0, wm, wn);
   for (int64_t vt = 0; vt < nv; ++vt) {
-    const int64_t ahead = nv - 1 - vt;  // stages after vt that have been issued (at most 2)
-    if (ahead >= 2) wait_vm_barrier<2 * LOADS>();
-    else if (ahead == 1) wait_vm_barrier<LOADS>();
-    else wait_vm_barrier<0>();
-    // every wave is past its reads of stage vt-1: refill that buffer
-    if (vt + NSTAGE - 1 < nv) {
-      issue_stage(ring_lds + (unsigned)((vt + NSTAGE - 1) % NSTAGE) * STAGE, g.oz + in.s * g.slice_bytes,
-                  g.oz + in.t * g.slice_bytes, g.pstride, arow0, brow0, in.kb);
-      in.advance(nkb);
+    const char* st = ring + (vt % NSTAGE) * STAGE;
+    // k-step 0 of stage vt, reading k-step 1
+    read_frag(f1, st, 1, wm, wn);
+    mma_frag(f0, acc);
+    interleave_reads();
+    __builtin_amdgcn_sched_barrier(0);
+    if (vt + 1 < nv) {
+      // stage vt+1 must have landed (up to two later stages may be in flight);
+      // after the barrier every wave has read all of stage vt: refill its buffer
+      const int64_t later = nv - 1 - (vt + 1) < 2 ? nv - 1 - (vt + 1) : 2;
+      if (later == 2) wait_vm_barrier<2 * LOADS>();
+      else if (later == 1) wait_vm_barrier<LOADS>();
+      else wait_vm_barrier<0>();
+      if (vt + NSTAGE < nv) {
+        issue_stage(ring_lds + (unsigned)(vt % NSTAGE) * STAGE, g.oz + in.s * g.slice_bytes,
+                    g.oz + in.t * g.slice_bytes, g.pstride, arow0, brow0, in.kb);
+        in.advance(nkb);
+      }
     }
-    mma_stage(ring + (vt % NSTAGE) * STAGE, wm, wn, acc);
-    if (cu.level_ends(nkb)) {
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-#pragma unroll
-          for (int q = 0; q < 16; ++q) tot[bi][bj][q] = fma((double)acc[bi][bj][q], weight, tot[bi][bj][q]);
-          acc[bi][bj] = i32x16{};
-        }
-      weight *= 0x1p-7;
-    }
+    __builtin_amdgcn_sched_barrier(0);
+    // k-step 1 of stage vt, reading k-step 0 of stage vt+1 (after the last
+    // stage this reads a buffer of the ring whose data goes unused)
+    read_frag(f0, ring + ((vt + 1) % NSTAGE) * STAGE, 0, wm, wn);
+    mma_frag(f1, acc);
+    interleave_reads();
+    __builtin_amdgcn_sched_barrier(0);
+    // park the level's exact sums in the tile's level buffer and start the next
+    if (cu.level_ends(nkb) && cu.lvl < S - 1) park_level(lvl_tile + cu.lvl * kLvlInts, lane_off, acc);
     cu.advance(nkb);
   }
-  // scatter: lane l, register q of 32 x 32 block (bi, bj) holds row
-  // 8 (q / 4) + 4 (l / 32) + q % 4 and column l % 32 of the block
+  // combine the levels in FP64 (each term a 31-bit integer times a power of
+  // two), scale by the row exponents, scatter.  Register (bi, bj, 4 gq + u)
+  // of lane l holds row 32 bi + 8 gq + 4 (l / 32) + u and column 32 bj + l % 32
+  // of the wave's 128 x 64 share.
   const int l = threadIdx.x & 63;
 #pragma unroll
-  for (int bj = 0; bj < 2; ++bj) {
-    const int j = (int)brow0 + wn * 64 + bj * 32 + (l & 31);
+  for (int bj = 0; bj < BJ; ++bj) {
+    const int j = (int)brow0 + wn * WN + bj * 32 + (l & 31);
     const double sj = j < g.N ? g.scale[j] : 0.0;
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int i = (int)arow0 + wm * 64 + bi * 32 + (q >> 2) * 8 + (l >> 5) * 4 + (q & 3);
-        if (i < g.N && j < g.N && i <= j) {
-          const double wgt = (i == j) ? 1.0 : 2.0;
-          unsafeAtomicAdd(g.r + pair_rank(g.rk, i, j), wgt * (tot[bi][bj][q] * g.scale[i] * sj));
+      for (int gq = 0; gq < 4; ++gq) {
+        i32x4 lv[S - 1];
+#pragma unroll
+        for (int q = 0; q < S - 1; ++q) lv[q] = *(const i32x4*)(lvl_tile + q * kLvlInts + lane_off + lvl_const(bi, bj, gq));
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = (int)arow0 + wm * WM + bi * 32 + gq * 8 + (l >> 5) * 4 + u;
+          if (i < g.N && j < g.N && i <= j) {
+            double tot = 0.0, w = 1.0;
+#pragma unroll
+            for (int q = 0; q < S - 1; ++q) {
+              tot = fma((double)lv[q][u], w, tot);
+              w *= 0x1p-7;
+            }
+            tot = fma((double)acc[bi][bj][4 * gq + u], w, tot);
+            const double wgt = (i == j) ? 1.0 : 2.0;
+            unsafeAtomicAdd(g.r + pair_rank(g.rk, i, j), wgt * (tot * g.scale[i] * sj));
+          }
         }
       }
   }
@@ -325,9 +393,10 @@ hipError_t launch_gram_i8(const sos_plan_s* p, hipStream_t s) {
   g.ntiles = p->ntiles256;
   g.N = (int)p->N;
   g.scale = (const double*)(ws + p->lay.oz_scale);
+  g.lvl = (int*)(ws + p->lay.oz_lvl);
   g.rk = rank_tab(p);
   g.r = (double*)(ws + p->lay.r);
-  i8::k_gram_i8<<<2 * g.ntiles, i8::NT, 0, s>>>(g);
+  i8::k_gram_i8<<<g.ntiles, i8::NT, 0, s>>>(g);
   return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 
 #include <cstdint>
 
@@ -47,17 +48,24 @@ struct PrepArgs {
   int64_t Kp2, Np2;    // transposed copies: rows Kp2, ld Np2
   void* a_hi; void* a_lo; float* a_f32; float* x_f32;
   void* t_hi; void* t_lo;
+  const int* sx;       // fp16 split (mode 3): sx[0] = sW, the copies hold 2^sW w
 };
+
+// fp16 words carried in the bf16-typed operand arrays
+__device__ __forceinline__ __bf16 f16_bits(float x) { return __builtin_bit_cast(__bf16, (_Float16)x); }
+__device__ __forceinline__ float f16_value(__bf16 h) { return (float)__builtin_bit_cast(_Float16, h); }
 
 // 64 x 64 tiles through LDS so that both the row-major and the transposed
 // copies are written with coalesced stores.  Mode: 0 = FP64, 1 = FP32,
-// 2 = bf16 hi/lo split.  Each destination is written only when its pointer
-// is set: the caller asks for the copies its forward and backward read.
+// 2 = bf16 hi/lo split, 3 = fp16 hi/lo split of 2^sW w.  Each destination is
+// written only when its pointer is set: the caller asks for the copies its
+// forward and backward read.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
   using WT = typename std::conditional<MODE == 0, double, float>::type;
   __shared__ WT tile[64][65];
   const int64_t i0 = (int64_t)blockIdx.y * 64, l0 = (int64_t)blockIdx.x * 64;
+  const float wsc = (MODE == 3) ? pow2f(a.sx[0]) : 1.0f;
   const WT* W = (const WT*)a.W;
   const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
   for (int r = ty; r < 64; r += 4) {
@@ -74,10 +82,17 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
         if (a.a_hi) ((float*)a.a_hi)[o] = (float)v;
       } else {
         if (a.a_hi) {
-          const __bf16 h = (__bf16)(float)v;
           const int64_t ob = blk_off(i, l, panel_stride(a.Kp / kBlkK, 2));
-          ((__bf16*)a.a_hi)[ob] = h;
-          ((__bf16*)a.a_lo)[ob] = (__bf16)((float)v - (float)h);
+          if (MODE == 3) {
+            const float ws = (float)v * wsc;
+            const __bf16 h = f16_bits(ws);
+            ((__bf16*)a.a_hi)[ob] = h;
+            ((__bf16*)a.a_lo)[ob] = f16_bits(ws - f16_value(h));
+          } else {
+            const __bf16 h = (__bf16)(float)v;
+            ((__bf16*)a.a_hi)[ob] = h;
+            ((__bf16*)a.a_lo)[ob] = (__bf16)((float)v - (float)h);
+          }
         }
         if (a.a_f32) a.a_f32[o] = (float)v;
       }
@@ -92,7 +107,13 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
       const int64_t o = l * a.Np2 + i;
       if (MODE == 0) ((double*)a.t_hi)[o] = (double)v;
       else if (MODE == 1) ((float*)a.t_hi)[o] = (float)v;
-      else {
+      else if (MODE == 3) {
+        const float ws = (float)v * wsc;
+        const __bf16 h = f16_bits(ws);
+        const int64_t ob = blk_off(l, i, panel_stride(a.Np2 / kBlkK, 2));
+        ((__bf16*)a.t_hi)[ob] = h;
+        if (a.t_lo) ((__bf16*)a.t_lo)[ob] = f16_bits(ws - f16_value(h));
+      } else {
         const __bf16 h = (__bf16)(float)v;
         const int64_t ob = blk_off(l, i, panel_stride(a.Np2 / kBlkK, 2));
         ((__bf16*)a.t_hi)[ob] = h;
@@ -131,35 +152,96 @@ __device__ double block_sum(double v) {
   return s;
 }
 
-// x32 (optional): FP32 copy of x, written on the way (the gather of R reads it)
+__device__ float block_max(float v) {
+  __shared__ float part[16];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  if (l == 0) part[w] = v;
+  __syncthreads();
+  float m = 0.f;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < (int)(blockDim.x / 64); ++q) m = fmaxf(m, part[q]);
+  return m;
+}
+
+// The exponent s with max * 2^s < 2^top: the power-of-two scale that puts
+// the largest magnitude just below 2^top (0 when max is 0 or not finite),
+// clamped to [-100, 100] so that every scale and its inverse, and their
+// products in the epilogues, stay normal floats.
+__device__ __forceinline__ int pow2_exponent(float m, int top) {
+  if (!(m > 0.f) || !(m <= FLT_MAX)) return 0;
+  int e;
+  (void)frexpf(m, &e);  // m < 2^e
+  return min(100, max(-100, top - e));
+}
+
+// x32 (optional): FP32 copy of x, written on the way (the gather of R reads it);
+// pmax (optional): per-block max |x32| (the fp16 gather's scale)
 __global__ __launch_bounds__(256) void k_sumsq_partial(const double* __restrict__ x, int64_t M,
-                                                       double* __restrict__ partial, float* __restrict__ x32) {
+                                                       double* __restrict__ partial, float* __restrict__ x32,
+                                                       float* __restrict__ pmax) {
   double s = 0;
+  float m = 0.f;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < M;
        e += (int64_t)gridDim.x * blockDim.x) {
     const double v = x[e];
     s += v * v;
-    if (x32) x32[e] = (float)v;
+    if (x32) {
+      x32[e] = (float)v;
+      m = fmaxf(m, fabsf((float)v));
+    }
   }
   s = block_sum(s);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  if (pmax) {
+    m = block_max(m);
+    if (threadIdx.x == 0) pmax[blockIdx.x] = m;
+  }
 }
 
+// rexp (optional): the fp16 gather's scale exponent sR from the block
+// maxima, so that 2^sR |R| < 2^14
 __global__ __launch_bounds__(256) void k_sumsq_final(const double* __restrict__ partial,
-                                                     double* __restrict__ out) {
+                                                     double* __restrict__ out, const float* __restrict__ pmax,
+                                                     int* __restrict__ rexp) {
   double s = 0;
   for (int q = threadIdx.x; q < kSumBlocks; q += blockDim.x) s += partial[q];
   s = block_sum(s);
   if (threadIdx.x == 0) out[0] = s;
+  if (pmax) {
+    float m = 0.f;
+    for (int q = threadIdx.x; q < kSumBlocks; q += blockDim.x) m = fmaxf(m, pmax[q]);
+    m = block_max(m);
+    if (threadIdx.x == 0) rexp[0] = pow2_exponent(m, 14);
+  }
+}
+
+// The scale of the fp16 copies of W: 2^sW with 2^sW max|W| < 2^12, leaving a
+// factor 16 of headroom below fp16's largest value for W to grow while fused
+// steps reuse the scale.  Per-block maxima, then one block.
+__global__ __launch_bounds__(256) void k_absmax_partial(const float* __restrict__ W, int64_t n,
+                                                        float* __restrict__ pmax) {
+  float m = 0.f;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    m = fmaxf(m, fabsf(W[e]));
+  m = block_max(m);
+  if (threadIdx.x == 0) pmax[blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(256) void k_absmax_final(const float* __restrict__ pmax, int* __restrict__ wexp) {
+  float m = 0.f;
+  for (int q = threadIdx.x; q < kSumBlocks; q += blockDim.x) m = fmaxf(m, pmax[q]);
+  m = block_max(m);
+  if (threadIdx.x == 0) wexp[0] = pow2_exponent(m, 12);
 }
 
 // ---------------------------------------------------------------------------
 // Tiled NT GEMM core: 128 x 128 output tile, 256 threads = 4 waves (2 x 2),
 // each wave 64 x 64.  Operands staged through double-buffered LDS.
 // ---------------------------------------------------------------------------
-constexpr int BM = 128;
+constexpr int BM = kGenericTile;
 constexpr int kThreads = 256;
-constexpr int kGramMinBlocks = 512;   // contraction splits of the gram below this many tiles
 
 // Mode F64: double operands, f64 16x16x4 MFMA.  Output of one 16x16 block:
 // lane l, register q holds row (l / 16) + 4 q, column l % 16.
@@ -392,6 +474,8 @@ struct GramArgs {
   int tiles;          // T (T + 1) / 2
   RankTab rk;
   double* r;
+  double* Gd;         // deterministic forward: store G_ij (i <= j) of slice s at Gd[(s N + i) N + j]
+                      // instead of adding into r (nullptr: add)
 };
 
 __device__ __forceinline__ void tri_tile(int b, int& I, int& J) {
@@ -405,7 +489,8 @@ __device__ __forceinline__ void tri_tile(int b, int& I, int& J) {
 
 // Block b takes tile b % tiles over the contraction slice b / tiles (more
 // than one slice only when the tiles alone would leave the chip idle); the
-// FP64 atomics sum tiles and slices alike.
+// FP64 atomics sum tiles and slices alike, or, for the deterministic
+// forward, each slice's G entries are stored for k_coeff_det to sum.
 template <class Md>
 __global__ __launch_bounds__(kThreads) void k_gram(GramArgs g) {
   extern __shared__ __align__(16) char smem[];
@@ -438,6 +523,14 @@ __global__ __launch_bounds__(kThreads) void k_gram(GramArgs g) {
       }
     }
     __syncthreads();
+    if (g.Gd) {
+      double* Gs = g.Gd + (int64_t)(blockIdx.x / g.tiles) * g.N * g.N;
+      for (int x = threadIdx.x; x < HR * BM; x += kThreads) {
+        const int i = I * BM + hh * HR + x / BM, j = J * BM + x % BM;
+        if (i < g.N && j < g.N && i <= j) Gs[(int64_t)i * g.N + j] = (double)half[x];
+      }
+      continue;
+    }
     for (int x = threadIdx.x; x < HR * BM; x += kThreads) {
       const int i = I * BM + hh * HR + x / BM, j = J * BM + x % BM;
       if (i < g.N && j < g.N && i <= j) {
@@ -446,6 +539,27 @@ __global__ __launch_bounds__(kThreads) void k_gram(GramArgs g) {
       }
     }
   }
+}
+
+// Deterministic coefficients: r_m = sum over the pairs of monomial m, in the
+// plan's pair-list order (i, then j, ascending), of w_ij sum_s G_ij^(s)
+// (slices in order; w = 2 off the diagonal), minus p_m.  No atomics, so the
+// result depends on nothing but W and p.
+__global__ __launch_bounds__(256) void k_coeff_det(const double* __restrict__ Gd, int splits, int N,
+                                                   const int32_t* __restrict__ off, const int32_t* __restrict__ idx,
+                                                   const double* __restrict__ p, double* __restrict__ r, int M) {
+  const int m = blockIdx.x * 256 + threadIdx.x;
+  if (m >= M) return;
+  const int64_t nn = (int64_t)N * N;
+  double c = 0.0;
+  for (int e = off[m]; e < off[m + 1]; ++e) {
+    const uint32_t x = (uint32_t)idx[e];
+    const int64_t ij = x & 0x7FFFFFFFu;
+    double gsum = 0.0;
+    for (int s = 0; s < splits; ++s) gsum += Gd[s * nn + ij];
+    c += (x >> 31) ? 2.0 * gsum : gsum;
+  }
+  r[m] = c - p[m];
 }
 
 // ---------------------------------------------------------------------------
@@ -489,6 +603,8 @@ __device__ __forceinline__ int64_t gather_off(int64_t i, int64_t j, int64_t ld, 
   return MODE >= 2 ? blk_off(i, j, ps) : i * ld + j;
 }
 
+// Modes: 1 FP32 row-major; 2 bf16 hi and lo, 3 bf16 hi only, 4 fp16 hi and
+// lo, 5 fp16 hi only (blocked; fp16 values are 2^sR R, scale applied by the caller)
 template <int MODE>
 __device__ __forceinline__ void gather_store16(void* R_hi, void* R_lo, int64_t o, const float* v) {
   if (MODE == 1) {
@@ -499,13 +615,18 @@ __device__ __forceinline__ void gather_store16(void* R_hi, void* R_lo, int64_t o
     bf16x8 h[2], lo[2];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      h[q >> 3][q & 7] = (__bf16)v[q];
-      lo[q >> 3][q & 7] = (__bf16)(v[q] - (float)h[q >> 3][q & 7]);
+      if (MODE >= 4) {
+        h[q >> 3][q & 7] = f16_bits(v[q]);
+        lo[q >> 3][q & 7] = f16_bits(v[q] - f16_value(h[q >> 3][q & 7]));
+      } else {
+        h[q >> 3][q & 7] = (__bf16)v[q];
+        lo[q >> 3][q & 7] = (__bf16)(v[q] - (float)h[q >> 3][q & 7]);
+      }
     }
     bf16x8* dh = (bf16x8*)((__bf16*)R_hi + o);
     dh[0] = h[0];
     dh[1] = h[1];
-    if (MODE == 2) {
+    if (MODE == 2 || MODE == 4) {
       bf16x8* dl = (bf16x8*)((__bf16*)R_lo + o);
       dl[0] = lo[0];
       dl[1] = lo[1];
@@ -525,7 +646,9 @@ __device__ __forceinline__ void gather_store16(void* R_hi, void* R_lo, int64_t o
 // Mode 1 = FP32 row-major, 2 = bf16 hi and lo (blocked), 3 = bf16 hi only.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_gather_sym(RankTab rk, const float* __restrict__ r32, int N, int64_t Np,
-                                                    int64_t ld, int T2, int64_t nup, void* R_hi, void* R_lo) {
+                                                    int64_t ld, int T2, int64_t nup, void* R_hi, void* R_lo,
+                                                    const int* __restrict__ sx) {
+  const float rsc = MODE >= 4 ? pow2f(sx[1]) : 1.0f;  // 2^sR for fp16 operands
   __shared__ float V[64][65];
   __shared__ uint32_t Cj[64 * kMaxWords];          // codes of the tile's 64 columns
   extern __shared__ int32_t Tab[];                 // field terms (dense) or binomials (sparse): ntab entries
@@ -567,7 +690,7 @@ __global__ __launch_bounds__(256) void k_gather_sym(RankTab rk, const float* __r
       for (int q = 0; q < 16; ++q) {
 #pragma unroll
         for (int w = 0; w < kMaxWords; ++w) cj[w] = w < rk.nwords ? Cj[(jc + q) * rk.nwords + w] : 0u;
-        v[q] = (j0 + q < N) ? r32[dense_rank_fields(ci, cj, rk.n, Tab)] : 0.f;
+        v[q] = (j0 + q < N) ? rsc * r32[dense_rank_fields(ci, cj, rk.n, Tab)] : 0.f;
       }
     } else {
       const uint32_t ci = rk.codes[i];
@@ -575,7 +698,7 @@ __global__ __launch_bounds__(256) void k_gather_sym(RankTab rk, const float* __r
       auto binom = [&](int x, int y) { return Tab[x * D1 + y]; };
 #pragma unroll
       for (int q = 0; q < 16; ++q)
-        v[q] = (j0 + q < N) ? r32[sparse_pair_rank(ci, Cj[jc + q], rk.n, rk.total, binom)] : 0.f;
+        v[q] = (j0 + q < N) ? rsc * r32[sparse_pair_rank(ci, Cj[jc + q], rk.n, rk.total, binom)] : 0.f;
     }
   } else {
 #pragma unroll
@@ -662,7 +785,8 @@ hipError_t launch_prep(const sos_plan_s* p, const void* W, const PrepNeeds& need
   PrepArgs a;
   a.W = W; a.N = (int)p->N; a.k = p->k;
   a.Np = p->Np; a.Kp = p->Kp; a.Kp2 = p->Kp2; a.Np2 = p->Np2;
-  const bool split = p->prec == SOS_BF16X3;
+  const bool split = split_plan(p);
+  a.sx = scale_exponents(p);
   a.a_hi = need.a ? p->ws + p->lay.a_hi : nullptr;
   a.a_lo = (need.a && split) ? p->ws + p->lay.a_lo : nullptr;
   a.a_f32 = (split && need.a_f32) ? (float*)(p->ws + p->lay.a_f32) : nullptr;
@@ -674,7 +798,17 @@ hipError_t launch_prep(const sos_plan_s* p, const void* W, const PrepNeeds& need
   dim3 grid((unsigned)(cols / 64), (unsigned)(rows / 64));
   if (p->prec == SOS_FP64) k_prep<0><<<grid, 256, 0, s>>>(a);
   else if (p->prec == SOS_FP32) k_prep<1><<<grid, 256, 0, s>>>(a);
-  else k_prep<2><<<grid, 256, 0, s>>>(a);
+  else if (p->prec == SOS_FP16X3) {
+    // the scale of the 16-bit copies from max |W| first (the fused steps that
+    // follow keep it)
+    if (need.a || need.t) {
+      float* pmax = (float*)((double*)(p->ws + p->lay.scal) + kScalMax);
+      const int64_t n = p->N * (int64_t)p->k;
+      k_absmax_partial<<<kSumBlocks, 256, 0, s>>>((const float*)W, n, pmax);
+      k_absmax_final<<<1, 256, 0, s>>>(pmax, scale_exponents(p));
+    }
+    k_prep<3><<<grid, 256, 0, s>>>(a);
+  } else k_prep<2><<<grid, 256, 0, s>>>(a);
   return hipGetLastError();
 }
 
@@ -684,14 +818,18 @@ hipError_t launch_init_r(const sos_plan_s* p, const double* d_p, hipStream_t s) 
 }
 
 hipError_t launch_sumsq(const sos_plan_s* p, const double* x, int64_t M, double* out, hipStream_t s, float* x32) {
-  double* partial = (double*)(p->ws + p->lay.scal) + 8;
-  k_sumsq_partial<<<kSumBlocks, 256, 0, s>>>(x, M, partial, x32);
-  k_sumsq_final<<<1, 256, 0, s>>>(partial, out);
+  double* sc = (double*)(p->ws + p->lay.scal);
+  double* partial = sc + 8;
+  // fp16 plans: the block maxima of |r| give the gather's scale when r32 is written
+  float* pmax = (x32 && p->prec == SOS_FP16X3) ? (float*)(sc + kScalMax) : nullptr;
+  k_sumsq_partial<<<kSumBlocks, 256, 0, s>>>(x, M, partial, x32, pmax);
+  k_sumsq_final<<<1, 256, 0, s>>>(partial, out, pmax, scale_exponents(p) + 1);
   return hipGetLastError();
 }
 
 template <class Md>
-static hipError_t gram_launch(const sos_plan_s* p, const void* a0, const void* a1, hipStream_t s) {
+static hipError_t gram_launch(const sos_plan_s* p, const void* a0, const void* a1, hipStream_t s,
+                              double* Gd = nullptr) {
   GramArgs g;
   g.A[0] = a0; g.A[1] = a1;
   g.ld = p->Kp; g.K = p->Kp;
@@ -699,21 +837,31 @@ static hipError_t gram_launch(const sos_plan_s* p, const void* a0, const void* a
   g.T = (int)(p->Np / BM);
   g.rk = rank_tab(p);
   g.r = (double*)(p->ws + p->lay.r);
+  g.Gd = Gd;
   const int tiles = g.T * (g.T + 1) / 2;
   g.tiles = tiles;
   // split the contraction when there are too few tiles to fill the chip
-  int64_t splits = 1;
-  if (tiles < kGramMinBlocks) splits = std::min<int64_t>((kGramMinBlocks + tiles - 1) / tiles, g.K / 64);
-  if (splits < 1) splits = 1;
-  g.kslice = (g.K + splits - 1) / splits;
-  g.kslice = (g.kslice + 63) / 64 * 64;
-  splits = (g.K + g.kslice - 1) / g.kslice;
+  g.kslice = generic_gram_kslice(p->Np, p->Kp);
+  const int64_t splits = generic_gram_splits(p->Np, p->Kp);
   const size_t sm = 2 * sizeof(Stage<Md>);
   // set on every launch (a host-side setting, cheap next to these kernels):
   // no shared flag between threads or devices
   hipError_t e = hipFuncSetAttribute((const void*)k_gram<Md>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
   if (e != hipSuccess) return e;
   k_gram<Md><<<(unsigned)(tiles * splits), kThreads, sm, s>>>(g);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_det(const sos_plan_s* p, const double* d_p, hipStream_t s) {
+  char* ws = p->ws;
+  double* Gd = (double*)(ws + p->lay.det_G);
+  hipError_t e = (p->prec == SOS_FP64) ? gram_launch<MF64>(p, ws + p->lay.a_hi, nullptr, s, Gd)
+                                       : gram_launch<MF32>(p, ws + p->lay.a_hi, nullptr, s, Gd);
+  if (e != hipSuccess) return e;
+  k_coeff_det<<<(unsigned)((p->M + 255) / 256), 256, 0, s>>>(Gd, (int)generic_gram_splits(p->Np, p->Kp), (int)p->N,
+                                                              (const int32_t*)(ws + p->lay.pair_off),
+                                                              (const int32_t*)(ws + p->lay.pair_idx), d_p,
+                                                              (double*)(ws + p->lay.r), (int)p->M);
   return hipGetLastError();
 }
 
@@ -732,8 +880,8 @@ template <class Md>
 static hipError_t rw_launch(const sos_plan_s* p, void* g, hipStream_t s) {
   RwArgs a;
   const char* ws = p->ws;
-  a.A[0] = ws + p->lay.R_hi; a.A[1] = p->prec == SOS_BF16X3 ? ws + p->lay.R_lo : nullptr;
-  a.B[0] = ws + p->lay.t_hi; a.B[1] = p->prec == SOS_BF16X3 ? ws + p->lay.t_lo : nullptr;
+  a.A[0] = ws + p->lay.R_hi; a.A[1] = split_plan(p) ? ws + p->lay.R_lo : nullptr;
+  a.B[0] = ws + p->lay.t_hi; a.B[1] = split_plan(p) ? ws + p->lay.t_lo : nullptr;
   a.K = p->Np2; a.N = (int)p->N; a.k = p->k;
   a.g = g; a.g_double = (p->prec == SOS_FP64);
   const size_t sm = 2 * sizeof(Stage<Md>);
@@ -751,7 +899,9 @@ hipError_t launch_gather(const sos_plan_s* p, bool split, hipStream_t s) {
   const RankTab rk = rank_tab(p);
   const int64_t total = p->Np * p->Np2;
   void* Rh = ws + p->lay.R_hi;
-  void* Rl = p->prec == SOS_BF16X3 ? ws + p->lay.R_lo : nullptr;
+  const bool f16 = p->prec == SOS_FP16X3;
+  void* Rl = split_plan(p) ? ws + p->lay.R_lo : nullptr;
+  const int* sc = scale_exponents(p);
   if (p->prec == SOS_FP64) {
     const double* r = (const double*)(ws + p->lay.r);
     k_gather<0><<<grid_for(total), 256, 0, s>>>(rk, r, (int)p->N, p->Np, p->Np2, Rh, Rl);
@@ -766,11 +916,15 @@ hipError_t launch_gather(const sos_plan_s* p, bool split, hipStream_t s) {
   const size_t tab = (size_t)rk.ntab * 4;
   if (rk.ntab > kStageTabMax) return hipErrorInvalidValue;
   if (p->prec == SOS_FP32)
-    k_gather_sym<1><<<(unsigned)blocks, 256, tab, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, T2, nup, Rh, Rl);
+    k_gather_sym<1><<<(unsigned)blocks, 256, tab, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, T2, nup, Rh, Rl, sc);
+  else if (f16 && split)
+    k_gather_sym<4><<<(unsigned)blocks, 256, tab, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, T2, nup, Rh, Rl, sc);
+  else if (f16)
+    k_gather_sym<5><<<(unsigned)blocks, 256, tab, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, T2, nup, Rh, Rl, sc);
   else if (split)
-    k_gather_sym<2><<<(unsigned)blocks, 256, tab, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, T2, nup, Rh, Rl);
+    k_gather_sym<2><<<(unsigned)blocks, 256, tab, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, T2, nup, Rh, Rl, sc);
   else
-    k_gather_sym<3><<<(unsigned)blocks, 256, tab, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, T2, nup, Rh, Rl);
+    k_gather_sym<3><<<(unsigned)blocks, 256, tab, s>>>(rk, r32, (int)p->N, p->Np, p->Np2, T2, nup, Rh, Rl, sc);
   return hipGetLastError();
 }
 

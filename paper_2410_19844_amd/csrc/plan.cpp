@@ -74,7 +74,7 @@ int plan_create(int n, int d, int rank, int prec, sos_plan_s** out) {
   *out = nullptr;
   if (n < 1 || d < 1 || rank < 1)
     return set_error(SOS_EINVAL, "sos_plan: n, d and rank must be >= 1");
-  if (prec != SOS_FP64 && prec != SOS_FP32 && prec != SOS_BF16X3)
+  if (prec != SOS_FP64 && prec != SOS_FP32 && prec != SOS_BF16X3 && prec != SOS_FP16X3)
     return set_error(SOS_EINVAL, "sos_plan: unknown precision");
   // dense codes (4-bit suffix-sum fields) for n <= 16, 2d <= 15; sparse
   // variable lists (one byte per factor) for more variables at low degree
@@ -185,9 +185,9 @@ int plan_create(int n, int d, int rank, int prec, sos_plan_s** out) {
   L.r = take((size_t)M * 8);
   if (prec != SOS_FP64) L.r32 = take((size_t)M * 4);
   L.tiles = take(p->tile_list.size() * 4);
-  L.scal = take(1024 * 8);   // [0..7] scalars, [8..519] reduction partials
+  L.scal = take(kScalDoubles * 8);   // scalars, reduction partials, fp16 scales (see kScalScales)
   // split-bf16 operands are panel-blocked with padded panels (see blk_off)
-  const bool blk = prec == SOS_BF16X3;
+  const bool blk = prec == SOS_BF16X3 || prec == SOS_FP16X3;
   const size_t a_el = blk ? (size_t)(p->Np / kBlkRows) * panel_stride(p->Kp / kBlkK, 2) : (size_t)p->Np * p->Kp;
   const size_t t_el = blk ? (size_t)(p->Kp2 / kBlkRows) * panel_stride(p->Np2 / kBlkK, 2) : (size_t)p->Kp2 * p->Np2;
   const size_t R_el = blk ? (size_t)(p->Np / kBlkRows) * panel_stride(p->Np2 / kBlkK, 2) : (size_t)p->Np * p->Np2;
@@ -199,21 +199,25 @@ int plan_create(int n, int d, int rank, int prec, sos_plan_s** out) {
   if (blk) L.R_lo = take(R_el * oel);
   // split-precision plans keep an FP32 padded copy of W for the exact FP64 forward
   // (FP32 plans use a_hi, which already is that copy)
-  if (prec == SOS_BF16X3) L.a_f32 = take((size_t)p->Np * p->Kp * 4);
+  if (blk) L.a_f32 = take((size_t)p->Np * p->Kp * 4);
   if (prec != SOS_FP64) L.x_f32 = take((size_t)(p->Np / kBlkRows) * panel_stride(p->Kp / kBlkK, 4) * 4);
-  L.g = take((size_t)N * rank * wel);
+  // gradient scratch; in split plans also the stored Gram tiles of the unfused
+  // scatter variant (256 x 256 FP32 per upper tile)
+  L.g = take(std::max((size_t)N * rank * wel, blk ? (size_t)p->ntiles256 * 256 * 256 * 4 : 0));
   if (prec != SOS_FP64) {  // Ozaki-split forward: int8 slices, row exponents and scales
     L.oz_slice = (size_t)(p->Np / kBlkRows) * oz_panel_stride(p->Kp);
     L.oz = take(L.oz_slice * kOzSlices);
     L.oz_exp = take((size_t)N * 4);
     L.oz_scale = take((size_t)N * 8);
+    L.oz_lvl = take((size_t)p->ntiles256 * (kOzSlices - 1) * kBlkRows * kBlkRows * 4);
   }
   // Grouped serving path: the coefficient of monomial m sums the Gram entries
   // of its pairs (i <= j, alpha_i + alpha_j = m) in one fixed order (i, then
   // j, ascending), so a problem's forward is deterministic.  The pair lists
   // are the inverse of the ranking map, built here once (counting sort).
-  if (prec == SOS_FP32 && N <= SOS_BATCH_MAX_N) {
-    p->batchable = true;
+  if ((prec == SOS_FP32 || prec == SOS_FP64) && N <= SOS_BATCH_MAX_N) {
+    p->batchable = prec == SOS_FP32;
+    p->det_ok = true;
     // rank of alpha_i + alpha_j by the closed form, one field term per
     // variable looked up in a table (the terms depend on (f, value) only)
     std::vector<int64_t> ft((size_t)n * (D + 1));
@@ -249,15 +253,18 @@ int plan_create(int n, int d, int rank, int prec, sos_plan_s** out) {
         p->pair_idx[e] = (int32_t)((uint32_t)(i * N + j) | (i < j ? 0x80000000u : 0u));
         p->pair_pos[i * N + j] = p->pair_pos[j * N + i] = e;
       }
-    L.bG = take((size_t)batch_slices(rank) * p->pair_idx.size() * 8);
-    L.pair_pos = take(p->pair_pos.size() * 4);
-    L.rank_map = take(p->rank_map.size() * 4);
-    L.bg = take((size_t)batch_slices_j((int)N) * N * rank * 4);
-    L.bpart = take((size_t)((M + 255) / 256) * 8);
-    L.bcount = take(4);
+    if (p->batchable) {
+      L.bG = take((size_t)batch_slices(rank) * p->pair_idx.size() * 8);
+      L.pair_pos = take(p->pair_pos.size() * 4);
+      L.rank_map = take(p->rank_map.size() * 4);
+      L.bg = take((size_t)batch_slices_j((int)N) * N * rank * 4);
+      L.bpart = take((size_t)((M + 255) / 256) * 8);
+      L.bcount = take(4);
+    }
     L.pair_off = take(p->pair_off.size() * 4);
     L.pair_idx = take(p->pair_idx.size() * 4);
-    L.bhdr = take(sizeof(BatchHeader));
+    if (p->batchable) L.bhdr = take(sizeof(BatchHeader));
+    L.det_G = take((size_t)generic_gram_splits(p->Np, p->Kp) * N * N * 8);
   }
   L.bytes = off;
   p->state_bytes = round_up((size_t)N * rank * wel, 256) * 4;  // m, v, best W, candidate W

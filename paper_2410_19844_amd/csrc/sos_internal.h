@@ -25,6 +25,14 @@ constexpr int kFieldsPerGroup = 3;
 constexpr int kGroupEntries = 4096;
 constexpr int kMaxWords = 3;     // n <= 16  ->  at most 6 groups
 
+// The plan's scalar area (doubles): [0] loss, [1] ||p||^2, [2] two int32
+// scale exponents of fp16 plans (sW: the W copies hold 2^sW w; sR: R holds
+// 2^sR r), [8 .. 520) the partial sums of the loss reduction, [1024 .. 1280)
+// block maxima (as floats) for the fp16 scales.
+constexpr int kScalScales = 2;
+constexpr int kScalMax = 1024;
+constexpr int kScalDoubles = 2048;
+
 // Tile sizes shared by host (padding, grids) and device.
 constexpr int kPadRows = 256;    // operand rows padded to this multiple (zero rows)
 constexpr int kPadK = 64;        // operand K extents padded to this multiple (zero columns)
@@ -58,6 +66,24 @@ __host__ __device__ inline int64_t oz_off(int64_t row, int64_t k, int64_t pstrid
   return (row / kBlkRows) * pstride + ((k / kOzBK) * kBlkRows + row % kBlkRows) * kOzBK + k % kOzBK;
 }
 constexpr int64_t kOzMaxK = ((int64_t(1) << 31) - 1) / (kOzSlices * 64 * 64);
+
+// Generic gram (kernels.hip, FP32 and FP64 plans): 128 x 128 upper tiles;
+// when they alone give fewer than kGramMinBlocks blocks, the contraction is
+// split into slices of kslice (a multiple of 64), one block per (tile, slice).
+constexpr int kGenericTile = 128;
+constexpr int kGramMinBlocks = 512;
+inline int64_t generic_gram_kslice(int64_t Np, int64_t Kp) {
+  const int64_t T = Np / kGenericTile, tiles = T * (T + 1) / 2;
+  int64_t splits = 1;
+  if (tiles < kGramMinBlocks) splits = std::min<int64_t>((kGramMinBlocks + tiles - 1) / tiles, Kp / 64);
+  if (splits < 1) splits = 1;
+  const int64_t ks = (Kp + splits - 1) / splits;
+  return (ks + 63) / 64 * 64;
+}
+inline int64_t generic_gram_splits(int64_t Np, int64_t Kp) {
+  const int64_t ks = generic_gram_kslice(Np, Kp);
+  return (Kp + ks - 1) / ks;
+}
 
 // Grouped serving kernels: the contraction length a block covers, and the
 // number of such slices (each with its own partial result) for length len.
@@ -205,6 +231,7 @@ struct Layout {
   size_t oz_slice = 0;           // bytes per slice array: (Np / 256) panels of oz_panel_stride(Kp)
   size_t oz_exp = 0;             // N int32: row exponents e_i
   size_t oz_scale = 0;           // N doubles: 2^(e_i - 6), NaN for a row holding a non-finite entry
+  size_t oz_lvl = 0;             // int32 level sums 0 .. kOzSlices-2 of every 256 x 256 gram tile
   // grouped (serving) path, FP32 plans with N <= SOS_BATCH_MAX_N only
   size_t bG = 0;                 // FP64 partial Gram per K slice: batch_slices(k) x P, entries in pair-list order
   size_t pair_pos = 0;           // N x N int32: position of pair (min(i,j), max(i,j)) in the pair lists
@@ -215,6 +242,9 @@ struct Layout {
   size_t pair_off = 0;           // M + 1 int32: pairs of coefficient m are pair_idx[off[m] .. off[m+1])
   size_t pair_idx = 0;           // N (N + 1) / 2 int32: i * N + j (i <= j), bit 31 set when i < j
   size_t bhdr = 0;               // BatchHeader: sizes and the places of the arrays above
+  // deterministic forward of FP32 and FP64 plans with N <= SOS_BATCH_MAX_N
+  // (uses pair_off / pair_idx above): the gram's slices, splits x N x N doubles
+  size_t det_G = 0;
   size_t bytes = 0;
 };
 
@@ -247,6 +277,7 @@ struct sos_plan_s {
   int ntiles256 = 0;               // upper-triangle tiles of 256 x 256
   std::vector<int32_t> tile_list;  // 2 * ntiles256
   bool batchable = false;          // grouped (serving) calls supported
+  bool det_ok = false;             // SOS_FLAG_DETERMINISTIC supported (pair lists, det_G)
   sos::BatchHeader bhdr{};         // uploaded to lay.bhdr at bind (batchable plans)
   // operand copies left by the last fused step (single-product backward with
   // Adam in its epilogue): valid for W pointer copies_W and forward mode
@@ -306,6 +337,18 @@ int hip_error(hipError_t e, const char* what);
 }  // namespace sos
 
 namespace sos {
+// plans whose operands are split into 16-bit hi and lo halves
+inline bool split_plan(const sos_plan_s* p) { return p->prec == SOS_BF16X3 || p->prec == SOS_FP16X3; }
+// device address of the fp16 scale exponents (sW, sR)
+inline int* scale_exponents(const sos_plan_s* p) { return (int*)((double*)(p->ws + p->lay.scal) + kScalScales); }
+// 2^e as a float, -126 <= e <= 127 (exact; integer operations only, so a
+// wave-uniform e stays in scalar registers)
+__host__ __device__ inline float pow2f(int e) {
+  const uint32_t b = (uint32_t)(127 + e) << 23;
+  float f;
+  __builtin_memcpy(&f, &b, 4);
+  return f;
+}
 // device ranking view of a bound plan
 inline RankTab rank_tab(const sos_plan_s* p) {
   RankTab t;
@@ -336,9 +379,15 @@ hipError_t launch_sumsq(const sos_plan_s* p, const double* x, int64_t M, double*
                         float* x32 = nullptr);
 enum { kFwdFast = 0, kFwdF32 = 1, kFwdExact = 2, kFwdOzaki = 3 };
 hipError_t launch_gram(const sos_plan_s* p, int mode, hipStream_t s);
+// deterministic forward (FP32 and FP64 plans with pair lists): the generic
+// gram stores its slices, then each coefficient sums its pairs in a fixed order
+hipError_t launch_gram_det(const sos_plan_s* p, const double* d_p, hipStream_t s);
 hipError_t launch_gather(const sos_plan_s* p, bool split, hipStream_t s);
 hipError_t launch_rw(const sos_plan_s* p, void* g, bool split, hipStream_t s);
-hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s);
+// store: the unfused measurement variant (tiles stored in the g region for
+// launch_scatter_tiles instead of scattered in the epilogue)
+hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s, bool store = false);
+hipError_t launch_scatter_tiles(const sos_plan_s* p, hipStream_t s);
 hipError_t launch_gram_x64(const sos_plan_s* p, hipStream_t s);
 // Ozaki-split forward (gemm_i8.hip): row exponents and int8 slices of W, then the gram
 hipError_t launch_oz_slices(const sos_plan_s* p, const float* W, hipStream_t s);
