@@ -553,7 +553,10 @@ def main():
     torch.cuda.empty_cache()
     if not a.no_ttt:
         out["ttt"] = {}
-        for name, prec, single, fin in (("mixed", "bf16x3", True, "fp64"), ("mixed_ozaki", "bf16x3", True, "ozaki"),
+        # mixed: split-bf16 bulk, then the FP64-accurate forward on int8 slices (the fastest finisher);
+        # mixed_fp64_finisher: the same with the FP64-MFMA finisher; fp32: the plain FP32 form
+        # (FP32 MFMA for both contractions, FP64-MFMA finisher)
+        for name, prec, single, fin in (("mixed", "bf16x3", True, "ozaki"), ("mixed_fp64_finisher", "bf16x3", True, "fp64"),
                                         ("fp32", "fp32", False, "fp64")):
             r = ttt_run(S, torch, a, c, W_start, p, prec, single, fin)
             out["ttt"][name] = {q: r[q] for q in ("seconds", "steps", "exact_steps", "rel", "best_rel", "certified",
