@@ -59,9 +59,10 @@ def full():
     pl = S.Plan(c.n, c.d, c.rank, "bf16x3")
     L_fast, g, r_fast = pl.loss_grad(Wd, pd, grad=True, want_r=True, single_backward=True)
     L_ex, _, r_ex = pl.loss_grad(Wd, pd, grad=False, want_r=True, exact=True)
+    L_oz, _, r_oz = pl.loss_grad(Wd, pd, grad=False, want_r=True, ozaki=True)
     torch.cuda.synchronize()
-    return dict(c=c, pl=pl, W=Wd, p=p, pd=pd, g=g, r_fast=r_fast, r_ex=r_ex,
-                L_fast=float(L_fast.item()), L_ex=float(L_ex.item()))
+    return dict(c=c, pl=pl, W=Wd, p=p, pd=pd, g=g, r_fast=r_fast, r_ex=r_ex, r_oz=r_oz,
+                L_fast=float(L_fast.item()), L_ex=float(L_ex.item()), L_oz=float(L_oz.item()))
 
 
 def sample_betas(M, count=96, seed=21):
@@ -86,11 +87,21 @@ def test_fullsize_sampled_coefficients(full):
     assert err.max() <= 1.0, f"fast forward: max |err|/bound {err.max():.3g}"
     err = np.abs(got_ex - want) / (1e-10 * cabs + slack)
     assert err.max() <= 1.0, f"exact forward: max |err|/bound {err.max():.3g}"
+    # the int8 Ozaki forward: its truncation bound 7.05 2^-42 K 2^(e_i + e_j) per
+    # Gram entry (2^e_i above row i's largest magnitude, from numpy's frexp),
+    # pair-summed by the oracle, and the FP64 path's 1e-10 of cabs
+    _, e = np.frexp(np.abs(W64).max(axis=1))
+    sc = np.ldexp(1.0, e)[:, None]
+    cs = O.sample_coefficients(sc, c.n, c.d, betas, basis, bidx, cidx)
+    got_oz = full["r_oz"][torch.as_tensor(betas, device=W.device)].cpu().numpy() + p
+    err = np.abs(got_oz - want)
+    assert np.max(err / (7.05 * 2.0 ** -42 * c.rank * cs + 1e-13 * cabs + slack)) <= 1.0
+    assert np.max(err / (1e-10 * cabs + slack)) <= 1.0, "Ozaki forward"
 
 
 def test_fullsize_loss_matches_residual(full):
     # L is the sum of squares of the r that the same call returns (FP64, fixed order)
-    for key_L, key_r in (("L_fast", "r_fast"), ("L_ex", "r_ex")):
+    for key_L, key_r in (("L_fast", "r_fast"), ("L_ex", "r_ex"), ("L_oz", "r_oz")):
         r = full[key_r]
         want = float(torch.dot(r, r))
         assert abs(full[key_L] - want) <= 1e-12 * want, key_L

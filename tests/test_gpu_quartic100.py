@@ -66,6 +66,29 @@ def test_quartic100_coefficients(case, prec, exact):
     assert abs(L.item() - want_L) <= 2 * np.sum(np.abs(case["c"] - case["p"]) * dc) + np.sum(dc * dc) + 1e-12 * want_L
 
 
+def test_quartic100_ozaki_coefficients(case):
+    """The int8 Ozaki forward on all 4,421,275 coefficients: within its
+    truncation bound (7.05 2^-42 K 2^(e_i + e_j) per Gram entry, 2^e_i the
+    least power of two above row i's largest magnitude, pair-summed by the
+    oracle's own map) and within 1e-10 of coeff(|W||W|^T)."""
+    n, d, N, M, K = case["n"], case["d"], case["N"], case["M"], case["k"]
+    pl = S.Plan(n, d, K, "bf16x3")
+    pd = torch.tensor(case["p"], dtype=torch.float64, device="cuda")
+    _, _, r = pl.loss_grad(case["Wd"], pd, grad=False, want_r=True, ozaki=True)
+    got = r.cpu().numpy() + case["p"]
+    _, e = np.frexp(np.abs(case["W64"]).max(axis=1))
+    sc = np.ldexp(1.0, e)
+    cs = np.zeros(M)
+    for r0 in range(0, N, 505):
+        rows = np.arange(r0, min(N, r0 + 505))
+        pr = O.pair_ranks_sparse(n, d, rows=rows, basis=case["basis"], cidx=case["cidx"])
+        cs += np.bincount(pr.ravel(), weights=np.outer(sc[rows], sc).ravel(), minlength=M)
+    slack = 1e-13 * (case["cabs"] + np.abs(case["p"]))
+    err = np.abs(got - case["c"])
+    assert np.max(err / (7.05 * 2.0 ** -42 * K * cs + slack)) <= 1.0
+    assert np.max(err / (1e-10 * case["cabs"] + 1e-15 * np.abs(case["p"]))) <= 1.0
+
+
 @pytest.mark.parametrize("prec,exact,single", [("bf16x3", False, True), ("bf16x3", True, False), ("fp32", False, False)])
 def test_quartic100_gradient_rows(case, prec, exact, single):
     """Rows of 4 R W against the oracle's r (bound: the backward's own error
