@@ -64,6 +64,8 @@ def parse():
                     help="FP64-accurate forward from int8 slices (Ozaki splitting) instead of the fast one")
     ap.add_argument("--unfused-scatter", action="store_true",
                     help="step: the gram stores its tiles and a separate kernel scatters them (measures the scatter)")
+    ap.add_argument("--unmerged-scatter", action="store_true",
+                    help="step: one FP64 atomic per Gram entry, without the plan's merge maps (measures them)")
     ap.add_argument("--deterministic", action="store_true",
                     help="step: FP32/FP64 plans, the forward sums each coefficient in a fixed order (no atomics)")
     ap.add_argument("--finisher", choices=("fp64", "ozaki"), default=None,
@@ -445,7 +447,8 @@ def main():
     flags = ((S.FLAG_EXACT_FORWARD if a.exact else 0) | (S.FLAG_OZAKI_FORWARD if a.ozaki else 0)
              | (S.FLAG_SINGLE_BACKWARD if a.single_backward else 0)
              | (S.FLAG_UNFUSED_SCATTER if a.unfused_scatter else 0)
-             | (S.FLAG_DETERMINISTIC if a.deterministic else 0))
+             | (S.FLAG_DETERMINISTIC if a.deterministic else 0)
+             | (S.FLAG_UNMERGED_SCATTER if a.unmerged_scatter else 0))
 
     if a.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -483,7 +486,8 @@ def main():
         peak = PEAKS_TFLOPS[a.precision]
     achieved = flops[dom] / (per_launch[dom] * 1e-3) / 1e12
     traffic = None
-    if c.name == "n12d6" and a.precision == "bf16x3" and a.single_backward and not (a.ozaki or a.unfused_scatter):
+    if (c.name == "n12d6" and a.precision == "bf16x3" and a.single_backward
+            and not (a.ozaki or a.unfused_scatter or a.unmerged_scatter)):
         key = {("gram", False): "step:k_gram_bf3", ("gram", True): "exact:k_gram_x64",
                ("rw", False): "step:k_rw_adam_bf3", ("rw", True): "step:k_rw_adam_bf3"}[(dom, a.exact)]
         traffic = measured_traffic(key)
@@ -498,7 +502,7 @@ def main():
                                + (f"U[-{c.w0_std:.4g},{c.w0_std:.4g}]; " if c.w0_uniform else f"N(0,{c.w0_std:.4g}^2); ")
                                + f"W N(0,{c.w_std:.4g}^2)",
                    "precision": a.precision, "exact_forward": a.exact, "ozaki_forward": a.ozaki, "lr": lr,
-                   "single_backward": a.single_backward,
+                   "single_backward": a.single_backward, "unmerged_scatter": a.unmerged_scatter,
                    "step": ("split-bf16 (hi/lo, three products) forward; one-product bf16 backward (hi*hi) with "
                             "Adam in its epilogue; FP64 residual and loss")
                    if (a.precision in SPLIT and a.single_backward and not a.exact and not a.ozaki) else None},
@@ -531,7 +535,7 @@ def main():
     if a.precision in SPLIT and a.single_backward and not (a.exact or a.ozaki or a.unfused_scatter):
         # the same step with the three-product (hi/lo) backward: separate R W GEMM, then Adam
         st2 = pl.new_state()
-        fl2 = 0
+        fl2 = flags & S.FLAG_UNMERGED_SCATTER
         for t in range(1, 3):
             pl.step(W, st2, t, p, adam, loss=loss, flags=fl2)
         torch.cuda.synchronize()

@@ -135,6 +135,13 @@ enum sos_flags {
    * SOS_K_SCATTER) ranks and adds them into r.  Same result as the fused
    * forward up to the order of the FP64 additions; slower.                */
   SOS_FLAG_UNFUSED_SCATTER = 64,
+  /* SOS_BF16X3 and SOS_FP16X3 plans, fused fast forward, a measurement
+   * variant: the gram's epilogue ranks each Gram entry and adds it into r by
+   * its own FP64 atomic, as the allocation-free entry point does, instead
+   * of first merging the entries of each 64 x 256 segment that share a
+   * coefficient in LDS (the merge maps that sos_plan_bind builds).  Same
+   * result up to the order of the FP64 additions; slower.                 */
+  SOS_FLAG_UNMERGED_SCATTER = 128,
 };
 
 /* Adam hyper-parameters (Kingma and Ba; the paper's optimiser, Section 3). */

@@ -27,6 +27,7 @@ FLAG_FP32_FORWARD = 8
 FLAG_OZAKI_FORWARD = 16
 FLAG_DETERMINISTIC = 32
 FLAG_UNFUSED_SCATTER = 64
+FLAG_UNMERGED_SCATTER = 128
 OK, NOT_CONVERGED = 0, 1
 EINVAL, ERANGE, ENOMEM, EHIP, ENUMERIC = -1, -2, -3, -4, -5
 
@@ -201,7 +202,8 @@ class Plan:
         return out
 
     def loss_grad(self, W, p, grad=True, want_r=False, exact=False, single_backward=False,
-                  fp32_forward=False, ozaki=False, deterministic=False, unfused_scatter=False, stream=None):
+                  fp32_forward=False, ozaki=False, deterministic=False, unfused_scatter=False,
+                  unmerged_scatter=False, stream=None):
         self._w(W), self._p(p)
         loss = torch.empty(1, dtype=torch.float64, device=self.device)
         g = torch.empty_like(W) if grad else None
@@ -212,7 +214,8 @@ class Plan:
                                   (FLAG_FP32_FORWARD if fp32_forward else 0) |
                                   (FLAG_OZAKI_FORWARD if ozaki else 0) |
                                   (FLAG_DETERMINISTIC if deterministic else 0) |
-                                  (FLAG_UNFUSED_SCATTER if unfused_scatter else 0), _stream(stream)))
+                                  (FLAG_UNFUSED_SCATTER if unfused_scatter else 0) |
+                                  (FLAG_UNMERGED_SCATTER if unmerged_scatter else 0), _stream(stream)))
         return loss, g, r
 
     def loss_grad_noalloc(self, W, p, loss, g=None, r=None, exact=False, single_backward=False,

@@ -118,7 +118,7 @@ static int run_forward(sos_plan_s* p, const void* W, const double* d_p, int flag
     TIMED(SOS_K_SCATTER, launch_scatter_tiles(p, s), "scatter");
   } else {
     TIMED(SOS_K_INIT, launch_init_r(p, d_p, s), "init_r");
-    TIMED(SOS_K_GRAM, launch_gram(p, mode, s), "gram");
+    TIMED(SOS_K_GRAM, launch_gram(p, mode, s, (flags & SOS_FLAG_UNMERGED_SCATTER) != 0), "gram");
   }
   float* r32 = (grad && p->prec != SOS_FP64) ? (float*)(p->ws + p->lay.r32) : nullptr;
   TIMED(SOS_K_LOSS, launch_sumsq(p, (const double*)(p->ws + p->lay.r), p->M, d_loss, s, r32), "loss");
@@ -179,6 +179,14 @@ static int check_unfused(const sos_plan_s* p, int flags, const char* fn) {
   if (!(flags & SOS_FLAG_UNFUSED_SCATTER)) return SOS_OK;
   if (p->prec != SOS_BF16X3 || fwd_mode(p, flags) != kFwdFast)
     return set_error(SOS_EINVAL, std::string(fn) + ": SOS_FLAG_UNFUSED_SCATTER needs a split plan's fast forward");
+  return SOS_OK;
+}
+
+// The unmerged scatter is a measurement variant of the split plans' fused fast forward.
+static int check_unmerged(const sos_plan_s* p, int flags, const char* fn) {
+  if (!(flags & SOS_FLAG_UNMERGED_SCATTER)) return SOS_OK;
+  if (!split_plan(p) || fwd_mode(p, flags) != kFwdFast || (flags & SOS_FLAG_UNFUSED_SCATTER))
+    return set_error(SOS_EINVAL, std::string(fn) + ": SOS_FLAG_UNMERGED_SCATTER needs a split plan's fused fast forward");
   return SOS_OK;
 }
 
@@ -293,7 +301,20 @@ int sos_plan_bind(sos_plan_t p, void* d_ws, size_t ws_bytes, void* stream) {
     SOS_HIP(hipMemcpyAsync(p->ws + p->lay.bhdr, &p->bhdr, sizeof(BatchHeader), hipMemcpyHostToDevice, s),
             "sos_plan_bind: batch header");
   }
+  p->merge_ready = false;
+  if (split_plan(p)) SOS_HIP(launch_merge_maps(p, s), "sos_plan_bind: merge maps of the gram epilogue");
   SOS_HIP(hipStreamSynchronize(s), "sos_plan_bind");
+  if (split_plan(p) && p->ntiles256 > 0) {
+    // merge only where it saves atomics (the counts the map kernel left)
+    const size_t segs = (size_t)p->ntiles256 * kMergeSegs;
+    std::vector<int32_t> issued(segs);
+    SOS_HIP(hipMemcpy(issued.data(), p->ws + p->lay.mg_count + segs * 4, segs * 4, hipMemcpyDeviceToHost),
+            "sos_plan_bind: merge counts");
+    double atomics = 0;
+    for (int32_t c : issued) atomics += c;
+    const double pairs = 0.5 * (double)p->N * (double)(p->N + 1);
+    p->merge_ready = pairs >= kMergeMinRatio * atomics;
+  }
   p->bound = true;
   return SOS_OK;
 }
@@ -331,8 +352,10 @@ int sos_loss_grad(sos_plan_t p, const void* d_W, const double* d_p, double* d_lo
   if (int rc = check_bound(p, "sos_loss_grad")) return rc;
   if (!d_W || !d_p || !d_loss) return set_error(SOS_EINVAL, "sos_loss_grad: d_W, d_p and d_loss are required");
   if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_SINGLE_BACKWARD | SOS_FLAG_FP32_FORWARD |
-                     SOS_FLAG_OZAKI_FORWARD | SOS_FLAG_DETERMINISTIC | SOS_FLAG_UNFUSED_SCATTER))
+                     SOS_FLAG_OZAKI_FORWARD | SOS_FLAG_DETERMINISTIC | SOS_FLAG_UNFUSED_SCATTER |
+                     SOS_FLAG_UNMERGED_SCATTER))
     return set_error(SOS_EINVAL, "sos_loss_grad: unknown flags");
+  if (int rc = check_unmerged(p, flags, "sos_loss_grad")) return rc;
   if (int rc = check_ozaki(p, flags, "sos_loss_grad")) return rc;
   if (int rc = check_unfused(p, flags, "sos_loss_grad")) return rc;
   if (int rc = check_det(p, flags, "sos_loss_grad")) return rc;
@@ -353,8 +376,9 @@ int sos_step(sos_plan_t p, void* d_W, void* d_state, int64_t t, const double* d_
   if (t < 1) return set_error(SOS_EINVAL, "sos_step: t is 1-based");
   if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_COPIES_VALID | SOS_FLAG_SINGLE_BACKWARD |
                      SOS_FLAG_FP32_FORWARD | SOS_FLAG_OZAKI_FORWARD | SOS_FLAG_DETERMINISTIC |
-                     SOS_FLAG_UNFUSED_SCATTER))
+                     SOS_FLAG_UNFUSED_SCATTER | SOS_FLAG_UNMERGED_SCATTER))
     return set_error(SOS_EINVAL, "sos_step: unknown flags");
+  if (int rc = check_unmerged(p, flags, "sos_step")) return rc;
   if (int rc = check_ozaki(p, flags, "sos_step")) return rc;
   if (int rc = check_unfused(p, flags, "sos_step")) return rc;
   if (int rc = check_det(p, flags, "sos_step")) return rc;

@@ -337,16 +337,111 @@ struct GramArgs {
   double* r;
   float* G;           // unfused variant: tile v stored row-major at G + 65536 v (nullptr: scatter)
   const int* sx;      // fp16 operands: sx[0] = sW, the W copies hold 2^sW w (bf16: unused)
+  // the plan's merge maps (see kMergeRows), or nullptr: every entry ranked and added on its own
+  const uint16_t* mmap;
+  const int* mrank;
+  const int* mcount;
 };
+
+// FP64 add into LDS (ds_add_f64: no return value is asked for).
+__device__ __forceinline__ void lds_add(double* p, double x) {
+  __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Epilogue with the plan's merge maps: the tile in four segments of 64 rows.
+// Per segment its accumulators go to LDS in FP32 (64 KB, the first half of
+// the pipeline ring); every pair is added, with its weight, into the FP64
+// slot its map names (the second half: kMergeSlots slots); then each slot in
+// use goes into r by one atomic, at the coefficient of the segment's rank
+// list.  About 3.6 pairs share a slot at n = 12, d = 6, so r sees that many
+// times fewer atomics than with one per pair.
+//
+// Loads and atomics share one in-order completion counter: a load issued
+// after an atomic can only be waited for once the atomic has completed.  So
+// a segment loads its share of the rank list at its start (while the
+// previous segment's atomics drain), not one entry per atomic, and its map
+// words one ahead of their use.
+template <bool F16>
+__device__ __forceinline__ void gram_merge_epilogue(const GramArgs& g, int v, int2 t, f32x16 (&acc)[BI][BJ],
+                                                    char* lds, double unscale) {
+  constexpr int RK = kMergeSlots / NT;  // rank-list entries per thread and segment, at most
+  const int wave = threadIdx.x >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+  float* stage = (float*)lds;
+  double* slots = (double*)(lds + kMergeSeg * 4);
+  static_assert(kMergeSeg * 4 + kMergeSlots * 8 <= NSTAGE * STAGE, "merge buffers exceed the ring");
+  static_assert(2 * kMergeRows == WM && BI == 4 && kMergeSeg % (NT * 8) == 0 && kMergeSlots % NT == 0,
+                "a segment is half a wave's rows");
+  const bool diag = t.x == t.y;
+#pragma unroll
+  for (int qq = 0; qq < kMergeSegs; ++qq) {
+    const int seg = v * kMergeSegs + qq;
+    const int ns = g.mcount[seg];
+    const uint16_t* mp = g.mmap + (size_t)seg * kMergeSeg;
+    const int* rl = g.mrank + (size_t)seg * kMergeSlots;
+    // every entry of the segment's list, used or not (q < kMergeSlots: inside
+    // it), so that the loads carry no branches and are waited for once
+    int rk[RK];
+#pragma unroll
+    for (int it = 0; it < RK; ++it) rk[it] = rl[threadIdx.x + it * NT];
+    uint4 mnext = *(const uint4*)(mp + threadIdx.x * 8);
+    __syncthreads();  // nobody reads the ring (or the previous segment's slots) any more
+    for (int q = threadIdx.x; q < ns; q += NT) slots[q] = 0.0;
+    if (wm == qq / 2) {
+#pragma unroll
+      for (int bi = 0; bi < BI; ++bi) {
+        if (bi / 2 != (qq & 1)) continue;
+#pragma unroll
+        for (int bj = 0; bj < BJ; ++bj)
+#pragma unroll
+          for (int q = 0; q < 16; ++q)
+            stage[(acc_row(wm, bi, q) - qq * kMergeRows) * TM + acc_col(wn, bj)] = acc[bi][bj][q];
+      }
+    }
+    __syncthreads();
+    for (int e0 = threadIdx.x * 8; e0 < kMergeSeg; e0 += NT * 8) {
+      const uint4 mw = mnext;
+      if (e0 + NT * 8 < kMergeSeg) mnext = *(const uint4*)(mp + e0 + NT * 8);
+      const float4 xa = *(const float4*)(stage + e0), xb = *(const float4*)(stage + e0 + 4);
+      const uint32_t m2[4] = {mw.x, mw.y, mw.z, mw.w};
+      const float xs[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const unsigned sl = (m2[u >> 1] >> (16 * (u & 1))) & 0xFFFFu;
+        if (sl == kMergeSkip) continue;
+        const int row = qq * kMergeRows + (e0 + u) / TM, col = (e0 + u) % TM;
+        const double x = ((diag && row == col) ? unscale : 2.0 * unscale) * (double)xs[u];
+        if (sl < kMergeSlots) lds_add(slots + sl, x);
+        else unsafeAtomicAdd(g.r + pair_rank(g.rk, t.x * TM + row, t.y * TM + col), x);
+      }
+    }
+    __syncthreads();
+    // all of this thread's slot sums first, into registers of their own, then
+    // the atomics: no atomic then waits for the previous one to release its
+    // data registers
+    double xv[RK];
+#pragma unroll
+    for (int it = 0; it < RK; ++it) {
+      const int q = threadIdx.x + it * NT;
+      const double x = slots[q];  // q < kMergeSlots: inside the slots, used or not
+      xv[it] = q < ns ? x : 0.0;
+    }
+#pragma unroll
+    for (int it = 0; it < RK; ++it)
+      if (xv[it] != 0.0) unsafeAtomicAdd(g.r + rk[it], xv[it]);
+  }
+}
 
 #define SOS_BF3_BUFFERS \
   __shared__ __attribute__((aligned(16))) char lds[NSTAGE * STAGE]
 
-// Epilogue through LDS: the accumulator tile (fp32, 256 KB) goes out in
-// row-halves of 128 x 256 (128 KB, the pipeline buffers being free by now);
-// then every thread takes consecutive elements of the half, ranks each
-// (row, col) pair and adds it into r.  Copying out with compile-time indices
-// keeps the accumulators in registers; the scatter loop indexes LDS instead.
+// The gram: one workgroup per upper tile, in the locality order of the tile
+// list.  Epilogue with merge maps (above), or without: the accumulator tile
+// (fp32, 256 KB) goes out in row-halves of 128 x 256 (128 KB, the pipeline
+// buffers being free by now); then every thread takes consecutive elements
+// of the half, ranks each (row, col) pair and adds it into r.  Copying out
+// with compile-time indices keeps the accumulators in registers; the scatter
+// loop indexes LDS instead.
 template <bool F16>
 __global__ __launch_bounds__(NT) void k_gram_bf3(GramArgs g) {
   SOS_BF3_BUFFERS;
@@ -355,6 +450,10 @@ __global__ __launch_bounds__(NT) void k_gram_bf3(GramArgs g) {
   f32x16 acc[BI][BJ];
   tile_gemm<true, F16>(g.o, g.K, (int64_t)t.x * TM, (int64_t)t.y * TM, lds, acc);
   const double unscale = F16 ? (double)pow2f(-2 * g.sx[0]) : 1.0;  // exact: a power of two
+  if (g.mmap) {
+    gram_merge_epilogue<F16>(g, v, t, acc, lds, unscale);
+    return;
+  }
   const int wave = threadIdx.x >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
   float* half = (float*)lds;  // the whole pipeline ring: 128 KB
@@ -388,6 +487,94 @@ __global__ __launch_bounds__(NT) void k_gram_bf3(GramArgs g) {
         unsafeAtomicAdd(g.r + pair_rank(g.rk, i, j), w * (double)half[e]);
       }
     }
+  }
+}
+
+// Merge maps, one workgroup per segment of 64 rows x 256 columns of a tile:
+// the rank of every pair of the segment in the upper triangle (i <= j < N)
+// goes with its position into a 64-bit key, the keys are sorted in LDS
+// (bitonic), and the distinct ranks numbered in ascending order; the first
+// kMergeSlots of them get slots, the rest kMergeDirect.  counts[seg] = slots
+// in use; counts[nsegs + seg] = the r atomics the segment then issues (slots
+// plus direct pairs).
+__global__ __launch_bounds__(512) void k_merge_maps(const int2* __restrict__ tiles, int N, RankTab rk,
+                                                    uint16_t* __restrict__ map, int* __restrict__ ranks,
+                                                    int* __restrict__ counts) {
+  constexpr int NTM = 512, PER = kMergeSeg / NTM;
+  constexpr unsigned long long kNone = 1ull << 46;  // above every (rank << 14 | position) key
+  static_assert(kMergeSeg == 1 << 14, "positions take 14 bits");
+  __shared__ unsigned long long key[kMergeSeg];
+  __shared__ int part[NTM + 1];
+  const int seg = blockIdx.x, v = seg / kMergeSegs, qq = seg % kMergeSegs;
+  const int2 t = tiles[v];
+  for (int e = threadIdx.x; e < kMergeSeg; e += NTM) {
+    const int i = t.x * TM + qq * kMergeRows + e / TM, j = t.y * TM + e % TM;
+    key[e] = (i < N && j < N && i <= j) ? ((unsigned long long)pair_rank(rk, i, j) << 14) | (unsigned)e
+                                        : kNone | (unsigned)e;
+  }
+  __syncthreads();
+  for (int size = 2; size <= kMergeSeg; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int x = threadIdx.x; x < kMergeSeg / 2; x += NTM) {
+        const int lo = 2 * x - (x & (stride - 1)), hi = lo + stride;  // lo has bit `stride` clear
+        const unsigned long long a = key[lo], b = key[hi];
+        if ((a > b) == ((lo & size) == 0)) {
+          key[lo] = b;
+          key[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  // each thread numbers PER consecutive keys: count the first key of every
+  // rank in its range, scan the counts, then assign
+  const int x0 = threadIdx.x * PER;
+  int firsts = 0;
+  for (int u = 0; u < PER; ++u) {
+    const unsigned long long k = key[x0 + u];
+    firsts += k < kNone && (x0 + u == 0 || (key[x0 + u - 1] >> 14) != (k >> 14));
+  }
+  part[threadIdx.x] = firsts;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int sum = 0;
+    for (int w = 0; w < NTM; ++w) {
+      const int c = part[w];
+      part[w] = sum;
+      sum += c;
+    }
+    part[NTM] = sum;
+  }
+  __syncthreads();
+  __shared__ int direct;
+  if (threadIdx.x == 0) direct = 0;
+  __syncthreads();
+  int slot = part[threadIdx.x] - 1;  // slot of a rank run continuing from the previous thread's keys
+  int ndirect = 0;
+  uint16_t* mp = map + (size_t)seg * kMergeSeg;
+  int* rl = ranks + (size_t)seg * kMergeSlots;
+  for (int u = 0; u < PER; ++u) {
+    const int x = x0 + u;
+    const unsigned long long k = key[x];
+    const int e = (int)(k & 0x3FFFu);
+    if (k >= kNone) {
+      mp[e] = kMergeSkip;
+      continue;
+    }
+    const bool first = x == 0 || (key[x - 1] >> 14) != (k >> 14);
+    slot += first;
+    if (slot < kMergeSlots) {
+      mp[e] = (uint16_t)slot;
+      if (first) rl[slot] = (int)(k >> 14);
+    } else {
+      mp[e] = kMergeDirect;
+      ++ndirect;
+    }
+  }
+  if (ndirect) atomicAdd(&direct, ndirect);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    counts[seg] = min(part[NTM], kMergeSlots);
+    counts[gridDim.x + seg] = min(part[NTM], kMergeSlots) + direct;
   }
 }
 
@@ -594,7 +781,7 @@ __global__ __launch_bounds__(NT) void k_rw_adam_bf3(RwAdamArgs a) {
 
 // Host side -----------------------------------------------------------------
 
-hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s, bool store) {
+hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s, bool store, bool unmerged) {
   bf3::GramArgs g;
   const bool f16 = p->prec == SOS_FP16X3;
   g.sx = scale_exponents(p);
@@ -609,8 +796,22 @@ hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s, bool store) {
   g.rk = rank_tab(p);
   g.r = (double*)(ws + p->lay.r);
   g.G = store ? (float*)(ws + p->lay.g) : nullptr;
+  const bool merge = p->merge_ready && !store && !unmerged;
+  g.mmap = merge ? (const uint16_t*)(ws + p->lay.mg_map) : nullptr;
+  g.mrank = merge ? (const int*)(ws + p->lay.mg_rank) : nullptr;
+  g.mcount = merge ? (const int*)(ws + p->lay.mg_count) : nullptr;
   if (f16) bf3::k_gram_bf3<true><<<g.ntiles, bf3::NT, 0, s>>>(g);
   else bf3::k_gram_bf3<false><<<g.ntiles, bf3::NT, 0, s>>>(g);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge_maps(const sos_plan_s* p, hipStream_t s) {
+  char* ws = p->ws;
+  if (p->ntiles256 == 0) return hipSuccess;
+  // grid = the number of segments (the kernel places its second count array after the first)
+  bf3::k_merge_maps<<<p->ntiles256 * kMergeSegs, 512, 0, s>>>(
+      (const int2*)(ws + p->lay.tiles), (int)p->N, rank_tab(p), (uint16_t*)(ws + p->lay.mg_map),
+      (int*)(ws + p->lay.mg_rank), (int*)(ws + p->lay.mg_count));
   return hipGetLastError();
 }
 

@@ -865,7 +865,7 @@ hipError_t launch_gram_det(const sos_plan_s* p, const double* d_p, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_gram(const sos_plan_s* p, int mode, hipStream_t s) {
+hipError_t launch_gram(const sos_plan_s* p, int mode, hipStream_t s, bool unmerged) {
   const char* ws = p->ws;
   if (p->prec == SOS_FP64) return gram_launch<MF64>(p, ws + p->lay.a_hi, nullptr, s);
   // FP32 padded row-major copy of W: a_hi in FP32 plans, a_f32 in split plans
@@ -873,7 +873,7 @@ hipError_t launch_gram(const sos_plan_s* p, int mode, hipStream_t s) {
   if (mode == kFwdExact) return launch_gram_x64(p, s);
   if (mode == kFwdOzaki) return launch_gram_i8(p, s);
   if (mode == kFwdF32 || p->prec == SOS_FP32) return gram_launch<MF32>(p, w32, nullptr, s);
-  return launch_gram_bf3(p, s);
+  return launch_gram_bf3(p, s, false, unmerged);
 }
 
 template <class Md>

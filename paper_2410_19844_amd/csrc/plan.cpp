@@ -204,6 +204,12 @@ int plan_create(int n, int d, int rank, int prec, sos_plan_s** out) {
   // gradient scratch; in split plans also the stored Gram tiles of the unfused
   // scatter variant (256 x 256 FP32 per upper tile)
   L.g = take(std::max((size_t)N * rank * wel, blk ? (size_t)p->ntiles256 * 256 * 256 * 4 : 0));
+  if (blk) {  // merge maps of the gram epilogue
+    const size_t segs = (size_t)p->ntiles256 * kMergeSegs;
+    L.mg_map = take(segs * kMergeSeg * 2);
+    L.mg_rank = take(segs * kMergeSlots * 4);
+    L.mg_count = take(segs * 2 * 4);
+  }
   if (prec != SOS_FP64) {  // Ozaki-split forward: int8 slices, row exponents and scales
     L.oz_slice = (size_t)(p->Np / kBlkRows) * oz_panel_stride(p->Kp);
     L.oz = take(L.oz_slice * kOzSlices);

@@ -67,6 +67,27 @@ __host__ __device__ inline int64_t oz_off(int64_t row, int64_t k, int64_t pstrid
 }
 constexpr int64_t kOzMaxK = ((int64_t(1) << 31) - 1) / (kOzSlices * 64 * 64);
 
+// Merge maps of the split plans' gram epilogue.  Each 256 x 256 tile is taken
+// in four segments of 64 rows (16,384 pairs); at n = 12, d = 6 the pairs of
+// a segment fall on about 4,600 distinct coefficients (3.6 pairs each, up to
+// ~7,900 distinct).  A map gives every pair of a segment its slot: the index
+// of its coefficient among the segment's distinct ones in ascending order
+// (kMergeSkip: outside the upper triangle or past N; kMergeDirect: beyond the
+// slot capacity, ranked and added on its own).  The epilogue adds the pairs
+// into FP64 slots in LDS and then each slot into r by one global atomic, to
+// the coefficient that the segment's rank list names.  Built on the GPU when
+// the plan is bound.
+constexpr int kMergeRows = 64;
+constexpr int kMergeSeg = kMergeRows * kBlkRows;   // pairs per segment
+constexpr int kMergeSegs = kBlkRows / kMergeRows;  // segments per tile
+constexpr int kMergeSlots = 8192;                  // FP64 slots per segment (64 KB of LDS)
+constexpr uint16_t kMergeSkip = 0xFFFF;
+constexpr uint16_t kMergeDirect = 0xFFFE;
+// Merging pays where it saves atomics: the plan uses the maps only when the
+// pairs of the upper triangle are at least kMergeMinRatio times the atomics
+// left after merging (n = 12, d = 6: 3.6; quartics in 99 variables: ~1.1).
+constexpr double kMergeMinRatio = 1.5;
+
 // Generic gram (kernels.hip, FP32 and FP64 plans): 128 x 128 upper tiles;
 // when they alone give fewer than kGramMinBlocks blocks, the contraction is
 // split into slices of kslice (a multiple of 64), one block per (tile, slice).
@@ -245,6 +266,10 @@ struct Layout {
   // deterministic forward of FP32 and FP64 plans with N <= SOS_BATCH_MAX_N
   // (uses pair_off / pair_idx above): the gram's slices, splits x N x N doubles
   size_t det_G = 0;
+  // split plans: merge maps of the gram epilogue (ntiles256 x 65,536 u16),
+  // the rank list of every segment (kMergeSlots int32 each), its length, and
+  // (second array of the same size) the r atomics the segment issues
+  size_t mg_map = 0, mg_rank = 0, mg_count = 0;
   size_t bytes = 0;
 };
 
@@ -278,6 +303,7 @@ struct sos_plan_s {
   std::vector<int32_t> tile_list;  // 2 * ntiles256
   bool batchable = false;          // grouped (serving) calls supported
   bool det_ok = false;             // SOS_FLAG_DETERMINISTIC supported (pair lists, det_G)
+  bool merge_ready = false;        // the workspace holds the gram's merge maps (built at bind)
   sos::BatchHeader bhdr{};         // uploaded to lay.bhdr at bind (batchable plans)
   // operand copies left by the last fused step (single-product backward with
   // Adam in its epilogue): valid for W pointer copies_W and forward mode
@@ -378,7 +404,7 @@ hipError_t launch_init_r(const sos_plan_s* p, const double* d_p, hipStream_t s);
 hipError_t launch_sumsq(const sos_plan_s* p, const double* x, int64_t M, double* out, hipStream_t s,
                         float* x32 = nullptr);
 enum { kFwdFast = 0, kFwdF32 = 1, kFwdExact = 2, kFwdOzaki = 3 };
-hipError_t launch_gram(const sos_plan_s* p, int mode, hipStream_t s);
+hipError_t launch_gram(const sos_plan_s* p, int mode, hipStream_t s, bool unmerged = false);
 // deterministic forward (FP32 and FP64 plans with pair lists): the generic
 // gram stores its slices, then each coefficient sums its pairs in a fixed order
 hipError_t launch_gram_det(const sos_plan_s* p, const double* d_p, hipStream_t s);
@@ -386,8 +412,11 @@ hipError_t launch_gather(const sos_plan_s* p, bool split, hipStream_t s);
 hipError_t launch_rw(const sos_plan_s* p, void* g, bool split, hipStream_t s);
 // store: the unfused measurement variant (tiles stored in the g region for
 // launch_scatter_tiles instead of scattered in the epilogue)
-hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s, bool store = false);
+// store: the unfused variant's stored tiles; unmerged: one atomic per Gram entry even where merge maps exist
+hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s, bool store = false, bool unmerged = false);
 hipError_t launch_scatter_tiles(const sos_plan_s* p, hipStream_t s);
+// the merge maps of a split plan's gram epilogue (into lay.mg_*; reads the ranking tables and the tile list)
+hipError_t launch_merge_maps(const sos_plan_s* p, hipStream_t s);
 hipError_t launch_gram_x64(const sos_plan_s* p, hipStream_t s);
 // Ozaki-split forward (gemm_i8.hip): row exponents and int8 slices of W, then the gram
 hipError_t launch_oz_slices(const sos_plan_s* p, const float* W, hipStream_t s);
