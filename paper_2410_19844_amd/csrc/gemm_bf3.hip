@@ -480,12 +480,26 @@ __global__ __launch_bounds__(NT) void k_gram_bf3(GramArgs g) {
       for (int e = threadIdx.x * 4; e < HROWS * TM; e += NT * 4) *(float4*)(dst + e) = *(const float4*)(half + e);
       continue;
     }
-    for (int e = threadIdx.x; e < HROWS * TM; e += NT) {
-      const int i = t.x * TM + hh * HROWS + e / TM, j = t.y * TM + e % TM;
-      if (i < g.N && j < g.N && i <= j) {
-        const double w = (i == j) ? unscale : 2.0 * unscale;
-        unsafeAtomicAdd(g.r + pair_rank(g.rk, i, j), w * (double)half[e]);
+    // In batches of SB entries per thread: the ranks of a batch first (their
+    // loads, with indices clamped into the basis so that none sits in a
+    // branch), then its atomics.  Loads and atomics complete in order, so
+    // this waits once per batch for the previous atomics, not once per entry.
+    constexpr int SB = 8, PER = HROWS * TM / NT;
+    static_assert(PER % SB == 0, "whole batches");
+    for (int k0 = 0; k0 < PER; k0 += SB) {
+      int rk[SB];
+      double xv[SB];
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        const int e = threadIdx.x + (k0 + u) * NT;
+        const int i = t.x * TM + hh * HROWS + e / TM, j = t.y * TM + e % TM;
+        const bool ok = i < g.N && j < g.N && i <= j;
+        rk[u] = pair_rank(g.rk, min(i, g.N - 1), min(j, g.N - 1));
+        xv[u] = ok ? ((i == j) ? unscale : 2.0 * unscale) * (double)half[e] : 0.0;
       }
+#pragma unroll
+      for (int u = 0; u < SB; ++u)
+        if (xv[u] != 0.0) unsafeAtomicAdd(g.r + rk[u], xv[u]);
     }
   }
 }
