@@ -22,6 +22,7 @@
 // given tiles that share operand panels.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 
 #include "sos_internal.h"
@@ -333,6 +334,7 @@ struct GramArgs {
   int64_t K;
   const int2* tiles;  // (I, J) tile pairs, I <= J, in locality order
   int ntiles, N;
+  int nfull, parts;   // tail split (see TailSplit): tiles nfull.. run in `parts` K ranges
   RankTab rk;
   double* r;
   float* G;           // unfused variant: tile v stored row-major at G + 65536 v (nullptr: scatter)
@@ -445,10 +447,28 @@ __device__ __forceinline__ void gram_merge_epilogue(const GramArgs& g, int v, in
 template <bool F16>
 __global__ __launch_bounds__(NT) void k_gram_bf3(GramArgs g) {
   SOS_BF3_BUFFERS;
-  const int v = xcd_order(blockIdx.x, g.ntiles);
+  // whole tiles first (XCD-aware order); then the tail tiles, `parts`
+  // contiguous K ranges each (whole blocks of every panel: the operands are
+  // the same arrays moved k0 blocks on)
+  int v;
+  int64_t k0 = 0, nks = g.K / BK;
+  if ((int)blockIdx.x < g.nfull) {
+    v = xcd_order(blockIdx.x, g.nfull);
+  } else {
+    const int u = (int)blockIdx.x - g.nfull, q = u % g.parts;
+    v = g.nfull + u / g.parts;
+    const int64_t nk = g.K / BK;
+    k0 = nk * q / g.parts;
+    nks = nk * (q + 1) / g.parts - k0;
+  }
   const int2 t = g.tiles[v];
+  Operands o = g.o;
+  o.a_hi += k0 * (TM * BK);
+  o.a_lo += k0 * (TM * BK);
+  o.b_hi += k0 * (TM * BK);
+  o.b_lo += k0 * (TM * BK);
   f32x16 acc[BI][BJ];
-  tile_gemm<true, F16>(g.o, g.K, (int64_t)t.x * TM, (int64_t)t.y * TM, lds, acc);
+  tile_gemm<true, F16>(o, nks * BK, (int64_t)t.x * TM, (int64_t)t.y * TM, lds, acc);
   const double unscale = F16 ? (double)pow2f(-2 * g.sx[0]) : 1.0;  // exact: a power of two
   if (g.mmap) {
     gram_merge_epilogue<F16>(g, v, t, acc, lds, unscale);
@@ -810,13 +830,48 @@ hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s, bool store, bool 
   g.rk = rank_tab(p);
   g.r = (double*)(ws + p->lay.r);
   g.G = store ? (float*)(ws + p->lay.g) : nullptr;
+  // the stored tiles of the unfused variant are whole: no tail split there
+  const TailSplit ts = store ? TailSplit{g.ntiles, 1} : gram_tail_split(g.ntiles, g.K / bf3::BK, s);
+  g.nfull = ts.nfull;
+  g.parts = ts.parts;
+  const int grid = ts.nfull + (g.ntiles - ts.nfull) * ts.parts;
   const bool merge = p->merge_ready && !store && !unmerged;
   g.mmap = merge ? (const uint16_t*)(ws + p->lay.mg_map) : nullptr;
   g.mrank = merge ? (const int*)(ws + p->lay.mg_rank) : nullptr;
   g.mcount = merge ? (const int*)(ws + p->lay.mg_count) : nullptr;
-  if (f16) bf3::k_gram_bf3<true><<<g.ntiles, bf3::NT, 0, s>>>(g);
-  else bf3::k_gram_bf3<false><<<g.ntiles, bf3::NT, 0, s>>>(g);
+  if (f16) bf3::k_gram_bf3<true><<<grid, bf3::NT, 0, s>>>(g);
+  else bf3::k_gram_bf3<false><<<grid, bf3::NT, 0, s>>>(g);
   return hipGetLastError();
+}
+
+TailSplit gram_tail_split(int ntiles, int64_t nstages, hipStream_t s) {
+  TailSplit ts;
+  ts.nfull = ntiles;
+  constexpr int kMaxDev = 64, kMaxParts = 8, kMinStages = 16;
+  static std::atomic<int> cus_of[kMaxDev];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return ts;
+  if (s && hipStreamGetDevice(s, &dev) != hipSuccess) return ts;
+  if (dev < 0 || dev >= kMaxDev) return ts;
+  int cus = cus_of[dev].load(std::memory_order_relaxed);
+  if (cus <= 0) {
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return ts;
+    cus_of[dev].store(cus, std::memory_order_relaxed);
+  }
+  const int rem = ntiles % cus;
+  if (ntiles < cus || rem == 0) return ts;
+  // the split that makes the last round shortest: ceil(rem p / cus) waves of
+  // 1/p of a tile each (rem = 141, cus = 256: p = 7, 0.57 of a round)
+  double best = 1.0;
+  for (int p = 2; p <= kMaxParts && nstages / p >= kMinStages; ++p) {
+    const double len = (double)((rem * p + cus - 1) / cus) / p;
+    if (len < best - 1e-9) {
+      best = len;
+      ts.parts = p;
+    }
+  }
+  if (ts.parts > 1) ts.nfull = ntiles - rem;
+  return ts;
 }
 
 hipError_t launch_merge_maps(const sos_plan_s* p, hipStream_t s) {

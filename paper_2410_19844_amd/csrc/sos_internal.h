@@ -412,6 +412,18 @@ hipError_t launch_gather(const sos_plan_s* p, bool split, hipStream_t s);
 hipError_t launch_rw(const sos_plan_s* p, void* g, bool split, hipStream_t s);
 // store: the unfused measurement variant (tiles stored in the g region for
 // launch_scatter_tiles instead of scattered in the epilogue)
+// Tail split of the 256-row grams: with one tile per workgroup and one
+// workgroup per CU, the last ntiles % CUs tiles run as a partial round on a
+// mostly idle chip (141 of 256 CUs at n = 12, d = 6).  Those tiles run
+// instead in `parts` contiguous K ranges each, every range scattering its
+// partial sum (the scatter is linear), so that the last round is shorter.
+// nfull = the tiles that run whole (the first nfull of the tile list);
+// parts = 1: no split.
+struct TailSplit {
+  int nfull = 0, parts = 1;
+};
+TailSplit gram_tail_split(int ntiles, int64_t nstages, hipStream_t s);
+
 // store: the unfused variant's stored tiles; unmerged: one atomic per Gram entry even where merge maps exist
 hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s, bool store = false, bool unmerged = false);
 hipError_t launch_scatter_tiles(const sos_plan_s* p, hipStream_t s);
