@@ -32,8 +32,8 @@
  *     pointers.  The library never allocates device memory: the caller
  *     provides a workspace (sos_plan_bind) and per-problem optimiser state.
  *   - `stream` is a hipStream_t passed as void* (NULL: the null stream).
- *     Device work is enqueued on it; only sos_solve, sos_verify and
- *     sos_exponents block the host.
+ *     Device work is enqueued on it; only sos_plan_bind, sos_solve,
+ *     sos_verify and sos_exponents block the host.
  *   - Return value: SOS_OK (0), a positive status, or a negative error.  On
  *     error sos_last_error() returns a message (thread-local).  Arguments
  *     are validated before anything is enqueued.  No entry point aborts the
@@ -215,8 +215,14 @@ int sos_plan_query(sos_plan_t plan, int64_t* N, int64_t* M, size_t* ws_bytes,
                    size_t* state_bytes);
 
 /* Attach a device workspace of at least ws_bytes (256-byte aligned) and
- * upload the ranking tables into it (asynchronously on `stream`).  The
- * workspace must stay allocated while the plan is used.                   */
+ * upload the ranking tables into it, on `stream`.  For SOS_BF16X3 and
+ * SOS_FP16X3 plans it also builds the gram epilogue's merge maps there (per
+ * 64 x 256 segment of every upper Gram tile: the slot of each pair among the
+ * segment's distinct coefficients, and their ranks; about 10 ms and 0.7 GB
+ * at n = 12, d = 6) and keeps them only where merging saves atomics (at least
+ * 1.5 pairs per coefficient of a segment on the whole).  Returns once the
+ * stream has done this work.  The workspace must stay allocated while the
+ * plan is used.                                                           */
 int sos_plan_bind(sos_plan_t plan, void* d_ws, size_t ws_bytes, void* stream);
 
 /* Free the host side of a plan (the workspace stays the caller's). */
