@@ -549,6 +549,7 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
   };
   bool w_moved = true;  // W changed outside a step (start, rollback): operand copies must be rebuilt
   int64_t t_adam = 0;   // Adam's step count since the moments were last zeroed
+  double done_rel = 0;  // the certificate of `best` that ended the loop
   while (t < o->max_steps && !done) {
     ++t;
     ++t_adam;
@@ -605,15 +606,22 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
       double vrel = 0;
       int vrc = sos_verify(p, best, d_p, &vrel, nullptr, stream);
       if (vrc) return vrc;
-      if (vrel <= o->tol) done = true;
-      else if (can_ladder && phase < 2) switch_phase = true;
+      if (vrel <= o->tol) {
+        done = true;
+        done_rel = vrel;
+      } else if (can_ladder && phase < 2) {
+        switch_phase = true;
+      }
     }
     if (switch_phase && !done) next_phase();
   }
   if (have_best) SOS_HIP(hipMemcpyAsync(d_W, best, wbytes, hipMemcpyDeviceToDevice, s), "sos_solve: best W");
-  double vrel = 0;
-  int vrc = sos_verify(p, d_W, d_p, &vrel, nullptr, stream);
-  if (vrc) return vrc;
+  // the returned W is `best`: when its certificate ended the loop, that is the result's
+  double vrel = done_rel;
+  if (!done) {
+    int vrc = sos_verify(p, d_W, d_p, &vrel, nullptr, stream);
+    if (vrc) return vrc;
+  }
   res->steps = t;
   res->exact_steps = exact_steps;
   res->loss = last_loss;
@@ -887,6 +895,7 @@ int sos_net_solve(sos_plan_t p, int n, int m, float* d_At, float* d_Bt, void* d_
   int64_t t = 0, exact_steps = 0;
   double loss = 0, best_rel = std::numeric_limits<double>::infinity();
   bool done = false;
+  double done_rel = 0;  // the certificate of the best weights that ended the loop
   int64_t t_adam = 0;  // Adam's step count since the moments were last zeroed
   auto verify = [&](int which, double* vrel) -> int {
     void* W = st + L.W;
@@ -937,8 +946,10 @@ int sos_net_solve(sos_plan_t p, int n, int m, float* d_At, float* d_Bt, void* d_
       // certify the best weights: W = net(A, B), FP64 forward
       double vrel = 0;
       if (int rc = verify(best, &vrel)) return rc;
-      if (vrel <= o->tol) done = true;
-      else if (can_ladder && phase == 0) {
+      if (vrel <= o->tol) {
+        done = true;
+        done_rel = vrel;
+      } else if (can_ladder && phase == 0) {
         phase = 1;
         if (o->lr_exact > 0) h.lr = o->lr_exact;
       }
@@ -948,8 +959,10 @@ int sos_net_solve(sos_plan_t p, int n, int m, float* d_At, float* d_Bt, void* d_
     SOS_HIP(hipMemcpyAsync(d_At, st + L.snapA[best], abytes, hipMemcpyDeviceToDevice, s), "net: best A");
     SOS_HIP(hipMemcpyAsync(d_Bt, st + L.snapB[best], bbytes, hipMemcpyDeviceToDevice, s), "net: best B");
   }
-  double vrel = 0;
-  if (int rc = verify(-1, &vrel)) return rc;
+  // the returned weights are the best ones: when their certificate ended the loop, that is the result's
+  double vrel = done_rel;
+  if (!done)
+    if (int rc = verify(-1, &vrel)) return rc;
   res->steps = t;
   res->exact_steps = exact_steps;
   res->loss = loss;

@@ -174,7 +174,16 @@ struct Args {
   int* lvl;               // level buffer: per tile, levels 0 .. S-2 of its int32 sums
   RankTab rk;
   double* r;
+  // the plan's merge maps (see kMergeRows), or nullptr: every entry ranked and added on its own
+  const uint16_t* mmap;
+  const int* mrank;
+  const int* mcount;
 };
+
+// FP64 add into LDS (ds_add_f64: no return value is asked for).
+__device__ __forceinline__ void lds_add(double* p, double x) {
+  __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 
 // Accumulator registers (bi, bj, 4 g .. 4 g + 3) of lane l sit at ints
 // 4 (((bi BJ + bj) 4 + g) 64 + l) of the wave's 8192-int share of a level, as
@@ -201,6 +210,100 @@ __device__ __forceinline__ void park_level(int* base, int lane_off, i32x16 (&acc
     }
 }
 
+// One pass of the merged epilogue (see k_gram_i8): segments h and 2 + h.
+// H is a template argument so that the accumulator blocks 2H, 2H + 1 are
+// named by compile-time indices (a run-time pass index would put the
+// accumulators in scratch memory).
+template <int H>
+__device__ __forceinline__ void merge_pass(const Args& g, int v, int wm, int wn, int64_t arow0, int64_t brow0,
+                                           const int* lvl_tile, int lane_off, char* ring, double* slots_w,
+                                           i32x16 (&acc)[BI][BJ]) {
+  constexpr int RK = kMergeSlots / NT;
+  constexpr int h = H;
+  const int l = threadIdx.x & 63;
+  const int sa = v * kMergeSegs + h, sb = v * kMergeSegs + 2 + h;
+  asm volatile("" ::: "memory");  // this pass's loads stay in it: registers for one pass at a time
+  const int na = g.mcount[sa], nb = g.mcount[sb];
+  int rka[RK];
+#pragma unroll
+  for (int it = 0; it < RK; ++it)  // every entry of the list, used or not (inside it), without branches
+    rka[it] = g.mrank[(size_t)sa * kMergeSlots + threadIdx.x + it * NT];
+  __syncthreads();  // nobody reads the ring (the last stage, or the previous pass's slots) any more
+  double* const s0 = (double*)ring;
+  double* const s1 = (double*)(ring + kMergeSlots * 8);
+  for (int q = threadIdx.x; q < na; q += NT) s0[q] = 0.0;
+  for (int q = threadIdx.x; q < nb; q += NT) s1[q] = 0.0;
+  __syncthreads();
+  const int seg = 2 * wm + h;
+  const uint16_t* mp = g.mmap + (size_t)(v * kMergeSegs + seg) * kMergeSeg;
+#pragma unroll
+  for (int bj = 0; bj < BJ; ++bj) {
+    const int col = wn * WN + bj * 32 + (l & 31);
+    const int j = (int)brow0 + col;
+    const double sj = j < g.N ? g.scale[j] : 0.0;
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb) {
+      const int bi = 2 * h + bb;
+#pragma unroll
+      for (int gq = 0; gq < 4; ++gq) {
+        i32x4 lv[S - 1];
+#pragma unroll
+        for (int q = 0; q < S - 1; ++q)
+          lv[q] = *(const i32x4*)(lvl_tile + q * kLvlInts + lane_off + lvl_const(bi, bj, gq));
+        unsigned sl[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int row = wm * WM + bi * 32 + gq * 8 + (l >> 5) * 4 + u;
+          sl[u] = mp[(row - seg * kMergeRows) * TM + col];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = (int)arow0 + wm * WM + bi * 32 + gq * 8 + (l >> 5) * 4 + u;
+          if (i < g.N && j < g.N && i <= j) {
+            double tot = 0.0, w = 1.0;
+#pragma unroll
+            for (int q = 0; q < S - 1; ++q) {
+              tot = fma((double)lv[q][u], w, tot);
+              w *= 0x1p-7;
+            }
+            tot = fma((double)acc[bi][bj][4 * gq + u], w, tot);
+            const double x = ((i == j) ? 1.0 : 2.0) * (tot * g.scale[i] * sj);
+            if (sl[u] < (unsigned)kMergeSlots) lds_add(slots_w + sl[u], x);
+            else unsafeAtomicAdd(g.r + pair_rank(g.rk, i, j), x);
+          }
+        }
+      }
+    }
+  }
+  // the second list now, still before this pass's first atomic
+  int rkb[RK];
+#pragma unroll
+  for (int it = 0; it < RK; ++it) rkb[it] = g.mrank[(size_t)sb * kMergeSlots + threadIdx.x + it * NT];
+  __syncthreads();
+  // per segment, all of this thread's slot sums first, into registers of
+  // their own, then the atomics
+  double x[RK];
+#pragma unroll
+  for (int it = 0; it < RK; ++it) {
+    const int q = threadIdx.x + it * NT;
+    const double a = s0[q];  // q < kMergeSlots: inside the slots, used or not
+    x[it] = q < na ? a : 0.0;
+  }
+#pragma unroll
+  for (int it = 0; it < RK; ++it)
+    if (x[it] != 0.0) unsafeAtomicAdd(g.r + rka[it], x[it]);
+#pragma unroll
+  for (int it = 0; it < RK; ++it) {
+    const int q = threadIdx.x + it * NT;
+    const double b = s1[q];
+    x[it] = q < nb ? b : 0.0;
+  }
+#pragma unroll
+  for (int it = 0; it < RK; ++it)
+    if (x[it] != 0.0) unsafeAtomicAdd(g.r + rkb[it], x[it]);
+}
+
+template <bool MERGE>
 __global__ __launch_bounds__(NT) void k_gram_i8(Args g) {
   __shared__ __attribute__((aligned(16))) char ring[NSTAGE * STAGE];
   const int v = xcd_order(blockIdx.x, g.ntiles);
@@ -268,38 +371,54 @@ __global__ __launch_bounds__(NT) void k_gram_i8(Args g) {
     if (cu.level_ends(nkb) && cu.lvl < S - 1) park_level(lvl_tile + cu.lvl * kLvlInts, lane_off, acc);
     cu.advance(nkb);
   }
-  // combine the levels in FP64 (each term a 31-bit integer times a power of
-  // two), scale by the row exponents, scatter.  Register (bi, bj, 4 gq + u)
-  // of lane l holds row 32 bi + 8 gq + 4 (l / 32) + u and column 32 bj + l % 32
-  // of the wave's 128 x 64 share.
+  // With merge maps: the tile in two passes over its 64-row segments, {0, 2}
+  // then {1, 3}, so that two segments' FP64 slots (2 x 64 KB) fill the ring.
+  // In pass h a wave of row half wm adds its row blocks 2h and 2h + 1 (the
+  // rows of segment 2 wm + h), combined as below, into the slot its map names;
+  // then each slot in use goes into r by one atomic, at the coefficient of
+  // the segment's rank list.  Each pass loads its rank-list entries at its
+  // start: loads and atomics complete in order, so the pass waits once for
+  // the previous one's atomics, not once per atomic.
   const int l = threadIdx.x & 63;
+  if constexpr (MERGE) {
+    static_assert(kMergeRows * 2 == WM && BI == 4 && kMergeSlots % NT == 0, "a segment is two row blocks of a wave");
+    static_assert(2 * kMergeSlots * 8 <= NSTAGE * STAGE, "two segments' slots fill at most the ring");
+    double* const slots_w = (double*)(ring + wm * (kMergeSlots * 8));  // this wave's segment in a pass
+    merge_pass<0>(g, v, wm, wn, arow0, brow0, lvl_tile, lane_off, ring, slots_w, acc);
+    merge_pass<1>(g, v, wm, wn, arow0, brow0, lvl_tile, lane_off, ring, slots_w, acc);
+  } else {
+    // combine the levels in FP64 (each term a 31-bit integer times a power of
+    // two), scale by the row exponents, scatter.  Register (bi, bj, 4 gq + u)
+    // of lane l holds row 32 bi + 8 gq + 4 (l / 32) + u and column 32 bj + l % 32
+    // of the wave's 128 x 64 share.
 #pragma unroll
-  for (int bj = 0; bj < BJ; ++bj) {
-    const int j = (int)brow0 + wn * WN + bj * 32 + (l & 31);
-    const double sj = j < g.N ? g.scale[j] : 0.0;
+    for (int bj = 0; bj < BJ; ++bj) {
+      const int j = (int)brow0 + wn * WN + bj * 32 + (l & 31);
+      const double sj = j < g.N ? g.scale[j] : 0.0;
 #pragma unroll
-    for (int bi = 0; bi < BI; ++bi)
+      for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
-      for (int gq = 0; gq < 4; ++gq) {
-        i32x4 lv[S - 1];
+        for (int gq = 0; gq < 4; ++gq) {
+          i32x4 lv[S - 1];
 #pragma unroll
-        for (int q = 0; q < S - 1; ++q) lv[q] = *(const i32x4*)(lvl_tile + q * kLvlInts + lane_off + lvl_const(bi, bj, gq));
+          for (int q = 0; q < S - 1; ++q) lv[q] = *(const i32x4*)(lvl_tile + q * kLvlInts + lane_off + lvl_const(bi, bj, gq));
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int i = (int)arow0 + wm * WM + bi * 32 + gq * 8 + (l >> 5) * 4 + u;
-          if (i < g.N && j < g.N && i <= j) {
-            double tot = 0.0, w = 1.0;
+          for (int u = 0; u < 4; ++u) {
+            const int i = (int)arow0 + wm * WM + bi * 32 + gq * 8 + (l >> 5) * 4 + u;
+            if (i < g.N && j < g.N && i <= j) {
+              double tot = 0.0, w = 1.0;
 #pragma unroll
-            for (int q = 0; q < S - 1; ++q) {
-              tot = fma((double)lv[q][u], w, tot);
-              w *= 0x1p-7;
+              for (int q = 0; q < S - 1; ++q) {
+                tot = fma((double)lv[q][u], w, tot);
+                w *= 0x1p-7;
+              }
+              tot = fma((double)acc[bi][bj][4 * gq + u], w, tot);
+              const double wgt = (i == j) ? 1.0 : 2.0;
+              unsafeAtomicAdd(g.r + pair_rank(g.rk, i, j), wgt * (tot * g.scale[i] * sj));
             }
-            tot = fma((double)acc[bi][bj][4 * gq + u], w, tot);
-            const double wgt = (i == j) ? 1.0 : 2.0;
-            unsafeAtomicAdd(g.r + pair_rank(g.rk, i, j), wgt * (tot * g.scale[i] * sj));
           }
         }
-      }
+    }
   }
 }
 
@@ -396,7 +515,11 @@ hipError_t launch_gram_i8(const sos_plan_s* p, hipStream_t s) {
   g.lvl = (int*)(ws + p->lay.oz_lvl);
   g.rk = rank_tab(p);
   g.r = (double*)(ws + p->lay.r);
-  i8::k_gram_i8<<<g.ntiles, i8::NT, 0, s>>>(g);
+  g.mmap = p->merge_ready ? (const uint16_t*)(ws + p->lay.mg_map) : nullptr;
+  g.mrank = p->merge_ready ? (const int*)(ws + p->lay.mg_rank) : nullptr;
+  g.mcount = p->merge_ready ? (const int*)(ws + p->lay.mg_count) : nullptr;
+  if (g.mmap) i8::k_gram_i8<true><<<g.ntiles, i8::NT, 0, s>>>(g);
+  else i8::k_gram_i8<false><<<g.ntiles, i8::NT, 0, s>>>(g);
   return hipGetLastError();
 }
 
