@@ -62,13 +62,15 @@ def parse():
     ap.add_argument("--exact", action="store_true", help="FP64 forward (the finishing phase)")
     ap.add_argument("--ozaki", action="store_true",
                     help="FP64-accurate forward from int8 slices (Ozaki splitting) instead of the fast one")
+    ap.add_argument("--ozaki-slices", type=int, default=6, choices=(5, 6),
+                    help="with --ozaki: digit slices (5: 15 slice products instead of 21, the finisher's forward)")
     ap.add_argument("--unfused-scatter", action="store_true",
                     help="step: the gram stores its tiles and a separate kernel scatters them (measures the scatter)")
     ap.add_argument("--unmerged-scatter", action="store_true",
                     help="step: one FP64 atomic per Gram entry, without the plan's merge maps (measures them)")
     ap.add_argument("--deterministic", action="store_true",
                     help="step: FP32/FP64 plans, the forward sums each coefficient in a fixed order (no atomics)")
-    ap.add_argument("--finisher", choices=("fp64", "ozaki"), default=None,
+    ap.add_argument("--finisher", choices=("fp64", "ozaki", "ozaki5"), default=None,
                     help="ttt: forward of the exact phase (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttt", action="store_true", help="step mode: skip the time-to-target runs")
@@ -289,7 +291,8 @@ def serve_mode(a, S, torch):
 def ttt_run(S, torch, a, c, W_host, p, precision, single_backward, finisher=None):
     """sos_solve from W_host to an FP64-verified ||r|| / ||p|| <= a.tol: the
     ladder (the plan's fast forward, then an FP64-accurate forward: FP64 MFMA,
-    or int8 slices with finisher "ozaki") with the workload's step sizes.
+    or int8 slices with finisher "ozaki", five slices with "ozaki5") with the
+    workload's step sizes.
     Returns the result with its wall time."""
     finisher = finisher or a.finisher or "fp64"
     lr_bulk, lr_fin = LR_DEFAULTS.get(c.name, (3e-3, 1e-3))
@@ -445,6 +448,7 @@ def main():
     adam = S.Adam(lr=lr)
     stream = torch.cuda.current_stream()
     flags = ((S.FLAG_EXACT_FORWARD if a.exact else 0) | (S.FLAG_OZAKI_FORWARD if a.ozaki else 0)
+             | (S.FLAG_OZAKI_FIVE_SLICES if a.ozaki and a.ozaki_slices == 5 else 0)
              | (S.FLAG_SINGLE_BACKWARD if a.single_backward else 0)
              | (S.FLAG_UNFUSED_SCATTER if a.unfused_scatter else 0)
              | (S.FLAG_DETERMINISTIC if a.deterministic else 0)
@@ -501,7 +505,8 @@ def main():
                                f"p=coeff(W0 W0^T), W0 {c.N}x{c.w0_rank} "
                                + (f"U[-{c.w0_std:.4g},{c.w0_std:.4g}]; " if c.w0_uniform else f"N(0,{c.w0_std:.4g}^2); ")
                                + f"W N(0,{c.w_std:.4g}^2)",
-                   "precision": a.precision, "exact_forward": a.exact, "ozaki_forward": a.ozaki, "lr": lr,
+                   "precision": a.precision, "exact_forward": a.exact, "ozaki_forward": a.ozaki,
+                   "ozaki_slices": a.ozaki_slices if a.ozaki else None, "lr": lr,
                    "single_backward": a.single_backward, "unmerged_scatter": a.unmerged_scatter,
                    "step": ("split-bf16 (hi/lo, three products) forward; one-product bf16 backward (hi*hi) with "
                             "Adam in its epilogue; FP64 residual and loss")
@@ -510,7 +515,8 @@ def main():
                      "frac": achieved / peak, "traffic": traffic,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1)",
                      "algorithmic_flops": flops[dom], "avg_ms": per_launch[dom],
-                     "executed_mfma_factor": (21 if (a.ozaki and not a.exact and dom == "gram") else
+                     "executed_mfma_factor": ((a.ozaki_slices * (a.ozaki_slices + 1) // 2)
+                                              if (a.ozaki and not a.exact and dom == "gram") else
                                               (1 if (dom == "rw" and a.single_backward) else 3)
                                               if (a.precision in SPLIT and not (a.exact and dom == "gram"))
                                               else 1)},
@@ -557,11 +563,12 @@ def main():
     torch.cuda.empty_cache()
     if not a.no_ttt:
         out["ttt"] = {}
-        # mixed: split-bf16 bulk, then the FP64-accurate forward on int8 slices (the fastest finisher);
-        # mixed_fp64_finisher: the same with the FP64-MFMA finisher; fp32: the plain FP32 form
-        # (FP32 MFMA for both contractions, FP64-MFMA finisher)
-        for name, prec, single, fin in (("mixed", "bf16x3", True, "ozaki"), ("mixed_fp64_finisher", "bf16x3", True, "fp64"),
-                                        ("fp32", "fp32", False, "fp64")):
+        # mixed: split-bf16 bulk, then the Ozaki forward on five int8 slices (the fastest finisher);
+        # mixed_ozaki6_finisher: six slices (the FP64-level Ozaki forward); mixed_fp64_finisher: the
+        # FP64-MFMA finisher; fp32: the plain FP32 form (FP32 MFMA for both contractions, FP64-MFMA
+        # finisher).  Every result is certified by the FP64-MFMA forward.
+        for name, prec, single, fin in (("mixed", "bf16x3", True, "ozaki5"), ("mixed_ozaki6_finisher", "bf16x3", True, "ozaki"),
+                                        ("mixed_fp64_finisher", "bf16x3", True, "fp64"), ("fp32", "fp32", False, "fp64")):
             r = ttt_run(S, torch, a, c, W_start, p, prec, single, fin)
             out["ttt"][name] = {q: r[q] for q in ("seconds", "steps", "exact_steps", "rel", "best_rel", "certified",
                                                   "precision", "lr", "lr_exact", "switch_rel", "single_backward",

@@ -142,6 +142,14 @@ enum sos_flags {
    * coefficient in LDS (the merge maps that sos_plan_bind builds).  Same
    * result up to the order of the FP64 additions; slower.                 */
   SOS_FLAG_UNMERGED_SCATTER = 128,
+  /* With SOS_FLAG_OZAKI_FORWARD: 5 digit slices instead of 6 (levels
+   * s + t < 5: 15 slice products instead of 21, about 0.7x the time).  Per
+   * Gram entry the error is then at most 6.05 * 2^-35 * rank * 2^(e_i + e_j)
+   * plus FP64 rounding, about 128x the six-slice figure; for Gaussian rows
+   * the coefficients come out within ~3e-10 of ||coeff(W W^T)||, far below
+   * residual targets such as 1e-8, so it serves as a finisher's forward
+   * (sos_solve's finisher 2).  SOS_EINVAL without SOS_FLAG_OZAKI_FORWARD. */
+  SOS_FLAG_OZAKI_FIVE_SLICES = 256,
 };
 
 /* Adam hyper-parameters (Kingma and Ba; the paper's optimiser, Section 3). */
@@ -176,8 +184,11 @@ typedef struct {
                             the solve with SOS_ENUMERIC                     */
   int32_t single_backward; /* 1: steps use SOS_FLAG_SINGLE_BACKWARD         */
   int32_t finisher;      /* forward of the exact phase: 0 FP64 MFMA
-                            (SOS_FLAG_EXACT_FORWARD), 1 int8 slices
-                            (SOS_FLAG_OZAKI_FORWARD)                        */
+                            (SOS_FLAG_EXACT_FORWARD), 1 six int8 slices
+                            (SOS_FLAG_OZAKI_FORWARD), 2 five int8 slices
+                            (with SOS_FLAG_OZAKI_FIVE_SLICES).  The result
+                            is certified by the FP64-MFMA forward in every
+                            case                                            */
   double mid_rel;        /* SOS_BF16X3 ladder with a middle rung: after the
                             fast phase, steps use SOS_FLAG_FP32_FORWARD until
                             rel <= mid_rel (or a stall), then the exact

@@ -28,6 +28,7 @@ FLAG_OZAKI_FORWARD = 16
 FLAG_DETERMINISTIC = 32
 FLAG_UNFUSED_SCATTER = 64
 FLAG_UNMERGED_SCATTER = 128
+FLAG_OZAKI_FIVE_SLICES = 256
 OK, NOT_CONVERGED = 0, 1
 EINVAL, ERANGE, ENOMEM, EHIP, ENUMERIC = -1, -2, -3, -4, -5
 
@@ -122,6 +123,17 @@ def _ptr(t):
     return ctypes.c_void_p(0 if t is None else t.data_ptr())
 
 
+def _oz_flags(ozaki):
+    """Flags of the Ozaki forward: False (off), True or 6 (six digit slices), 5 (five)."""
+    if ozaki is False or ozaki is None or ozaki == 0:
+        return 0
+    if ozaki is True or ozaki == 6:
+        return FLAG_OZAKI_FORWARD
+    if ozaki == 5:
+        return FLAG_OZAKI_FORWARD | FLAG_OZAKI_FIVE_SLICES
+    raise ValueError("ozaki must be False, True, 5 or 6")
+
+
 @dataclass
 class Adam:
     lr: float = 1e-3
@@ -212,7 +224,7 @@ class Plan:
                                   (FLAG_EXACT_FORWARD if exact else 0) |
                                   (FLAG_SINGLE_BACKWARD if single_backward else 0) |
                                   (FLAG_FP32_FORWARD if fp32_forward else 0) |
-                                  (FLAG_OZAKI_FORWARD if ozaki else 0) |
+                                  _oz_flags(ozaki) |
                                   (FLAG_DETERMINISTIC if deterministic else 0) |
                                   (FLAG_UNFUSED_SCATTER if unfused_scatter else 0) |
                                   (FLAG_UNMERGED_SCATTER if unmerged_scatter else 0), _stream(stream)))
@@ -228,7 +240,7 @@ class Plan:
                                           (FLAG_EXACT_FORWARD if exact else 0) |
                                           (FLAG_SINGLE_BACKWARD if single_backward else 0) |
                                           (FLAG_FP32_FORWARD if fp32_forward else 0) |
-                                          (FLAG_OZAKI_FORWARD if ozaki else 0), _stream(stream)))
+                                          _oz_flags(ozaki), _stream(stream)))
         return loss, g, r
 
     def step(self, W, state, t, p, adam: Adam, loss=None, flags=0, stream=None):
@@ -262,10 +274,11 @@ class Plan:
               single_backward=False, mid_rel=0.0, finisher="fp64", deterministic=False, state=None,
               stream=None):
         """sos_solve: Adam to an FP64-verified ||r||/||p|| <= tol; W ends as the best iterate.
-        finisher: forward of the exact phase, "fp64" (FP64 MFMA) or "ozaki" (int8 slices)."""
+        finisher: forward of the exact phase, "fp64" (FP64 MFMA), "ozaki" (six int8 slices) or
+        "ozaki5" (five int8 slices)."""
         self._w(W), self._p(p)
         state = self.new_state() if state is None else state
-        fin = {"fp64": 0, "ozaki": 1}[finisher]
+        fin = {"fp64": 0, "ozaki": 1, "ozaki5": 2}[finisher]
         opts = _SolveOpts(tol, max_steps, check_every, 1 if ladder else 0, stall_checks, stall_ratio,
                           switch_rel, lr_exact, rollback_ratio, 1 if single_backward else 0, fin, mid_rel,
                           FLAG_DETERMINISTIC if deterministic else 0, 0)

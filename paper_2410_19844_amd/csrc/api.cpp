@@ -91,6 +91,9 @@ static int fwd_mode(const sos_plan_s* p, int flags) {
   return kFwdFast;
 }
 
+// Digit slices of the Ozaki forward.
+static int oz_slices(int flags) { return (flags & SOS_FLAG_OZAKI_FIVE_SLICES) ? 5 : kOzSlices; }
+
 // grad: a backward follows (so the transposed operand copies are needed).
 // reuse: the operand copies already in the workspace were made from this W
 // for this mode (by the epilogue of the previous fused step): no preparation.
@@ -109,7 +112,7 @@ static int run_forward(sos_plan_s* p, const void* W, const double* d_p, int flag
     p->t_cur = 0;  // the preparation writes the transposed copy into t_hi
   }
   // the int8 slices need the row maxima of W, so no GEMM epilogue leaves them: built every time
-  if (mode == kFwdOzaki) TIMED(SOS_K_PREP, launch_oz_slices(p, (const float*)W, s), "Ozaki slices");
+  if (mode == kFwdOzaki) TIMED(SOS_K_PREP, launch_oz_slices(p, (const float*)W, s, oz_slices(flags)), "Ozaki slices");
   if ((flags & SOS_FLAG_DETERMINISTIC) && mode == kFwdFast) {
     TIMED(SOS_K_GRAM, launch_gram_det(p, d_p, s), "gram (deterministic)");
   } else if ((flags & SOS_FLAG_UNFUSED_SCATTER) && mode == kFwdFast && p->prec == SOS_BF16X3) {
@@ -118,7 +121,7 @@ static int run_forward(sos_plan_s* p, const void* W, const double* d_p, int flag
     TIMED(SOS_K_SCATTER, launch_scatter_tiles(p, s), "scatter");
   } else {
     TIMED(SOS_K_INIT, launch_init_r(p, d_p, s), "init_r");
-    TIMED(SOS_K_GRAM, launch_gram(p, mode, s, (flags & SOS_FLAG_UNMERGED_SCATTER) != 0), "gram");
+    TIMED(SOS_K_GRAM, launch_gram(p, mode, s, (flags & SOS_FLAG_UNMERGED_SCATTER) != 0, oz_slices(flags)), "gram");
   }
   float* r32 = (grad && p->prec != SOS_FP64) ? (float*)(p->ws + p->lay.r32) : nullptr;
   TIMED(SOS_K_LOSS, launch_sumsq(p, (const double*)(p->ws + p->lay.r), p->M, d_loss, s, r32), "loss");
@@ -192,6 +195,8 @@ static int check_unmerged(const sos_plan_s* p, int flags, const char* fn) {
 
 // The Ozaki forward needs an FP32 master W and a K extent whose level sums stay exact in int32.
 static int check_ozaki(const sos_plan_s* p, int flags, const char* fn) {
+  if ((flags & SOS_FLAG_OZAKI_FIVE_SLICES) && !(flags & SOS_FLAG_OZAKI_FORWARD))
+    return set_error(SOS_EINVAL, std::string(fn) + ": SOS_FLAG_OZAKI_FIVE_SLICES needs SOS_FLAG_OZAKI_FORWARD");
   if (!(flags & SOS_FLAG_OZAKI_FORWARD) || (flags & SOS_FLAG_EXACT_FORWARD)) return SOS_OK;
   if (p->prec == SOS_FP64)
     return set_error(SOS_EINVAL, std::string(fn) + ": SOS_FLAG_OZAKI_FORWARD needs an FP32 or split plan");
@@ -353,7 +358,7 @@ int sos_loss_grad(sos_plan_t p, const void* d_W, const double* d_p, double* d_lo
   if (!d_W || !d_p || !d_loss) return set_error(SOS_EINVAL, "sos_loss_grad: d_W, d_p and d_loss are required");
   if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_SINGLE_BACKWARD | SOS_FLAG_FP32_FORWARD |
                      SOS_FLAG_OZAKI_FORWARD | SOS_FLAG_DETERMINISTIC | SOS_FLAG_UNFUSED_SCATTER |
-                     SOS_FLAG_UNMERGED_SCATTER))
+                     SOS_FLAG_UNMERGED_SCATTER | SOS_FLAG_OZAKI_FIVE_SLICES))
     return set_error(SOS_EINVAL, "sos_loss_grad: unknown flags");
   if (int rc = check_unmerged(p, flags, "sos_loss_grad")) return rc;
   if (int rc = check_ozaki(p, flags, "sos_loss_grad")) return rc;
@@ -376,7 +381,7 @@ int sos_step(sos_plan_t p, void* d_W, void* d_state, int64_t t, const double* d_
   if (t < 1) return set_error(SOS_EINVAL, "sos_step: t is 1-based");
   if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_COPIES_VALID | SOS_FLAG_SINGLE_BACKWARD |
                      SOS_FLAG_FP32_FORWARD | SOS_FLAG_OZAKI_FORWARD | SOS_FLAG_DETERMINISTIC |
-                     SOS_FLAG_UNFUSED_SCATTER | SOS_FLAG_UNMERGED_SCATTER))
+                     SOS_FLAG_UNFUSED_SCATTER | SOS_FLAG_UNMERGED_SCATTER | SOS_FLAG_OZAKI_FIVE_SLICES))
     return set_error(SOS_EINVAL, "sos_step: unknown flags");
   if (int rc = check_unmerged(p, flags, "sos_step")) return rc;
   if (int rc = check_ozaki(p, flags, "sos_step")) return rc;
@@ -474,7 +479,7 @@ int sos_loss_grad_noalloc(sos_plan_t p, const void* d_W, const double* d_p, doub
   if (!d_W || !d_p || !d_loss)
     return set_error(SOS_EINVAL, "sos_loss_grad_noalloc: d_W, d_p and d_loss are required");
   if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_SINGLE_BACKWARD | SOS_FLAG_FP32_FORWARD |
-                     SOS_FLAG_OZAKI_FORWARD))
+                     SOS_FLAG_OZAKI_FORWARD | SOS_FLAG_OZAKI_FIVE_SLICES))
     return set_error(SOS_EINVAL, "sos_loss_grad_noalloc: unknown flags");
   if (int rc = check_ozaki(p, flags, "sos_loss_grad_noalloc")) return rc;
   if (p->lay.bytes > (size_t)SOS_NOALLOC_MAX_WS)
@@ -510,7 +515,7 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
       !(o->rollback_ratio >= 0) || o->stall_checks < 0)
     return set_error(SOS_EINVAL, "sos_solve: needs max_steps >= 0, check_every >= 1, tol, lr_exact, "
                                  "rollback_ratio >= 0 and stall_checks >= 0");
-  if (o->finisher != 0 && o->finisher != 1) return set_error(SOS_EINVAL, "sos_solve: finisher must be 0 or 1");
+  if (o->finisher < 0 || o->finisher > 2) return set_error(SOS_EINVAL, "sos_solve: finisher must be 0, 1 or 2");
   if (o->step_flags & ~(int)SOS_FLAG_DETERMINISTIC)
     return set_error(SOS_EINVAL, "sos_solve: step_flags may be SOS_FLAG_DETERMINISTIC");
   if (int rc = check_det(p, o->step_flags, "sos_solve")) return rc;
@@ -555,7 +560,9 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
     ++t_adam;
     const bool check = (t % o->check_every == 0) || t == o->max_steps;
     if (check) SOS_HIP(hipMemcpyAsync(cand, d_W, wbytes, hipMemcpyDeviceToDevice, s), "sos_solve: snapshot");
-    const int exact_flag = o->finisher ? SOS_FLAG_OZAKI_FORWARD : SOS_FLAG_EXACT_FORWARD;
+    const int exact_flag = o->finisher == 2   ? SOS_FLAG_OZAKI_FORWARD | SOS_FLAG_OZAKI_FIVE_SLICES
+                           : o->finisher == 1 ? SOS_FLAG_OZAKI_FORWARD
+                                              : SOS_FLAG_EXACT_FORWARD;
     const int flags = (phase == 2 ? exact_flag : phase == 1 ? SOS_FLAG_FP32_FORWARD : (o->step_flags & SOS_FLAG_DETERMINISTIC)) |
                       (o->single_backward ? SOS_FLAG_SINGLE_BACKWARD : 0) |
                       (w_moved ? 0 : SOS_FLAG_COPIES_VALID);

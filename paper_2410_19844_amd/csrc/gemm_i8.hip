@@ -18,6 +18,9 @@
 // (S + 1.05) 2^-7S K 2^(e_i + e_j), plus FP64 rounding (about 1e-12 of the
 // Gram entry at S = 6 and Gaussian rows; the errors of individual digits are
 // independent, so the actual error is far below this bound).
+// S is a template argument: 6 (kOzSlices, the FP64-level forward) or 5
+// (levels s + t < 5: 15 slice products instead of 21, about 128x the error,
+// for a finisher whose target lies far above it).
 //
 // Kernel: one 256 x 256 upper-triangle tile per 512-thread workgroup, 8 waves
 // of 128 x 64 (4 x 2 blocks of v_mfma_i32_32x32x32_i8, two waves per SIMD),
@@ -46,7 +49,6 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x16 __attribute__((ext_vector_type(16)));
 typedef __attribute__((address_space(3))) void* lds_t;
 
-constexpr int S = kOzSlices;
 constexpr int TM = 256;             // tile rows and columns (one panel each)
 constexpr int BK = kOzBK;           // K (bytes) per stage: one block of the slice layout
 constexpr int NT = 512;
@@ -59,6 +61,7 @@ constexpr int BI = WM / 32, BJ = WN / 32;
 constexpr int kXcds = 8;
 constexpr int LOADS = 4;            // 32 KB per stage = 32 loads of 1 KB over 8 waves
 constexpr int kLvlInts = TM * TM;   // one level of one tile in the level buffer
+constexpr int64_t kLvlTile = (int64_t)(kOzSlices - 1) * kLvlInts;  // a tile's levels (room for the most slices)
 
 __device__ __forceinline__ int xcd_order(int b, int nb) {
   const int q = nb / kXcds, rem = nb % kXcds;
@@ -171,7 +174,7 @@ struct Args {
   const int2* tiles;      // 256 x 256 upper-triangle tile list
   int ntiles, N;
   const double* scale;    // 2^(e_i - 6) per row (NaN: the row holds a non-finite entry)
-  int* lvl;               // level buffer: per tile, levels 0 .. S-2 of its int32 sums
+  int* lvl;               // level buffer: per tile (kLvlTile ints), levels 0 .. S-2 of its int32 sums
   RankTab rk;
   double* r;
   // the plan's merge maps (see kMergeRows), or nullptr: every entry ranked and added on its own
@@ -214,7 +217,7 @@ __device__ __forceinline__ void park_level(int* base, int lane_off, i32x16 (&acc
 // H is a template argument so that the accumulator blocks 2H, 2H + 1 are
 // named by compile-time indices (a run-time pass index would put the
 // accumulators in scratch memory).
-template <int H>
+template <int H, int S>
 __device__ __forceinline__ void merge_pass(const Args& g, int v, int wm, int wn, int64_t arow0, int64_t brow0,
                                            const int* lvl_tile, int lane_off, char* ring, double* slots_w,
                                            i32x16 (&acc)[BI][BJ]) {
@@ -303,8 +306,9 @@ __device__ __forceinline__ void merge_pass(const Args& g, int v, int wm, int wn,
     if (x[it] != 0.0) unsafeAtomicAdd(g.r + rkb[it], x[it]);
 }
 
-template <bool MERGE>
+template <bool MERGE, int S>
 __global__ __launch_bounds__(NT) void k_gram_i8(Args g) {
+  static_assert(S >= 2 && S <= kOzSlices, "the level buffer and the slice arrays hold at most kOzSlices");
   __shared__ __attribute__((aligned(16))) char ring[NSTAGE * STAGE];
   const int v = xcd_order(blockIdx.x, g.ntiles);
   const int2 t = g.tiles[v];
@@ -319,7 +323,7 @@ __global__ __launch_bounds__(NT) void k_gram_i8(Args g) {
   const int64_t nkb = g.nkb;
   const int64_t nv = (int64_t)(S * (S + 1) / 2) * nkb;  // stages over all segments
   const unsigned ring_lds = __builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)(lds_t)ring);
-  int* const lvl_tile = g.lvl + (int64_t)v * (S - 1) * kLvlInts;
+  int* const lvl_tile = g.lvl + (int64_t)v * kLvlTile;
   const int lane_off = wave * (kLvlInts / 8) + 4 * (threadIdx.x & 63);
   Cursor in, cu;  // next stage to issue, stage to compute
   // Software pipeline: the ring holds four stages, loads run three stages
@@ -384,8 +388,8 @@ __global__ __launch_bounds__(NT) void k_gram_i8(Args g) {
     static_assert(kMergeRows * 2 == WM && BI == 4 && kMergeSlots % NT == 0, "a segment is two row blocks of a wave");
     static_assert(2 * kMergeSlots * 8 <= NSTAGE * STAGE, "two segments' slots fill at most the ring");
     double* const slots_w = (double*)(ring + wm * (kMergeSlots * 8));  // this wave's segment in a pass
-    merge_pass<0>(g, v, wm, wn, arow0, brow0, lvl_tile, lane_off, ring, slots_w, acc);
-    merge_pass<1>(g, v, wm, wn, arow0, brow0, lvl_tile, lane_off, ring, slots_w, acc);
+    merge_pass<0, S>(g, v, wm, wn, arow0, brow0, lvl_tile, lane_off, ring, slots_w, acc);
+    merge_pass<1, S>(g, v, wm, wn, arow0, brow0, lvl_tile, lane_off, ring, slots_w, acc);
   } else {
     // combine the levels in FP64 (each term a 31-bit integer times a power of
     // two), scale by the row exponents, scatter.  Register (bi, bj, 4 gq + u)
@@ -458,10 +462,11 @@ __global__ __launch_bounds__(256) void k_oz_scale(const float* __restrict__ W, i
   }
 }
 
-// Digits of a 64 x 64 tile of W into the S slice arrays (padding rows and
-// columns get zero digits).  Loads are coalesced along rows; the digits go
-// through LDS so that every slice is written in 16-byte chunks of the
+// Digits of a 64 x 64 tile of W into the first S slice arrays (padding rows
+// and columns get zero digits).  Loads are coalesced along rows; the digits
+// go through LDS so that every slice is written in 16-byte chunks of the
 // blocked layout.
+template <int S>
 __global__ __launch_bounds__(256) void k_oz_slice(const float* __restrict__ W, int N, int k,
                                                   const int* __restrict__ ex, int8_t* __restrict__ oz,
                                                   int64_t slice_bytes, int64_t pstride) {
@@ -489,19 +494,23 @@ __global__ __launch_bounds__(256) void k_oz_slice(const float* __restrict__ W, i
 
 }  // namespace i8
 
-hipError_t launch_oz_slices(const sos_plan_s* p, const float* W, hipStream_t s) {
+hipError_t launch_oz_slices(const sos_plan_s* p, const float* W, hipStream_t s, int slices) {
+  if (slices != kOzSlices && slices != 5) return hipErrorInvalidValue;
   char* ws = p->ws;
   int* ex = (int*)(ws + p->lay.oz_exp);
   i8::k_oz_scale<<<(unsigned)p->N, 256, 0, s>>>(W, (int)p->N, p->k, ex, (double*)(ws + p->lay.oz_scale));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const dim3 grid((unsigned)(p->Kp / 64), (unsigned)(p->Np / 64));
-  i8::k_oz_slice<<<grid, 256, 0, s>>>(W, (int)p->N, p->k, ex, (int8_t*)(ws + p->lay.oz), (int64_t)p->lay.oz_slice,
-                                      oz_panel_stride(p->Kp));
+  int8_t* oz = (int8_t*)(ws + p->lay.oz);
+  const int64_t sb = (int64_t)p->lay.oz_slice, ps = oz_panel_stride(p->Kp);
+  if (slices == 5) i8::k_oz_slice<5><<<grid, 256, 0, s>>>(W, (int)p->N, p->k, ex, oz, sb, ps);
+  else i8::k_oz_slice<kOzSlices><<<grid, 256, 0, s>>>(W, (int)p->N, p->k, ex, oz, sb, ps);
   return hipGetLastError();
 }
 
-hipError_t launch_gram_i8(const sos_plan_s* p, hipStream_t s) {
+hipError_t launch_gram_i8(const sos_plan_s* p, hipStream_t s, int slices) {
+  if (slices != kOzSlices && slices != 5) return hipErrorInvalidValue;
   i8::Args g;
   const char* ws = p->ws;
   g.oz = (const int8_t*)(ws + p->lay.oz);
@@ -518,8 +527,13 @@ hipError_t launch_gram_i8(const sos_plan_s* p, hipStream_t s) {
   g.mmap = p->merge_ready ? (const uint16_t*)(ws + p->lay.mg_map) : nullptr;
   g.mrank = p->merge_ready ? (const int*)(ws + p->lay.mg_rank) : nullptr;
   g.mcount = p->merge_ready ? (const int*)(ws + p->lay.mg_count) : nullptr;
-  if (g.mmap) i8::k_gram_i8<true><<<g.ntiles, i8::NT, 0, s>>>(g);
-  else i8::k_gram_i8<false><<<g.ntiles, i8::NT, 0, s>>>(g);
+  if (slices == 5) {
+    if (g.mmap) i8::k_gram_i8<true, 5><<<g.ntiles, i8::NT, 0, s>>>(g);
+    else i8::k_gram_i8<false, 5><<<g.ntiles, i8::NT, 0, s>>>(g);
+  } else {
+    if (g.mmap) i8::k_gram_i8<true, kOzSlices><<<g.ntiles, i8::NT, 0, s>>>(g);
+    else i8::k_gram_i8<false, kOzSlices><<<g.ntiles, i8::NT, 0, s>>>(g);
+  }
   return hipGetLastError();
 }
 

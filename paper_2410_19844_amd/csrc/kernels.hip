@@ -865,13 +865,13 @@ hipError_t launch_gram_det(const sos_plan_s* p, const double* d_p, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_gram(const sos_plan_s* p, int mode, hipStream_t s, bool unmerged) {
+hipError_t launch_gram(const sos_plan_s* p, int mode, hipStream_t s, bool unmerged, int oz_slices) {
   const char* ws = p->ws;
   if (p->prec == SOS_FP64) return gram_launch<MF64>(p, ws + p->lay.a_hi, nullptr, s);
   // FP32 padded row-major copy of W: a_hi in FP32 plans, a_f32 in split plans
   const void* w32 = (p->prec == SOS_FP32) ? ws + p->lay.a_hi : ws + p->lay.a_f32;
   if (mode == kFwdExact) return launch_gram_x64(p, s);
-  if (mode == kFwdOzaki) return launch_gram_i8(p, s);
+  if (mode == kFwdOzaki) return launch_gram_i8(p, s, oz_slices);
   if (mode == kFwdF32 || p->prec == SOS_FP32) return gram_launch<MF32>(p, w32, nullptr, s);
   return launch_gram_bf3(p, s, false, unmerged);
 }

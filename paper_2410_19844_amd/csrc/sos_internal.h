@@ -404,7 +404,8 @@ hipError_t launch_init_r(const sos_plan_s* p, const double* d_p, hipStream_t s);
 hipError_t launch_sumsq(const sos_plan_s* p, const double* x, int64_t M, double* out, hipStream_t s,
                         float* x32 = nullptr);
 enum { kFwdFast = 0, kFwdF32 = 1, kFwdExact = 2, kFwdOzaki = 3 };
-hipError_t launch_gram(const sos_plan_s* p, int mode, hipStream_t s, bool unmerged = false);
+// oz_slices: digit slices of the Ozaki forward (kOzSlices, or 5 with SOS_FLAG_OZAKI_FIVE_SLICES)
+hipError_t launch_gram(const sos_plan_s* p, int mode, hipStream_t s, bool unmerged = false, int oz_slices = kOzSlices);
 // deterministic forward (FP32 and FP64 plans with pair lists): the generic
 // gram stores its slices, then each coefficient sums its pairs in a fixed order
 hipError_t launch_gram_det(const sos_plan_s* p, const double* d_p, hipStream_t s);
@@ -430,9 +431,10 @@ hipError_t launch_scatter_tiles(const sos_plan_s* p, hipStream_t s);
 // the merge maps of a split plan's gram epilogue (into lay.mg_*; reads the ranking tables and the tile list)
 hipError_t launch_merge_maps(const sos_plan_s* p, hipStream_t s);
 hipError_t launch_gram_x64(const sos_plan_s* p, hipStream_t s);
-// Ozaki-split forward (gemm_i8.hip): row exponents and int8 slices of W, then the gram
-hipError_t launch_oz_slices(const sos_plan_s* p, const float* W, hipStream_t s);
-hipError_t launch_gram_i8(const sos_plan_s* p, hipStream_t s);
+// Ozaki-split forward (gemm_i8.hip): row exponents and the first `slices`
+// int8 slices of W (kOzSlices or 5), then the gram on as many
+hipError_t launch_oz_slices(const sos_plan_s* p, const float* W, hipStream_t s, int slices);
+hipError_t launch_gram_i8(const sos_plan_s* p, hipStream_t s, int slices);
 inline bool ozaki_supported(const sos_plan_s* p) { return p->prec != SOS_FP64 && p->Kp <= kOzMaxK; }
 hipError_t launch_rw_bf3(const sos_plan_s* p, void* g, bool split, hipStream_t s);
 hipError_t launch_adam(const sos_plan_s* p, void* W, void* m, void* v, const void* g, int64_t t,

@@ -28,6 +28,15 @@ def test_library_exports_every_header_function():
     assert set(S.EXPORTS) == set(names)
 
 
+def test_binding_flag_values_match_the_header():
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    flags = dict(re.findall(r"SOS_(FLAG_\w+)\s*=\s*(\d+)", text))
+    assert len(flags) >= 9
+    for name, value in flags.items():
+        assert getattr(S, name) == int(value), name
+    assert len(set(flags.values())) == len(flags)  # distinct bits
+
+
 @pytest.mark.parametrize("n,d", [(1, 1), (1, 7), (2, 2), (3, 2), (4, 3), (6, 3), (6, 4), (16, 1), (2, 7)])
 def test_exponents_match_oracle(n, d):
     pl = S.Plan(n, d, 3, "fp32", device="cpu")

@@ -17,6 +17,12 @@ numpy's frexp on the host, independently of the library.  The digit errors
 are independent and of both signs, so the actual error is far inside this
 worst case: the tests also hold it to 1e-10 of cabs, the bar of the FP64
 path.
+
+Five slices (SOS_FLAG_OZAKI_FIVE_SLICES, S = 5) keep the levels s + t < 5:
+the same bound with S = 5, about 128 times the six-slice one, and a
+statistical bar of 2e-9 of cabs (a CPU emulation of the split puts the
+largest error on these shapes at 2.3e-10 of cabs; dropping one more level
+would give ~4e-8).
 """
 import math
 from math import comb
@@ -33,7 +39,7 @@ S = pytest.importorskip("paper_2410_19844_amd")
 pytestmark = pytest.mark.gpu
 
 U32 = 2.0 ** -24
-SLICES = 6
+BAR = {6: 1e-10, 5: 2e-9}  # statistical bars (of cabs) per slice count
 
 
 def gamma(n):
@@ -47,10 +53,10 @@ def row_scales(W64):
     return np.ldexp(1.0, e)
 
 
-def ozaki_bound(W64, p, n, d, pr):
+def ozaki_bound(W64, p, n, d, pr, slices=6):
     k = W64.shape[1]
     s = row_scales(W64)[:, None]
-    worst = (SLICES + 1.05) * 2.0 ** (-7 * SLICES) * k * O.coefficients(s, n, d, pr)
+    worst = (slices + 1.05) * 2.0 ** (-7 * slices) * k * O.coefficients(s, n, d, pr)
     return worst + 1e-13 * (O.coefficients_abs(W64, n, d, pr) + np.abs(p))
 
 
@@ -66,24 +72,25 @@ def make(n, d, k, seed, row_exp=None):
 CASES = [(3, 2, 20), (4, 3, 37), (6, 3, 168), (6, 4, 420), (10, 5, 300), (17, 2, 40), (40, 2, 130)]
 
 
+@pytest.mark.parametrize("slices", [6, 5])
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("n,d,k", CASES)
-def test_ozaki_forward_matches_oracle(prec, n, d, k):
+def test_ozaki_forward_matches_oracle(prec, n, d, k, slices):
     W, p = make(n, d, k, seed=n * 10 + d)
     Wd = torch.tensor(W, dtype=torch.float32, device="cuda")
     W64 = Wd.double().cpu().numpy()
     pd = torch.tensor(p, dtype=torch.float64, device="cuda")
     pl = S.Plan(n, d, k, prec)
-    loss, g, r = pl.loss_grad(Wd, pd, grad=True, want_r=True, ozaki=True)
+    loss, g, r = pl.loss_grad(Wd, pd, grad=True, want_r=True, ozaki=slices)
     torch.cuda.synchronize()
     pr = O.pair_ranks(n, d)
     L_o, g_o, r_o = O.loss_grad(W64, p, n, d, pr)
     cabs = O.coefficients_abs(W64, n, d, pr)
-    dc = ozaki_bound(W64, p, n, d, pr)
+    dc = ozaki_bound(W64, p, n, d, pr, slices)
     got = r.cpu().numpy() + p
     err = np.abs(got - (r_o + p))
     assert np.max(err / (dc + 1e-300)) <= 1.0
-    assert np.max(err / (1e-10 * cabs + 1e-300)) <= 1.0
+    assert np.max(err / (BAR[slices] * cabs + 1e-300)) <= 1.0
     dL = 2.0 * np.sum(np.abs(r_o) * dc) + np.sum(dc * dc)
     assert abs(loss.item() - L_o) <= dL + 1e-13 * L_o
     # the plan's own backward on the Ozaki residual
@@ -115,6 +122,27 @@ def test_ozaki_rows_of_very_different_scales(prec):
     assert np.max(err / (dc + 1e-300)) <= 1.0
 
 
+@pytest.mark.parametrize("n,d,k", [(6, 4, 420), (40, 2, 130)])
+def test_five_slices_are_five(n, d, k):
+    """The five-slice forward really drops the sixth digit: its error is
+    well above the six-slice one (an emulation gives ~50-130x in norm), and
+    both stay inside their bounds."""
+    W, p = make(n, d, k, seed=n * 10 + d)
+    Wd = torch.tensor(W, dtype=torch.float32, device="cuda")
+    W64 = Wd.double().cpu().numpy()
+    pd = torch.tensor(p, dtype=torch.float64, device="cuda")
+    pl = S.Plan(n, d, k, "bf16x3")
+    pr = O.pair_ranks(n, d)
+    r_o = O.residual(W64, p, n, d, pr)
+    e = {}
+    for sl in (5, 6):
+        _, _, r = pl.loss_grad(Wd, pd, grad=False, want_r=True, ozaki=sl)
+        err = r.cpu().numpy() - r_o
+        assert np.all(np.abs(err) <= ozaki_bound(W64, p, n, d, pr, sl)), sl
+        e[sl] = np.linalg.norm(err)
+    assert e[5] >= 10.0 * e[6], e
+
+
 def test_ozaki_forward_agrees_with_exact_forward_at_a_fit():
     """Near a fit (W from p's own factor) the residual is ~1e3 times smaller
     than the coefficients; both FP64-accurate forwards must see the same
@@ -141,10 +169,11 @@ def test_ozaki_forward_agrees_with_exact_forward_at_a_fit():
     assert np.all(np.abs(r_oz.cpu().numpy()) <= dc)
 
 
-def test_ozaki_finisher_solve_certified_by_the_oracle():
-    """The ladder with the Ozaki forward in its exact phase reaches an
-    FP64-verified 1e-8 (the certificate is the FP64-MFMA forward), and the
-    oracle agrees on the returned W."""
+@pytest.mark.parametrize("finisher", ["ozaki", "ozaki5"])
+def test_ozaki_finisher_solve_certified_by_the_oracle(finisher):
+    """The ladder with the Ozaki forward (six or five slices) in its exact
+    phase reaches an FP64-verified 1e-8 (the certificate is the FP64-MFMA
+    forward), and the oracle agrees on the returned W."""
     n, d = 6, 4
     N = comb(n + d, d)
     k = 2 * N
@@ -154,7 +183,7 @@ def test_ozaki_finisher_solve_certified_by_the_oracle():
     Wd = torch.tensor(gaussian((N, k), 1, 1 / math.sqrt(k)), dtype=torch.float32, device="cuda")
     res = pl.solve(Wd, torch.tensor(p, dtype=torch.float64, device="cuda"), S.Adam(lr=3e-3), tol=1e-8,
                    max_steps=20000, check_every=10, ladder=True, stall_checks=6, stall_ratio=0.8,
-                   switch_rel=3e-6, lr_exact=1e-3, rollback_ratio=10.0, single_backward=True, finisher="ozaki")
+                   switch_rel=3e-6, lr_exact=1e-3, rollback_ratio=10.0, single_backward=True, finisher=finisher)
     assert res["status"] == S.OK and res["phase"] == 2 and res["exact_steps"] > 0, res
     W64 = Wd.double().cpu().numpy()
     rel_o = float(np.linalg.norm(O.residual(W64, p, n, d, pr)) / np.linalg.norm(p))
@@ -196,3 +225,13 @@ def test_ozaki_nonfinite_and_errors():
     with pytest.raises(S.SosError) as e:
         p64.loss_grad(Wd.double(), pd, grad=False, ozaki=True)
     assert e.value.code == S.EINVAL
+    # five slices is a modifier of the Ozaki forward only
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    rc = S._lib.sos_loss_grad(pl._h, S._ptr(Wd), S._ptr(pd), S._ptr(loss), S._ptr(None), S._ptr(None),
+                              S.FLAG_OZAKI_FIVE_SLICES, S._stream())
+    assert rc == S.EINVAL
+    with pytest.raises(S.SosError) as e:
+        pl.step(Wd, pl.new_state(), 1, pd, S.Adam(lr=1e-3), flags=S.FLAG_OZAKI_FIVE_SLICES)
+    assert e.value.code == S.EINVAL
+    with pytest.raises(ValueError):
+        pl.loss_grad(Wd, pd, grad=False, ozaki=4)
