@@ -244,10 +244,12 @@ __device__ __forceinline__ void pipe_step(Frag& cur, Frag& nxt, char* ring, cons
 
 // The same step in the steady state (kt + 4 < nk), ordered differently: the
 // barrier comes first (stage kt+1 has landed, and every wave is done reading
-// the buffer of stage kt, whose fragments are in registers), then the refill
-// of that buffer with stage kt+4, then the MFMAs of stage kt with the
-// fragment reads of stage kt+1 interleaved among them, so that the reads
-// have the whole stage's MFMA time to complete.  No branches.
+// the buffer of stage kt, whose fragments are in registers), then the MFMAs
+// of stage kt with the fragment reads of stage kt+1 interleaved among them,
+// so that the reads have the whole stage's MFMA time to complete, and last
+// the refill of stage kt's buffer with stage kt+4 (issued after the MFMAs
+// rather than before them: 1-2% faster here, 7% in the int8 gram).  No
+// branches.
 template <bool SPLIT, bool F16>
 __device__ __forceinline__ void pipe_step_steady(Frag& cur, Frag& nxt, char* ring, const RingAddr& ra, const Operands& o,
                                                  int64_t kt,
@@ -258,7 +260,6 @@ __device__ __forceinline__ void pipe_step_steady(Frag& cur, Frag& nxt, char* rin
   constexpr int NREAD = 2 * (BI + BJ);
   constexpr int RATIO = NMFMA / NREAD;
   wait_vm_barrier<2 * per>();
-  issue_stage<SPLIT>(ra, (int)(kt % NSTAGE), o, arow0, brow0, (kt + NSTAGE) * kstage<SPLIT>());
   __builtin_amdgcn_sched_barrier(0);
   load_frag<SPLIT>(nxt, ring + ((kt + 1) % NSTAGE) * STAGE, wm, wn);
   mma_rows<SPLIT, F16, 0, BI>(cur, acc);
@@ -269,6 +270,8 @@ __device__ __forceinline__ void pipe_step_steady(Frag& cur, Frag& nxt, char* rin
     __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
   }
   __builtin_amdgcn_sched_group_barrier(0x008, NMFMA - RATIO * NREAD, 0);
+  __builtin_amdgcn_sched_barrier(0);
+  issue_stage<SPLIT>(ra, (int)(kt % NSTAGE), o, arow0, brow0, (kt + NSTAGE) * kstage<SPLIT>());
   __builtin_amdgcn_sched_barrier(0);
 }
 

