@@ -1,11 +1,10 @@
 """Per-kernel resources of the built library (the compiler's report, kept by
 the build in _build/kernel_resources.tsv).
 
-Scratch memory per lane must be zero everywhere except a few epilogues that
-spill one 16-register block of accumulators once per tile (outside the
-MFMA loop).  A private array that the compiler cannot keep in registers
-(dynamically indexed accumulators, a per-thread list) lands in scratch and
-slows a kernel several times; this test catches that at build time.
+Scratch memory per lane must be zero in every kernel.  A private array that
+the compiler cannot keep in registers (dynamically indexed accumulators, a
+per-thread list) lands in scratch and slows a kernel several times; this
+test catches that at build time.
 """
 import csv
 import os
@@ -14,13 +13,8 @@ import pytest
 
 RES = os.path.join(os.path.dirname(__file__), "..", "paper_2410_19844_amd", "_build", "kernel_resources.tsv")
 
-# kernel name fragment -> largest scratch allowed (bytes per lane)
-EPILOGUE_SPILLS = {
-    "k_gram_bf3": 128,     # accumulators of the second row half, kept across the first half's scatter
-    "k_rw_bf3": 128,       # the same in the unfused R W epilogue
-    "k_rw_adam_bf3": 64,   # a few W / m / v addresses in the Adam epilogue (two waves per SIMD leave
-                           # 256 registers per wave)
-}
+# kernel name fragment -> largest scratch allowed (bytes per lane); none at present
+EPILOGUE_SPILLS = {}
 
 HOT = ["k_gram_bf3", "k_rw_adam_bf3", "k_gram_x64", "k_gather_sym", "k_gramINS_4MF32", "k_gramINS_4MF64",
        "k_b_gram", "k_b_coeff", "k_b_rw", "k_b_adam", "k_prep", "k_sumsq"]
