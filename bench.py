@@ -49,6 +49,10 @@ SPLIT = ("bf16x3", "fp16x3")   # split 16-bit operand plans
 # when the rounding order of the forward's sums changes; at 3e-3 it swings
 # between about 500 and 2200 steps.
 LR_DEFAULTS = {"n12d6": (3e-3, 1e-3), "q100": (3e-3, 2e-3)}
+# Split-plan ladders start with the single-product forward until rel <= this
+# (chosen by a sweep of time to 1e-8 at n=12, d=6: 1e-2, 3e-3 and 2e-3 keep
+# the 340 steps, 1e-3 takes 350; 3e-3 leaves a factor 3).
+SINGLE_REL_DEFAULTS = {"n12d6": 3e-3}
 DTYPE = {"bf16x3": "bf16", "fp16x3": "fp16", "fp32": "fp32", "fp64": "fp64"}
 
 
@@ -70,6 +74,10 @@ def parse():
                     help="step: one FP64 atomic per Gram entry, without the plan's merge maps (measures them)")
     ap.add_argument("--deterministic", action="store_true",
                     help="step: FP32/FP64 plans, the forward sums each coefficient in a fixed order (no atomics)")
+    ap.add_argument("--single-forward", action="store_true",
+                    help="step: split plans, the gram takes one product (hi hi^T) instead of three")
+    ap.add_argument("--single-rel", type=float, default=None,
+                    help="ttt: split plans start with the single-product forward until rel <= this (0: off)")
     ap.add_argument("--finisher", choices=("fp64", "ozaki", "ozaki5"), default=None,
                     help="ttt: forward of the exact phase (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -300,6 +308,8 @@ def ttt_run(S, torch, a, c, W_host, p, precision, single_backward, finisher=None
     lr_exact = a.lr_exact if a.lr_exact is not None else lr_fin
     switch_rel = a.switch_rel if a.switch_rel is not None else {"bf16x3": 3e-6, "fp16x3": 3e-6, "fp32": 1e-6, "fp64": 0.0}[precision]
     mid_rel = a.mid_rel if a.mid_rel is not None else 0.0
+    single_rel = ((a.single_rel if a.single_rel is not None else SINGLE_REL_DEFAULTS.get(c.name, 0.0))
+                  if precision in SPLIT else 0.0)
     pl = S.Plan(c.n, c.d, c.rank, precision)
     wdt = torch.float64 if precision == "fp64" else torch.float32
     W = torch.tensor(W_host, dtype=wdt, device="cuda")
@@ -308,13 +318,13 @@ def ttt_run(S, torch, a, c, W_host, p, precision, single_backward, finisher=None
     res = pl.solve(W, p, S.Adam(lr=lr), tol=a.tol, max_steps=a.max_steps, check_every=10, ladder=True,
                    stall_checks=6, stall_ratio=0.8, switch_rel=switch_rel, lr_exact=lr_exact,
                    rollback_ratio=10.0, single_backward=single_backward, mid_rel=mid_rel,
-                   finisher=finisher if precision != "fp64" else "fp64")
+                   finisher=finisher if precision != "fp64" else "fp64", single_rel=single_rel)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     del pl, W
     torch.cuda.empty_cache()
     return dict(res, seconds=dt, precision=precision, lr=lr, lr_exact=lr_exact, switch_rel=switch_rel,
-                mid_rel=mid_rel, single_backward=single_backward, tol=a.tol, finisher=finisher,
+                mid_rel=mid_rel, single_rel=single_rel, single_backward=single_backward, tol=a.tol, finisher=finisher,
                 certified=res["status"] == S.OK)
 
 
@@ -449,6 +459,7 @@ def main():
     stream = torch.cuda.current_stream()
     flags = ((S.FLAG_EXACT_FORWARD if a.exact else 0) | (S.FLAG_OZAKI_FORWARD if a.ozaki else 0)
              | (S.FLAG_OZAKI_FIVE_SLICES if a.ozaki and a.ozaki_slices == 5 else 0)
+             | (S.FLAG_SINGLE_FORWARD if a.single_forward else 0)
              | (S.FLAG_SINGLE_BACKWARD if a.single_backward else 0)
              | (S.FLAG_UNFUSED_SCATTER if a.unfused_scatter else 0)
              | (S.FLAG_DETERMINISTIC if a.deterministic else 0)
@@ -491,7 +502,7 @@ def main():
     achieved = flops[dom] / (per_launch[dom] * 1e-3) / 1e12
     traffic = None
     if (c.name == "n12d6" and a.precision == "bf16x3" and a.single_backward
-            and not (a.ozaki or a.unfused_scatter or a.unmerged_scatter)):
+            and not (a.ozaki or a.unfused_scatter or a.unmerged_scatter or a.single_forward)):
         key = {("gram", False): "step:k_gram_bf3", ("gram", True): "exact:k_gram_x64",
                ("rw", False): "step:k_rw_adam_bf3", ("rw", True): "step:k_rw_adam_bf3"}[(dom, a.exact)]
         traffic = measured_traffic(key)
@@ -517,6 +528,7 @@ def main():
                      "algorithmic_flops": flops[dom], "avg_ms": per_launch[dom],
                      "executed_mfma_factor": ((a.ozaki_slices * (a.ozaki_slices + 1) // 2)
                                               if (a.ozaki and not a.exact and dom == "gram") else
+                                              1 if (a.single_forward and dom == "gram" and not a.exact) else
                                               (1 if (dom == "rw" and a.single_backward) else 3)
                                               if (a.precision in SPLIT and not (a.exact and dom == "gram"))
                                               else 1)},
@@ -563,7 +575,8 @@ def main():
     torch.cuda.empty_cache()
     if not a.no_ttt:
         out["ttt"] = {}
-        # mixed: split-bf16 bulk, then the Ozaki forward on five int8 slices (the fastest finisher);
+        # mixed: split-bf16 bulk (its first part with the single-product forward, the workload's
+        # single_rel), then the Ozaki forward on five int8 slices (the fastest finisher);
         # mixed_ozaki6_finisher: six slices (the FP64-level Ozaki forward); mixed_fp64_finisher: the
         # FP64-MFMA finisher; fp32: the plain FP32 form (FP32 MFMA for both contractions, FP64-MFMA
         # finisher).  Every result is certified by the FP64-MFMA forward.
@@ -572,7 +585,7 @@ def main():
             r = ttt_run(S, torch, a, c, W_start, p, prec, single, fin)
             out["ttt"][name] = {q: r[q] for q in ("seconds", "steps", "exact_steps", "rel", "best_rel", "certified",
                                                   "precision", "lr", "lr_exact", "switch_rel", "single_backward",
-                                                  "tol", "finisher")}
+                                                  "tol", "finisher", "single_rel")}
             print(f"ttt {name}: {r['seconds']:.2f} s, {r['steps']} steps ({r['exact_steps']} exact), "
                   f"rel {r['rel']:.3g}", file=sys.stderr, flush=True)
         m, f = out["ttt"]["mixed"], out["ttt"]["fp32"]

@@ -150,6 +150,16 @@ enum sos_flags {
    * residual targets such as 1e-8, so it serves as a finisher's forward
    * (sos_solve's finisher 2).  SOS_EINVAL without SOS_FLAG_OZAKI_FORWARD. */
   SOS_FLAG_OZAKI_FIVE_SLICES = 256,
+  /* SOS_BF16X3 and SOS_FP16X3 plans, fast forward: the gram takes one
+   * 16-bit product per element pair (hi * hi) instead of three.  Each
+   * coefficient is then off by at most about 2^-7 (bf16) or 2^-10 (fp16)
+   * of coeff(|W||W|^T), the gram costs about a third, and the answer is that
+   * of the rounded W; for the first phase of a solve, while the residual is
+   * far above that level (sos_solve's single_rel).  SOS_FLAG_EXACT_FORWARD,
+   * SOS_FLAG_OZAKI_FORWARD and SOS_FLAG_FP32_FORWARD take precedence;
+   * SOS_EINVAL on other plans or with SOS_FLAG_UNFUSED_SCATTER,
+   * SOS_FLAG_UNMERGED_SCATTER or SOS_FLAG_DETERMINISTIC.                 */
+  SOS_FLAG_SINGLE_FORWARD = 512,
 };
 
 /* Adam hyper-parameters (Kingma and Ba; the paper's optimiser, Section 3). */
@@ -196,6 +206,11 @@ typedef struct {
   int32_t step_flags;    /* SOS_FLAG_DETERMINISTIC or 0: added to the steps
                             of the plan's own forward                       */
   int32_t reserved;
+  double single_rel;     /* SOS_BF16X3 / SOS_FP16X3 ladder: the fast phase
+                            starts with SOS_FLAG_SINGLE_FORWARD and goes on
+                            to the three-product forward once rel <=
+                            single_rel (or on a stall); same Adam state and
+                            step size (0: three products from the start)    */
 } sos_solve_opts_t;
 
 typedef struct {

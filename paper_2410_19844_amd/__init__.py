@@ -29,6 +29,7 @@ FLAG_DETERMINISTIC = 32
 FLAG_UNFUSED_SCATTER = 64
 FLAG_UNMERGED_SCATTER = 128
 FLAG_OZAKI_FIVE_SLICES = 256
+FLAG_SINGLE_FORWARD = 512
 OK, NOT_CONVERGED = 0, 1
 EINVAL, ERANGE, ENOMEM, EHIP, ENUMERIC = -1, -2, -3, -4, -5
 
@@ -51,7 +52,8 @@ class _SolveOpts(ctypes.Structure):
                 ("switch_rel", ctypes.c_double), ("lr_exact", ctypes.c_double),
                 ("rollback_ratio", ctypes.c_double), ("single_backward", ctypes.c_int32),
                 ("finisher", ctypes.c_int32), ("mid_rel", ctypes.c_double),
-                ("step_flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("step_flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("single_rel", ctypes.c_double)]
 
 
 class _Result(ctypes.Structure):
@@ -215,7 +217,7 @@ class Plan:
 
     def loss_grad(self, W, p, grad=True, want_r=False, exact=False, single_backward=False,
                   fp32_forward=False, ozaki=False, deterministic=False, unfused_scatter=False,
-                  unmerged_scatter=False, stream=None):
+                  unmerged_scatter=False, single_forward=False, stream=None):
         self._w(W), self._p(p)
         loss = torch.empty(1, dtype=torch.float64, device=self.device)
         g = torch.empty_like(W) if grad else None
@@ -227,7 +229,8 @@ class Plan:
                                   _oz_flags(ozaki) |
                                   (FLAG_DETERMINISTIC if deterministic else 0) |
                                   (FLAG_UNFUSED_SCATTER if unfused_scatter else 0) |
-                                  (FLAG_UNMERGED_SCATTER if unmerged_scatter else 0), _stream(stream)))
+                                  (FLAG_UNMERGED_SCATTER if unmerged_scatter else 0) |
+                                  (FLAG_SINGLE_FORWARD if single_forward else 0), _stream(stream)))
         return loss, g, r
 
     def loss_grad_noalloc(self, W, p, loss, g=None, r=None, exact=False, single_backward=False,
@@ -272,16 +275,17 @@ class Plan:
     def solve(self, W, p, adam: Adam, tol=1e-8, max_steps=10000, check_every=50, ladder=True,
               stall_checks=4, stall_ratio=0.7, switch_rel=0.0, lr_exact=0.0, rollback_ratio=0.0,
               single_backward=False, mid_rel=0.0, finisher="fp64", deterministic=False, state=None,
-              stream=None):
+              single_rel=0.0, stream=None):
         """sos_solve: Adam to an FP64-verified ||r||/||p|| <= tol; W ends as the best iterate.
         finisher: forward of the exact phase, "fp64" (FP64 MFMA), "ozaki" (six int8 slices) or
-        "ozaki5" (five int8 slices)."""
+        "ozaki5" (five int8 slices).  single_rel: split plans start with the single-product
+        forward until rel <= single_rel (0: off)."""
         self._w(W), self._p(p)
         state = self.new_state() if state is None else state
         fin = {"fp64": 0, "ozaki": 1, "ozaki5": 2}[finisher]
         opts = _SolveOpts(tol, max_steps, check_every, 1 if ladder else 0, stall_checks, stall_ratio,
                           switch_rel, lr_exact, rollback_ratio, 1 if single_backward else 0, fin, mid_rel,
-                          FLAG_DETERMINISTIC if deterministic else 0, 0)
+                          FLAG_DETERMINISTIC if deterministic else 0, 0, single_rel)
         res = _Result()
         _check(_lib.sos_solve(self._h, _ptr(W), _ptr(state), _ptr(p), ctypes.byref(adam.c()),
                               ctypes.byref(opts), ctypes.byref(res), _stream(stream)),

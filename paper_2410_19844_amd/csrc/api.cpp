@@ -88,6 +88,7 @@ static int fwd_mode(const sos_plan_s* p, int flags) {
   if (flags & SOS_FLAG_EXACT_FORWARD) return kFwdExact;
   if (flags & SOS_FLAG_OZAKI_FORWARD) return kFwdOzaki;
   if ((flags & SOS_FLAG_FP32_FORWARD) && split_plan(p)) return kFwdF32;
+  if ((flags & SOS_FLAG_SINGLE_FORWARD) && split_plan(p)) return kFwdSingle;
   return kFwdFast;
 }
 
@@ -102,7 +103,7 @@ static int run_forward(sos_plan_s* p, const void* W, const double* d_p, int flag
   const int mode = fwd_mode(p, flags);
   if (!reuse) {
     PrepNeeds need;
-    need.a = p->prec == SOS_FP64 || mode == kFwdFast;
+    need.a = p->prec == SOS_FP64 || mode == kFwdFast || mode == kFwdSingle;
     need.a_f32 = mode == kFwdF32;
     need.x_f32 = mode == kFwdExact;
     need.t = grad;
@@ -142,7 +143,8 @@ static int run_step(sos_plan_s* p, void* W, void* state, int64_t t, const double
                     const sos_adam_t& h, double* d_loss, int flags, hipStream_t s) {
   const int mode = fwd_mode(p, flags);
   const bool single = (flags & SOS_FLAG_SINGLE_BACKWARD) != 0;
-  const bool fuse = split_plan(p) && single && (mode == kFwdFast || mode == kFwdExact || mode == kFwdOzaki);
+  const bool fuse = split_plan(p) && single &&
+                    (mode == kFwdFast || mode == kFwdSingle || mode == kFwdExact || mode == kFwdOzaki);
   const bool reuse = fuse && (flags & SOS_FLAG_COPIES_VALID) && p->copies_valid && p->copies_W == W &&
                      p->copies_mode == mode;
   int rc = run_forward(p, W, d_p, flags, d_loss, true, s, reuse);
@@ -190,6 +192,17 @@ static int check_unmerged(const sos_plan_s* p, int flags, const char* fn) {
   if (!(flags & SOS_FLAG_UNMERGED_SCATTER)) return SOS_OK;
   if (!split_plan(p) || fwd_mode(p, flags) != kFwdFast || (flags & SOS_FLAG_UNFUSED_SCATTER))
     return set_error(SOS_EINVAL, std::string(fn) + ": SOS_FLAG_UNMERGED_SCATTER needs a split plan's fused fast forward");
+  return SOS_OK;
+}
+
+// The single-product forward is a variant of the split plans' fused fast forward.
+static int check_single(const sos_plan_s* p, int flags, const char* fn) {
+  if (!(flags & SOS_FLAG_SINGLE_FORWARD)) return SOS_OK;
+  if (!split_plan(p))
+    return set_error(SOS_EINVAL, std::string(fn) + ": SOS_FLAG_SINGLE_FORWARD needs a SOS_BF16X3 or SOS_FP16X3 plan");
+  if (flags & (SOS_FLAG_UNFUSED_SCATTER | SOS_FLAG_UNMERGED_SCATTER | SOS_FLAG_DETERMINISTIC))
+    return set_error(SOS_EINVAL, std::string(fn) + ": SOS_FLAG_SINGLE_FORWARD does not combine with the "
+                                                   "measurement variants of the scatter");
   return SOS_OK;
 }
 
@@ -358,8 +371,9 @@ int sos_loss_grad(sos_plan_t p, const void* d_W, const double* d_p, double* d_lo
   if (!d_W || !d_p || !d_loss) return set_error(SOS_EINVAL, "sos_loss_grad: d_W, d_p and d_loss are required");
   if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_SINGLE_BACKWARD | SOS_FLAG_FP32_FORWARD |
                      SOS_FLAG_OZAKI_FORWARD | SOS_FLAG_DETERMINISTIC | SOS_FLAG_UNFUSED_SCATTER |
-                     SOS_FLAG_UNMERGED_SCATTER | SOS_FLAG_OZAKI_FIVE_SLICES))
+                     SOS_FLAG_UNMERGED_SCATTER | SOS_FLAG_OZAKI_FIVE_SLICES | SOS_FLAG_SINGLE_FORWARD))
     return set_error(SOS_EINVAL, "sos_loss_grad: unknown flags");
+  if (int rc = check_single(p, flags, "sos_loss_grad")) return rc;
   if (int rc = check_unmerged(p, flags, "sos_loss_grad")) return rc;
   if (int rc = check_ozaki(p, flags, "sos_loss_grad")) return rc;
   if (int rc = check_unfused(p, flags, "sos_loss_grad")) return rc;
@@ -381,8 +395,10 @@ int sos_step(sos_plan_t p, void* d_W, void* d_state, int64_t t, const double* d_
   if (t < 1) return set_error(SOS_EINVAL, "sos_step: t is 1-based");
   if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_COPIES_VALID | SOS_FLAG_SINGLE_BACKWARD |
                      SOS_FLAG_FP32_FORWARD | SOS_FLAG_OZAKI_FORWARD | SOS_FLAG_DETERMINISTIC |
-                     SOS_FLAG_UNFUSED_SCATTER | SOS_FLAG_UNMERGED_SCATTER | SOS_FLAG_OZAKI_FIVE_SLICES))
+                     SOS_FLAG_UNFUSED_SCATTER | SOS_FLAG_UNMERGED_SCATTER | SOS_FLAG_OZAKI_FIVE_SLICES |
+                     SOS_FLAG_SINGLE_FORWARD))
     return set_error(SOS_EINVAL, "sos_step: unknown flags");
+  if (int rc = check_single(p, flags, "sos_step")) return rc;
   if (int rc = check_unmerged(p, flags, "sos_step")) return rc;
   if (int rc = check_ozaki(p, flags, "sos_step")) return rc;
   if (int rc = check_unfused(p, flags, "sos_step")) return rc;
@@ -512,9 +528,9 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
   if (int rc = check_adam(adam, "sos_solve")) return rc;
   if (!d_W || !d_state || !d_p || !o || !res) return set_error(SOS_EINVAL, "sos_solve: NULL argument");
   if (o->max_steps < 0 || o->check_every < 1 || !(o->tol >= 0) || !(o->lr_exact >= 0) ||
-      !(o->rollback_ratio >= 0) || o->stall_checks < 0)
+      !(o->rollback_ratio >= 0) || o->stall_checks < 0 || !(o->single_rel >= 0))
     return set_error(SOS_EINVAL, "sos_solve: needs max_steps >= 0, check_every >= 1, tol, lr_exact, "
-                                 "rollback_ratio >= 0 and stall_checks >= 0");
+                                 "rollback_ratio, single_rel >= 0 and stall_checks >= 0");
   if (o->finisher < 0 || o->finisher > 2) return set_error(SOS_EINVAL, "sos_solve: finisher must be 0, 1 or 2");
   if (o->step_flags & ~(int)SOS_FLAG_DETERMINISTIC)
     return set_error(SOS_EINVAL, "sos_solve: step_flags may be SOS_FLAG_DETERMINISTIC");
@@ -546,6 +562,8 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
   double last_loss = 0;
   bool done = false;
   const bool has_mid = can_ladder && split_plan(p) && o->mid_rel > 0;
+  // fast start: the first part of phase 0 with the single-product forward
+  bool fast_start = can_ladder && split_plan(p) && o->single_rel > 0;
   auto next_phase = [&]() {
     phase = (phase == 0 && has_mid) ? 1 : 2;
     stall = 0;
@@ -563,7 +581,8 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
     const int exact_flag = o->finisher == 2   ? SOS_FLAG_OZAKI_FORWARD | SOS_FLAG_OZAKI_FIVE_SLICES
                            : o->finisher == 1 ? SOS_FLAG_OZAKI_FORWARD
                                               : SOS_FLAG_EXACT_FORWARD;
-    const int flags = (phase == 2 ? exact_flag : phase == 1 ? SOS_FLAG_FP32_FORWARD : (o->step_flags & SOS_FLAG_DETERMINISTIC)) |
+    const int fast_flags = (o->step_flags & SOS_FLAG_DETERMINISTIC) | (fast_start ? SOS_FLAG_SINGLE_FORWARD : 0);
+    const int flags = (phase == 2 ? exact_flag : phase == 1 ? SOS_FLAG_FP32_FORWARD : fast_flags) |
                       (o->single_backward ? SOS_FLAG_SINGLE_BACKWARD : 0) |
                       (w_moved ? 0 : SOS_FLAG_COPIES_VALID);
     int rc = run_step(p, d_W, st, t_adam, d_p, h, sc + 0, flags, s);
@@ -605,6 +624,17 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
       stall = 0;
     } else {
       ++stall;
+    }
+    if (fast_start) {
+      // on to the three products once the single product's rounding (~2^-7 of
+      // the coefficients' scale) could start to matter, or on a stall; the
+      // Adam state and step size carry over
+      if (rel <= o->single_rel || (o->stall_checks > 0 && stall >= o->stall_checks)) {
+        fast_start = false;
+        stall = 0;
+        best_rel = ref_rel = inf;  // values of the three-product forward from here on
+      }
+      continue;
     }
     const double target = phase == 0 ? o->switch_rel : o->mid_rel;
     bool switch_phase = can_ladder && phase < 2 &&

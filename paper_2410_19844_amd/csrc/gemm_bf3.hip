@@ -448,31 +448,36 @@ __device__ __forceinline__ void gram_merge_epilogue(const GramArgs& g, int v, in
 // of the half, ranks each (row, col) pair and adds it into r.  Copying out
 // with compile-time indices keeps the accumulators in registers; the scatter
 // loop indexes LDS instead.
-template <bool F16>
+// SINGLE: one product hi hi^T (the lo operands of GramArgs point one K block
+// past the hi ones, so a stage carries two K blocks, as in the single-product
+// R W GEMM); otherwise the three products of the split form.
+template <bool F16, bool SINGLE>
 __global__ __launch_bounds__(NT) void k_gram_bf3(GramArgs g) {
   SOS_BF3_BUFFERS;
+  constexpr int64_t KS = kstage<!SINGLE>();  // K per pipeline stage
   // whole tiles first (XCD-aware order); then the tail tiles, `parts`
-  // contiguous K ranges each (whole blocks of every panel: the operands are
-  // the same arrays moved k0 blocks on)
+  // contiguous K ranges each (whole stages of every panel: the operands are
+  // the same arrays moved k0 stages on)
   int v;
-  int64_t k0 = 0, nks = g.K / BK;
+  int64_t k0 = 0, nks = g.K / KS;
   if ((int)blockIdx.x < g.nfull) {
     v = xcd_order(blockIdx.x, g.nfull);
   } else {
     const int u = (int)blockIdx.x - g.nfull, q = u % g.parts;
     v = g.nfull + u / g.parts;
-    const int64_t nk = g.K / BK;
+    const int64_t nk = g.K / KS;
     k0 = nk * q / g.parts;
     nks = nk * (q + 1) / g.parts - k0;
   }
   const int2 t = g.tiles[v];
   Operands o = g.o;
-  o.a_hi += k0 * (TM * BK);
-  o.a_lo += k0 * (TM * BK);
-  o.b_hi += k0 * (TM * BK);
-  o.b_lo += k0 * (TM * BK);
+  const int64_t shift = k0 * (KS / BK) * (TM * BK);
+  o.a_hi += shift;
+  o.a_lo += shift;
+  o.b_hi += shift;
+  o.b_lo += shift;
   f32x16 acc[BI][BJ];
-  tile_gemm<true, F16>(o, nks * BK, (int64_t)t.x * TM, (int64_t)t.y * TM, lds, acc);
+  tile_gemm<!SINGLE, F16>(o, nks * KS, (int64_t)t.x * TM, (int64_t)t.y * TM, lds, acc);
   const double unscale = F16 ? (double)pow2f(-2 * g.sx[0]) : 1.0;  // exact: a power of two
   if (g.mmap) {
     gram_merge_epilogue<F16>(g, v, t, acc, lds, unscale);
@@ -852,15 +857,16 @@ __global__ __launch_bounds__(NT) void k_rw_adam_bf3(RwAdamArgs a) {
 
 // Host side -----------------------------------------------------------------
 
-hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s, bool store, bool unmerged) {
+hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s, bool store, bool unmerged, bool single) {
   bf3::GramArgs g;
   const bool f16 = p->prec == SOS_FP16X3;
   g.sx = scale_exponents(p);
   const char* ws = p->ws;
   g.o.a_hi = g.o.b_hi = (const __bf16*)(ws + p->lay.a_hi);
-  g.o.a_lo = g.o.b_lo = (const __bf16*)(ws + p->lay.a_lo);
+  // single product: the second K block of each stage is the next block of the same panel
+  g.o.a_lo = g.o.b_lo = single ? g.o.a_hi + bf3::TM * bf3::BK : (const __bf16*)(ws + p->lay.a_lo);
   g.o.pstride = panel_stride(p->Kp / kBlkK, 2);
-  g.K = p->Kp;
+  g.K = p->Kp;  // a multiple of 64: whole stages in both forms
   g.tiles = (const int2*)(ws + p->lay.tiles);
   g.ntiles = p->ntiles256;
   g.N = (int)p->N;
@@ -868,7 +874,7 @@ hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s, bool store, bool 
   g.r = (double*)(ws + p->lay.r);
   g.G = store ? (float*)(ws + p->lay.g) : nullptr;
   // the stored tiles of the unfused variant are whole: no tail split there
-  const TailSplit ts = store ? TailSplit{g.ntiles, 1} : gram_tail_split(g.ntiles, g.K / bf3::BK, s);
+  const TailSplit ts = store ? TailSplit{g.ntiles, 1} : gram_tail_split(g.ntiles, g.K / (single ? 2 * bf3::BK : bf3::BK), s);
   g.nfull = ts.nfull;
   g.parts = ts.parts;
   const int grid = ts.nfull + (g.ntiles - ts.nfull) * ts.parts;
@@ -876,8 +882,13 @@ hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s, bool store, bool 
   g.mmap = merge ? (const uint16_t*)(ws + p->lay.mg_map) : nullptr;
   g.mrank = merge ? (const int*)(ws + p->lay.mg_rank) : nullptr;
   g.mcount = merge ? (const int*)(ws + p->lay.mg_count) : nullptr;
-  if (f16) bf3::k_gram_bf3<true><<<grid, bf3::NT, 0, s>>>(g);
-  else bf3::k_gram_bf3<false><<<grid, bf3::NT, 0, s>>>(g);
+  if (single) {
+    if (f16) bf3::k_gram_bf3<true, true><<<grid, bf3::NT, 0, s>>>(g);
+    else bf3::k_gram_bf3<false, true><<<grid, bf3::NT, 0, s>>>(g);
+  } else {
+    if (f16) bf3::k_gram_bf3<true, false><<<grid, bf3::NT, 0, s>>>(g);
+    else bf3::k_gram_bf3<false, false><<<grid, bf3::NT, 0, s>>>(g);
+  }
   return hipGetLastError();
 }
 
@@ -992,8 +1003,9 @@ hipError_t launch_rw_adam_bf3(const sos_plan_s* p, void* W, void* m, void* v, in
   a.eps = (float)h.eps;
   a.bc1 = (float)(1.0 - pow(h.beta1, (double)t));
   a.bc2 = (float)(1.0 - pow(h.beta2, (double)t));
-  a.a_hi = next_mode == kFwdFast ? (__bf16*)(ws + p->lay.a_hi) : nullptr;
-  a.a_lo = next_mode == kFwdFast ? (__bf16*)(ws + p->lay.a_lo) : nullptr;
+  const bool split_copies = next_mode == kFwdFast || next_mode == kFwdSingle;
+  a.a_hi = split_copies ? (__bf16*)(ws + p->lay.a_hi) : nullptr;
+  a.a_lo = split_copies ? (__bf16*)(ws + p->lay.a_lo) : nullptr;
   a.x_f32 = next_mode == kFwdExact ? (float*)(ws + p->lay.x_f32) : nullptr;
   a.t_next = (__bf16*)(ws + t_write);
   a.aps = panel_stride(p->Kp / kBlkK, 2);

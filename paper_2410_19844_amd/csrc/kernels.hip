@@ -872,6 +872,7 @@ hipError_t launch_gram(const sos_plan_s* p, int mode, hipStream_t s, bool unmerg
   const void* w32 = (p->prec == SOS_FP32) ? ws + p->lay.a_hi : ws + p->lay.a_f32;
   if (mode == kFwdExact) return launch_gram_x64(p, s);
   if (mode == kFwdOzaki) return launch_gram_i8(p, s, oz_slices);
+  if (mode == kFwdSingle) return launch_gram_bf3(p, s, false, unmerged, true);
   if (mode == kFwdF32 || p->prec == SOS_FP32) return gram_launch<MF32>(p, w32, nullptr, s);
   return launch_gram_bf3(p, s, false, unmerged);
 }

@@ -403,7 +403,8 @@ hipError_t launch_prep(const sos_plan_s* p, const void* W, const PrepNeeds& need
 hipError_t launch_init_r(const sos_plan_s* p, const double* d_p, hipStream_t s);
 hipError_t launch_sumsq(const sos_plan_s* p, const double* x, int64_t M, double* out, hipStream_t s,
                         float* x32 = nullptr);
-enum { kFwdFast = 0, kFwdF32 = 1, kFwdExact = 2, kFwdOzaki = 3 };
+// kFwdSingle: split plans' fast forward with one product (hi hi^T)
+enum { kFwdFast = 0, kFwdF32 = 1, kFwdExact = 2, kFwdOzaki = 3, kFwdSingle = 4 };
 // oz_slices: digit slices of the Ozaki forward (kOzSlices, or 5 with SOS_FLAG_OZAKI_FIVE_SLICES)
 hipError_t launch_gram(const sos_plan_s* p, int mode, hipStream_t s, bool unmerged = false, int oz_slices = kOzSlices);
 // deterministic forward (FP32 and FP64 plans with pair lists): the generic
@@ -425,8 +426,10 @@ struct TailSplit {
 };
 TailSplit gram_tail_split(int ntiles, int64_t nstages, hipStream_t s);
 
-// store: the unfused variant's stored tiles; unmerged: one atomic per Gram entry even where merge maps exist
-hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s, bool store = false, bool unmerged = false);
+// store: the unfused variant's stored tiles; unmerged: one atomic per Gram entry even where merge maps exist;
+// single: one product hi hi^T instead of the three of the split form
+hipError_t launch_gram_bf3(const sos_plan_s* p, hipStream_t s, bool store = false, bool unmerged = false,
+                           bool single = false);
 hipError_t launch_scatter_tiles(const sos_plan_s* p, hipStream_t s);
 // the merge maps of a split plan's gram epilogue (into lay.mg_*; reads the ranking tables and the tile list)
 hipError_t launch_merge_maps(const sos_plan_s* p, hipStream_t s);
