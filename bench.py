@@ -53,6 +53,10 @@ LR_DEFAULTS = {"n12d6": (3e-3, 1e-3), "q100": (3e-3, 2e-3)}
 # (chosen by a sweep of time to 1e-8 at n=12, d=6: 1e-2, 3e-3 and 2e-3 keep
 # the 340 steps, 1e-3 takes 350; 3e-3 leaves a factor 3).
 SINGLE_REL_DEFAULTS = {"n12d6": 3e-3}
+# The five-slice finisher starts with four slices until rel <= this (a sweep
+# at n=12, d=6: 1e-6, 3e-7 and 1e-7 keep the 340 steps, 5e-8 and below take
+# 350; 2e-7 leaves a factor 4).
+FOUR_REL_DEFAULTS = {"n12d6": 2e-7}
 DTYPE = {"bf16x3": "bf16", "fp16x3": "fp16", "fp32": "fp32", "fp64": "fp64"}
 
 
@@ -66,7 +70,7 @@ def parse():
     ap.add_argument("--exact", action="store_true", help="FP64 forward (the finishing phase)")
     ap.add_argument("--ozaki", action="store_true",
                     help="FP64-accurate forward from int8 slices (Ozaki splitting) instead of the fast one")
-    ap.add_argument("--ozaki-slices", type=int, default=6, choices=(5, 6),
+    ap.add_argument("--ozaki-slices", type=int, default=6, choices=(4, 5, 6),
                     help="with --ozaki: digit slices (5: 15 slice products instead of 21, the finisher's forward)")
     ap.add_argument("--unfused-scatter", action="store_true",
                     help="step: the gram stores its tiles and a separate kernel scatters them (measures the scatter)")
@@ -78,6 +82,8 @@ def parse():
                     help="step: split plans, the gram takes one product (hi hi^T) instead of three")
     ap.add_argument("--single-rel", type=float, default=None,
                     help="ttt: split plans start with the single-product forward until rel <= this (0: off)")
+    ap.add_argument("--four-rel", type=float, default=None,
+                    help="ttt: the five-slice finisher takes four slices until rel <= this (0: off)")
     ap.add_argument("--finisher", choices=("fp64", "ozaki", "ozaki5"), default=None,
                     help="ttt: forward of the exact phase (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -310,6 +316,8 @@ def ttt_run(S, torch, a, c, W_host, p, precision, single_backward, finisher=None
     mid_rel = a.mid_rel if a.mid_rel is not None else 0.0
     single_rel = ((a.single_rel if a.single_rel is not None else SINGLE_REL_DEFAULTS.get(c.name, 0.0))
                   if precision in SPLIT else 0.0)
+    four_rel = ((a.four_rel if a.four_rel is not None else FOUR_REL_DEFAULTS.get(c.name, 0.0))
+                if finisher == "ozaki5" else 0.0)
     pl = S.Plan(c.n, c.d, c.rank, precision)
     wdt = torch.float64 if precision == "fp64" else torch.float32
     W = torch.tensor(W_host, dtype=wdt, device="cuda")
@@ -318,13 +326,14 @@ def ttt_run(S, torch, a, c, W_host, p, precision, single_backward, finisher=None
     res = pl.solve(W, p, S.Adam(lr=lr), tol=a.tol, max_steps=a.max_steps, check_every=10, ladder=True,
                    stall_checks=6, stall_ratio=0.8, switch_rel=switch_rel, lr_exact=lr_exact,
                    rollback_ratio=10.0, single_backward=single_backward, mid_rel=mid_rel,
-                   finisher=finisher if precision != "fp64" else "fp64", single_rel=single_rel)
+                   finisher=finisher if precision != "fp64" else "fp64", single_rel=single_rel,
+                   four_rel=four_rel)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     del pl, W
     torch.cuda.empty_cache()
     return dict(res, seconds=dt, precision=precision, lr=lr, lr_exact=lr_exact, switch_rel=switch_rel,
-                mid_rel=mid_rel, single_rel=single_rel, single_backward=single_backward, tol=a.tol, finisher=finisher,
+                mid_rel=mid_rel, single_rel=single_rel, four_rel=four_rel, single_backward=single_backward, tol=a.tol, finisher=finisher,
                 certified=res["status"] == S.OK)
 
 
@@ -459,6 +468,7 @@ def main():
     stream = torch.cuda.current_stream()
     flags = ((S.FLAG_EXACT_FORWARD if a.exact else 0) | (S.FLAG_OZAKI_FORWARD if a.ozaki else 0)
              | (S.FLAG_OZAKI_FIVE_SLICES if a.ozaki and a.ozaki_slices == 5 else 0)
+             | (S.FLAG_OZAKI_FOUR_SLICES if a.ozaki and a.ozaki_slices == 4 else 0)
              | (S.FLAG_SINGLE_FORWARD if a.single_forward else 0)
              | (S.FLAG_SINGLE_BACKWARD if a.single_backward else 0)
              | (S.FLAG_UNFUSED_SCATTER if a.unfused_scatter else 0)
@@ -576,7 +586,7 @@ def main():
     if not a.no_ttt:
         out["ttt"] = {}
         # mixed: split-bf16 bulk (its first part with the single-product forward, the workload's
-        # single_rel), then the Ozaki forward on five int8 slices (the fastest finisher);
+        # single_rel), then the Ozaki forward on four and then five int8 slices (the fastest finisher);
         # mixed_ozaki6_finisher: six slices (the FP64-level Ozaki forward); mixed_fp64_finisher: the
         # FP64-MFMA finisher; fp32: the plain FP32 form (FP32 MFMA for both contractions, FP64-MFMA
         # finisher).  Every result is certified by the FP64-MFMA forward.
@@ -585,7 +595,7 @@ def main():
             r = ttt_run(S, torch, a, c, W_start, p, prec, single, fin)
             out["ttt"][name] = {q: r[q] for q in ("seconds", "steps", "exact_steps", "rel", "best_rel", "certified",
                                                   "precision", "lr", "lr_exact", "switch_rel", "single_backward",
-                                                  "tol", "finisher", "single_rel")}
+                                                  "tol", "finisher", "single_rel", "four_rel")}
             print(f"ttt {name}: {r['seconds']:.2f} s, {r['steps']} steps ({r['exact_steps']} exact), "
                   f"rel {r['rel']:.3g}", file=sys.stderr, flush=True)
         m, f = out["ttt"]["mixed"], out["ttt"]["fp32"]

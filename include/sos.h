@@ -160,6 +160,13 @@ enum sos_flags {
    * SOS_EINVAL on other plans or with SOS_FLAG_UNFUSED_SCATTER,
    * SOS_FLAG_UNMERGED_SCATTER or SOS_FLAG_DETERMINISTIC.                 */
   SOS_FLAG_SINGLE_FORWARD = 512,
+  /* With SOS_FLAG_OZAKI_FORWARD: 4 digit slices (levels s + t < 4: 10
+   * slice products).  Per Gram entry the error is at most
+   * 5.05 * 2^-28 * rank * 2^(e_i + e_j) plus FP64 rounding, about 128x the
+   * five-slice figure (~4e-8 of ||coeff(W W^T)|| for Gaussian rows); for
+   * the start of a finisher (sos_solve's four_rel).  SOS_EINVAL without
+   * SOS_FLAG_OZAKI_FORWARD or with SOS_FLAG_OZAKI_FIVE_SLICES.             */
+  SOS_FLAG_OZAKI_FOUR_SLICES = 1024,
 };
 
 /* Adam hyper-parameters (Kingma and Ba; the paper's optimiser, Section 3). */
@@ -211,6 +218,10 @@ typedef struct {
                             to the three-product forward once rel <=
                             single_rel (or on a stall); same Adam state and
                             step size (0: three products from the start)    */
+  double four_rel;       /* finisher 2: the exact phase takes four int8
+                            slices (SOS_FLAG_OZAKI_FOUR_SLICES) until rel <=
+                            four_rel (or a stall), then five (0: five
+                            throughout)                                     */
 } sos_solve_opts_t;
 
 typedef struct {

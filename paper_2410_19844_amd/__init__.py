@@ -30,6 +30,7 @@ FLAG_UNFUSED_SCATTER = 64
 FLAG_UNMERGED_SCATTER = 128
 FLAG_OZAKI_FIVE_SLICES = 256
 FLAG_SINGLE_FORWARD = 512
+FLAG_OZAKI_FOUR_SLICES = 1024
 OK, NOT_CONVERGED = 0, 1
 EINVAL, ERANGE, ENOMEM, EHIP, ENUMERIC = -1, -2, -3, -4, -5
 
@@ -53,7 +54,7 @@ class _SolveOpts(ctypes.Structure):
                 ("rollback_ratio", ctypes.c_double), ("single_backward", ctypes.c_int32),
                 ("finisher", ctypes.c_int32), ("mid_rel", ctypes.c_double),
                 ("step_flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("single_rel", ctypes.c_double)]
+                ("single_rel", ctypes.c_double), ("four_rel", ctypes.c_double)]
 
 
 class _Result(ctypes.Structure):
@@ -126,14 +127,16 @@ def _ptr(t):
 
 
 def _oz_flags(ozaki):
-    """Flags of the Ozaki forward: False (off), True or 6 (six digit slices), 5 (five)."""
+    """Flags of the Ozaki forward: False (off), True or 6 (six digit slices), 5 or 4."""
     if ozaki is False or ozaki is None or ozaki == 0:
         return 0
     if ozaki is True or ozaki == 6:
         return FLAG_OZAKI_FORWARD
     if ozaki == 5:
         return FLAG_OZAKI_FORWARD | FLAG_OZAKI_FIVE_SLICES
-    raise ValueError("ozaki must be False, True, 5 or 6")
+    if ozaki == 4:
+        return FLAG_OZAKI_FORWARD | FLAG_OZAKI_FOUR_SLICES
+    raise ValueError("ozaki must be False, True, 4, 5 or 6")
 
 
 @dataclass
@@ -275,17 +278,18 @@ class Plan:
     def solve(self, W, p, adam: Adam, tol=1e-8, max_steps=10000, check_every=50, ladder=True,
               stall_checks=4, stall_ratio=0.7, switch_rel=0.0, lr_exact=0.0, rollback_ratio=0.0,
               single_backward=False, mid_rel=0.0, finisher="fp64", deterministic=False, state=None,
-              single_rel=0.0, stream=None):
+              single_rel=0.0, four_rel=0.0, stream=None):
         """sos_solve: Adam to an FP64-verified ||r||/||p|| <= tol; W ends as the best iterate.
         finisher: forward of the exact phase, "fp64" (FP64 MFMA), "ozaki" (six int8 slices) or
         "ozaki5" (five int8 slices).  single_rel: split plans start with the single-product
-        forward until rel <= single_rel (0: off)."""
+        forward until rel <= single_rel (0: off).  four_rel: with finisher "ozaki5", four slices
+        until rel <= four_rel (0: off)."""
         self._w(W), self._p(p)
         state = self.new_state() if state is None else state
         fin = {"fp64": 0, "ozaki": 1, "ozaki5": 2}[finisher]
         opts = _SolveOpts(tol, max_steps, check_every, 1 if ladder else 0, stall_checks, stall_ratio,
                           switch_rel, lr_exact, rollback_ratio, 1 if single_backward else 0, fin, mid_rel,
-                          FLAG_DETERMINISTIC if deterministic else 0, 0, single_rel)
+                          FLAG_DETERMINISTIC if deterministic else 0, 0, single_rel, four_rel)
         res = _Result()
         _check(_lib.sos_solve(self._h, _ptr(W), _ptr(state), _ptr(p), ctypes.byref(adam.c()),
                               ctypes.byref(opts), ctypes.byref(res), _stream(stream)),

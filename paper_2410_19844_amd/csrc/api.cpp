@@ -93,7 +93,9 @@ static int fwd_mode(const sos_plan_s* p, int flags) {
 }
 
 // Digit slices of the Ozaki forward.
-static int oz_slices(int flags) { return (flags & SOS_FLAG_OZAKI_FIVE_SLICES) ? 5 : kOzSlices; }
+static int oz_slices(int flags) {
+  return (flags & SOS_FLAG_OZAKI_FOUR_SLICES) ? 4 : (flags & SOS_FLAG_OZAKI_FIVE_SLICES) ? 5 : kOzSlices;
+}
 
 // grad: a backward follows (so the transposed operand copies are needed).
 // reuse: the operand copies already in the workspace were made from this W
@@ -210,6 +212,9 @@ static int check_single(const sos_plan_s* p, int flags, const char* fn) {
 static int check_ozaki(const sos_plan_s* p, int flags, const char* fn) {
   if ((flags & SOS_FLAG_OZAKI_FIVE_SLICES) && !(flags & SOS_FLAG_OZAKI_FORWARD))
     return set_error(SOS_EINVAL, std::string(fn) + ": SOS_FLAG_OZAKI_FIVE_SLICES needs SOS_FLAG_OZAKI_FORWARD");
+  if ((flags & SOS_FLAG_OZAKI_FOUR_SLICES) && (!(flags & SOS_FLAG_OZAKI_FORWARD) || (flags & SOS_FLAG_OZAKI_FIVE_SLICES)))
+    return set_error(SOS_EINVAL, std::string(fn) + ": SOS_FLAG_OZAKI_FOUR_SLICES needs SOS_FLAG_OZAKI_FORWARD "
+                                                   "and excludes SOS_FLAG_OZAKI_FIVE_SLICES");
   if (!(flags & SOS_FLAG_OZAKI_FORWARD) || (flags & SOS_FLAG_EXACT_FORWARD)) return SOS_OK;
   if (p->prec == SOS_FP64)
     return set_error(SOS_EINVAL, std::string(fn) + ": SOS_FLAG_OZAKI_FORWARD needs an FP32 or split plan");
@@ -371,7 +376,8 @@ int sos_loss_grad(sos_plan_t p, const void* d_W, const double* d_p, double* d_lo
   if (!d_W || !d_p || !d_loss) return set_error(SOS_EINVAL, "sos_loss_grad: d_W, d_p and d_loss are required");
   if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_SINGLE_BACKWARD | SOS_FLAG_FP32_FORWARD |
                      SOS_FLAG_OZAKI_FORWARD | SOS_FLAG_DETERMINISTIC | SOS_FLAG_UNFUSED_SCATTER |
-                     SOS_FLAG_UNMERGED_SCATTER | SOS_FLAG_OZAKI_FIVE_SLICES | SOS_FLAG_SINGLE_FORWARD))
+                     SOS_FLAG_UNMERGED_SCATTER | SOS_FLAG_OZAKI_FIVE_SLICES | SOS_FLAG_SINGLE_FORWARD |
+                     SOS_FLAG_OZAKI_FOUR_SLICES))
     return set_error(SOS_EINVAL, "sos_loss_grad: unknown flags");
   if (int rc = check_single(p, flags, "sos_loss_grad")) return rc;
   if (int rc = check_unmerged(p, flags, "sos_loss_grad")) return rc;
@@ -396,7 +402,7 @@ int sos_step(sos_plan_t p, void* d_W, void* d_state, int64_t t, const double* d_
   if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_COPIES_VALID | SOS_FLAG_SINGLE_BACKWARD |
                      SOS_FLAG_FP32_FORWARD | SOS_FLAG_OZAKI_FORWARD | SOS_FLAG_DETERMINISTIC |
                      SOS_FLAG_UNFUSED_SCATTER | SOS_FLAG_UNMERGED_SCATTER | SOS_FLAG_OZAKI_FIVE_SLICES |
-                     SOS_FLAG_SINGLE_FORWARD))
+                     SOS_FLAG_SINGLE_FORWARD | SOS_FLAG_OZAKI_FOUR_SLICES))
     return set_error(SOS_EINVAL, "sos_step: unknown flags");
   if (int rc = check_single(p, flags, "sos_step")) return rc;
   if (int rc = check_unmerged(p, flags, "sos_step")) return rc;
@@ -495,7 +501,7 @@ int sos_loss_grad_noalloc(sos_plan_t p, const void* d_W, const double* d_p, doub
   if (!d_W || !d_p || !d_loss)
     return set_error(SOS_EINVAL, "sos_loss_grad_noalloc: d_W, d_p and d_loss are required");
   if (flags & ~(int)(SOS_FLAG_EXACT_FORWARD | SOS_FLAG_SINGLE_BACKWARD | SOS_FLAG_FP32_FORWARD |
-                     SOS_FLAG_OZAKI_FORWARD | SOS_FLAG_OZAKI_FIVE_SLICES))
+                     SOS_FLAG_OZAKI_FORWARD | SOS_FLAG_OZAKI_FIVE_SLICES | SOS_FLAG_OZAKI_FOUR_SLICES))
     return set_error(SOS_EINVAL, "sos_loss_grad_noalloc: unknown flags");
   if (int rc = check_ozaki(p, flags, "sos_loss_grad_noalloc")) return rc;
   if (p->lay.bytes > (size_t)SOS_NOALLOC_MAX_WS)
@@ -528,9 +534,9 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
   if (int rc = check_adam(adam, "sos_solve")) return rc;
   if (!d_W || !d_state || !d_p || !o || !res) return set_error(SOS_EINVAL, "sos_solve: NULL argument");
   if (o->max_steps < 0 || o->check_every < 1 || !(o->tol >= 0) || !(o->lr_exact >= 0) ||
-      !(o->rollback_ratio >= 0) || o->stall_checks < 0 || !(o->single_rel >= 0))
+      !(o->rollback_ratio >= 0) || o->stall_checks < 0 || !(o->single_rel >= 0) || !(o->four_rel >= 0))
     return set_error(SOS_EINVAL, "sos_solve: needs max_steps >= 0, check_every >= 1, tol, lr_exact, "
-                                 "rollback_ratio, single_rel >= 0 and stall_checks >= 0");
+                                 "rollback_ratio, single_rel, four_rel >= 0 and stall_checks >= 0");
   if (o->finisher < 0 || o->finisher > 2) return set_error(SOS_EINVAL, "sos_solve: finisher must be 0, 1 or 2");
   if (o->step_flags & ~(int)SOS_FLAG_DETERMINISTIC)
     return set_error(SOS_EINVAL, "sos_solve: step_flags may be SOS_FLAG_DETERMINISTIC");
@@ -564,6 +570,8 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
   const bool has_mid = can_ladder && split_plan(p) && o->mid_rel > 0;
   // fast start: the first part of phase 0 with the single-product forward
   bool fast_start = can_ladder && split_plan(p) && o->single_rel > 0;
+  // the five-slice finisher's first part with four slices
+  bool four = o->finisher == 2 && o->four_rel > 0;
   auto next_phase = [&]() {
     phase = (phase == 0 && has_mid) ? 1 : 2;
     stall = 0;
@@ -578,7 +586,8 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
     ++t_adam;
     const bool check = (t % o->check_every == 0) || t == o->max_steps;
     if (check) SOS_HIP(hipMemcpyAsync(cand, d_W, wbytes, hipMemcpyDeviceToDevice, s), "sos_solve: snapshot");
-    const int exact_flag = o->finisher == 2   ? SOS_FLAG_OZAKI_FORWARD | SOS_FLAG_OZAKI_FIVE_SLICES
+    const int exact_flag = o->finisher == 2
+                               ? SOS_FLAG_OZAKI_FORWARD | (four ? SOS_FLAG_OZAKI_FOUR_SLICES : SOS_FLAG_OZAKI_FIVE_SLICES)
                            : o->finisher == 1 ? SOS_FLAG_OZAKI_FORWARD
                                               : SOS_FLAG_EXACT_FORWARD;
     const int fast_flags = (o->step_flags & SOS_FLAG_DETERMINISTIC) | (fast_start ? SOS_FLAG_SINGLE_FORWARD : 0);
@@ -634,6 +643,14 @@ int sos_solve(sos_plan_t p, void* d_W, void* d_state, const double* d_p, const s
         stall = 0;
         best_rel = ref_rel = inf;  // values of the three-product forward from here on
       }
+      continue;
+    }
+    if (phase == 2 && four && (rel <= o->four_rel || (o->stall_checks > 0 && stall >= o->stall_checks))) {
+      // on to five slices once the four-slice forward's rounding (~4e-8 of
+      // the coefficients' scale for Gaussian rows) could start to matter
+      four = false;
+      stall = 0;
+      best_rel = ref_rel = inf;
       continue;
     }
     const double target = phase == 0 ? o->switch_rel : o->mid_rel;

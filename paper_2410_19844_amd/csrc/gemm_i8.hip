@@ -18,9 +18,10 @@
 // (S + 1.05) 2^-7S K 2^(e_i + e_j), plus FP64 rounding (about 1e-12 of the
 // Gram entry at S = 6 and Gaussian rows; the errors of individual digits are
 // independent, so the actual error is far below this bound).
-// S is a template argument: 6 (kOzSlices, the FP64-level forward) or 5
+// S is a template argument: 6 (kOzSlices, the FP64-level forward), 5
 // (levels s + t < 5: 15 slice products instead of 21, about 128x the error,
-// for a finisher whose target lies far above it).
+// for a finisher whose target lies far above it) or 4 (10 products, another
+// 128x, for the start of such a finisher).
 //
 // Kernel: one 256 x 256 upper-triangle tile per 512-thread workgroup, 8 waves
 // of 128 x 64 (4 x 2 blocks of v_mfma_i32_32x32x32_i8, two waves per SIMD),
@@ -500,7 +501,7 @@ __global__ __launch_bounds__(256) void k_oz_slice(const float* __restrict__ W, i
 }  // namespace i8
 
 hipError_t launch_oz_slices(const sos_plan_s* p, const float* W, hipStream_t s, int slices) {
-  if (slices != kOzSlices && slices != 5) return hipErrorInvalidValue;
+  if (slices != kOzSlices && slices != 5 && slices != 4) return hipErrorInvalidValue;
   char* ws = p->ws;
   int* ex = (int*)(ws + p->lay.oz_exp);
   i8::k_oz_scale<<<(unsigned)p->N, 256, 0, s>>>(W, (int)p->N, p->k, ex, (double*)(ws + p->lay.oz_scale));
@@ -509,13 +510,14 @@ hipError_t launch_oz_slices(const sos_plan_s* p, const float* W, hipStream_t s, 
   const dim3 grid((unsigned)(p->Kp / 64), (unsigned)(p->Np / 64));
   int8_t* oz = (int8_t*)(ws + p->lay.oz);
   const int64_t sb = (int64_t)p->lay.oz_slice, ps = oz_panel_stride(p->Kp);
-  if (slices == 5) i8::k_oz_slice<5><<<grid, 256, 0, s>>>(W, (int)p->N, p->k, ex, oz, sb, ps);
+  if (slices == 4) i8::k_oz_slice<4><<<grid, 256, 0, s>>>(W, (int)p->N, p->k, ex, oz, sb, ps);
+  else if (slices == 5) i8::k_oz_slice<5><<<grid, 256, 0, s>>>(W, (int)p->N, p->k, ex, oz, sb, ps);
   else i8::k_oz_slice<kOzSlices><<<grid, 256, 0, s>>>(W, (int)p->N, p->k, ex, oz, sb, ps);
   return hipGetLastError();
 }
 
 hipError_t launch_gram_i8(const sos_plan_s* p, hipStream_t s, int slices) {
-  if (slices != kOzSlices && slices != 5) return hipErrorInvalidValue;
+  if (slices != kOzSlices && slices != 5 && slices != 4) return hipErrorInvalidValue;
   i8::Args g;
   const char* ws = p->ws;
   g.oz = (const int8_t*)(ws + p->lay.oz);
@@ -532,7 +534,10 @@ hipError_t launch_gram_i8(const sos_plan_s* p, hipStream_t s, int slices) {
   g.mmap = p->merge_ready ? (const uint16_t*)(ws + p->lay.mg_map) : nullptr;
   g.mrank = p->merge_ready ? (const int*)(ws + p->lay.mg_rank) : nullptr;
   g.mcount = p->merge_ready ? (const int*)(ws + p->lay.mg_count) : nullptr;
-  if (slices == 5) {
+  if (slices == 4) {
+    if (g.mmap) i8::k_gram_i8<true, 4><<<g.ntiles, i8::NT, 0, s>>>(g);
+    else i8::k_gram_i8<false, 4><<<g.ntiles, i8::NT, 0, s>>>(g);
+  } else if (slices == 5) {
     if (g.mmap) i8::k_gram_i8<true, 5><<<g.ntiles, i8::NT, 0, s>>>(g);
     else i8::k_gram_i8<false, 5><<<g.ntiles, i8::NT, 0, s>>>(g);
   } else {

@@ -405,7 +405,8 @@ hipError_t launch_sumsq(const sos_plan_s* p, const double* x, int64_t M, double*
                         float* x32 = nullptr);
 // kFwdSingle: split plans' fast forward with one product (hi hi^T)
 enum { kFwdFast = 0, kFwdF32 = 1, kFwdExact = 2, kFwdOzaki = 3, kFwdSingle = 4 };
-// oz_slices: digit slices of the Ozaki forward (kOzSlices, or 5 with SOS_FLAG_OZAKI_FIVE_SLICES)
+// oz_slices: digit slices of the Ozaki forward (kOzSlices; 5 or 4 with SOS_FLAG_OZAKI_FIVE_SLICES or
+// SOS_FLAG_OZAKI_FOUR_SLICES)
 hipError_t launch_gram(const sos_plan_s* p, int mode, hipStream_t s, bool unmerged = false, int oz_slices = kOzSlices);
 // deterministic forward (FP32 and FP64 plans with pair lists): the generic
 // gram stores its slices, then each coefficient sums its pairs in a fixed order
@@ -435,7 +436,7 @@ hipError_t launch_scatter_tiles(const sos_plan_s* p, hipStream_t s);
 hipError_t launch_merge_maps(const sos_plan_s* p, hipStream_t s);
 hipError_t launch_gram_x64(const sos_plan_s* p, hipStream_t s);
 // Ozaki-split forward (gemm_i8.hip): row exponents and the first `slices`
-// int8 slices of W (kOzSlices or 5), then the gram on as many
+// int8 slices of W (kOzSlices, 5 or 4), then the gram on as many
 hipError_t launch_oz_slices(const sos_plan_s* p, const float* W, hipStream_t s, int slices);
 hipError_t launch_gram_i8(const sos_plan_s* p, hipStream_t s, int slices);
 inline bool ozaki_supported(const sos_plan_s* p) { return p->prec != SOS_FP64 && p->Kp <= kOzMaxK; }

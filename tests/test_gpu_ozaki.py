@@ -22,7 +22,8 @@ Five slices (SOS_FLAG_OZAKI_FIVE_SLICES, S = 5) keep the levels s + t < 5:
 the same bound with S = 5, about 128 times the six-slice one, and a
 statistical bar of 2e-9 of cabs (a CPU emulation of the split puts the
 largest error on these shapes at 2.3e-10 of cabs; dropping one more level
-would give ~4e-8).
+would give ~4e-8).  Four slices (SOS_FLAG_OZAKI_FOUR_SLICES): the bound with
+S = 4 and a bar of 5e-7 (emulated largest error 6.6e-8).
 """
 import math
 from math import comb
@@ -39,7 +40,7 @@ S = pytest.importorskip("paper_2410_19844_amd")
 pytestmark = pytest.mark.gpu
 
 U32 = 2.0 ** -24
-BAR = {6: 1e-10, 5: 2e-9}  # statistical bars (of cabs) per slice count
+BAR = {6: 1e-10, 5: 2e-9, 4: 5e-7}  # statistical bars (of cabs) per slice count
 
 
 def gamma(n):
@@ -72,7 +73,7 @@ def make(n, d, k, seed, row_exp=None):
 CASES = [(3, 2, 20), (4, 3, 37), (6, 3, 168), (6, 4, 420), (10, 5, 300), (17, 2, 40), (40, 2, 130)]
 
 
-@pytest.mark.parametrize("slices", [6, 5])
+@pytest.mark.parametrize("slices", [6, 5, 4])
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("n,d,k", CASES)
 def test_ozaki_forward_matches_oracle(prec, n, d, k, slices):
@@ -126,7 +127,7 @@ def test_ozaki_rows_of_very_different_scales(prec):
 def test_five_slices_are_five(n, d, k):
     """The five-slice forward really drops the sixth digit: its error is
     well above the six-slice one (an emulation gives ~50-130x in norm), and
-    both stay inside their bounds."""
+    the four-slice one well above that; each stays inside its bound."""
     W, p = make(n, d, k, seed=n * 10 + d)
     Wd = torch.tensor(W, dtype=torch.float32, device="cuda")
     W64 = Wd.double().cpu().numpy()
@@ -135,12 +136,12 @@ def test_five_slices_are_five(n, d, k):
     pr = O.pair_ranks(n, d)
     r_o = O.residual(W64, p, n, d, pr)
     e = {}
-    for sl in (5, 6):
+    for sl in (4, 5, 6):
         _, _, r = pl.loss_grad(Wd, pd, grad=False, want_r=True, ozaki=sl)
         err = r.cpu().numpy() - r_o
         assert np.all(np.abs(err) <= ozaki_bound(W64, p, n, d, pr, sl)), sl
         e[sl] = np.linalg.norm(err)
-    assert e[5] >= 10.0 * e[6], e
+    assert e[5] >= 10.0 * e[6] and e[4] >= 10.0 * e[5], e
 
 
 def test_ozaki_forward_agrees_with_exact_forward_at_a_fit():
@@ -169,8 +170,8 @@ def test_ozaki_forward_agrees_with_exact_forward_at_a_fit():
     assert np.all(np.abs(r_oz.cpu().numpy()) <= dc)
 
 
-@pytest.mark.parametrize("finisher", ["ozaki", "ozaki5"])
-def test_ozaki_finisher_solve_certified_by_the_oracle(finisher):
+@pytest.mark.parametrize("finisher,four_rel", [("ozaki", 0.0), ("ozaki5", 0.0), ("ozaki5", 1e-7)])
+def test_ozaki_finisher_solve_certified_by_the_oracle(finisher, four_rel):
     """The ladder with the Ozaki forward (six or five slices) in its exact
     phase reaches an FP64-verified 1e-8 (the certificate is the FP64-MFMA
     forward), and the oracle agrees on the returned W."""
@@ -183,7 +184,8 @@ def test_ozaki_finisher_solve_certified_by_the_oracle(finisher):
     Wd = torch.tensor(gaussian((N, k), 1, 1 / math.sqrt(k)), dtype=torch.float32, device="cuda")
     res = pl.solve(Wd, torch.tensor(p, dtype=torch.float64, device="cuda"), S.Adam(lr=3e-3), tol=1e-8,
                    max_steps=20000, check_every=10, ladder=True, stall_checks=6, stall_ratio=0.8,
-                   switch_rel=3e-6, lr_exact=1e-3, rollback_ratio=10.0, single_backward=True, finisher=finisher)
+                   switch_rel=3e-6, lr_exact=1e-3, rollback_ratio=10.0, single_backward=True, finisher=finisher,
+                   four_rel=four_rel)
     assert res["status"] == S.OK and res["phase"] == 2 and res["exact_steps"] > 0, res
     W64 = Wd.double().cpu().numpy()
     rel_o = float(np.linalg.norm(O.residual(W64, p, n, d, pr)) / np.linalg.norm(p))
@@ -234,4 +236,9 @@ def test_ozaki_nonfinite_and_errors():
         pl.step(Wd, pl.new_state(), 1, pd, S.Adam(lr=1e-3), flags=S.FLAG_OZAKI_FIVE_SLICES)
     assert e.value.code == S.EINVAL
     with pytest.raises(ValueError):
-        pl.loss_grad(Wd, pd, grad=False, ozaki=4)
+        pl.loss_grad(Wd, pd, grad=False, ozaki=3)
+    both = S.FLAG_OZAKI_FORWARD | S.FLAG_OZAKI_FIVE_SLICES | S.FLAG_OZAKI_FOUR_SLICES
+    for fl in (S.FLAG_OZAKI_FOUR_SLICES, both):
+        rc = S._lib.sos_loss_grad(pl._h, S._ptr(Wd), S._ptr(pd), S._ptr(loss), S._ptr(None), S._ptr(None), fl,
+                                  S._stream())
+        assert rc == S.EINVAL, fl
