@@ -52,11 +52,11 @@ LR_DEFAULTS = {"n12d6": (3e-3, 1e-3), "q100": (3e-3, 2e-3)}
 # Split-plan ladders start with the single-product forward until rel <= this
 # (chosen by a sweep of time to 1e-8 at n=12, d=6: 1e-2, 3e-3 and 2e-3 keep
 # the 340 steps, 1e-3 takes 350; 3e-3 leaves a factor 3).
-SINGLE_REL_DEFAULTS = {"n12d6": 3e-3}
+SINGLE_REL_DEFAULTS = {"n12d6": 3e-3, "q100": 3e-3}
 # The five-slice finisher starts with four slices until rel <= this (a sweep
 # at n=12, d=6: 1e-6, 3e-7 and 1e-7 keep the 340 steps, 5e-8 and below take
 # 350; 2e-7 leaves a factor 4).
-FOUR_REL_DEFAULTS = {"n12d6": 2e-7}
+FOUR_REL_DEFAULTS = {"n12d6": 2e-7, "q100": 2e-7}  # q100: the same 450 steps with both
 DTYPE = {"bf16x3": "bf16", "fp16x3": "fp16", "fp32": "fp32", "fp64": "fp64"}
 
 

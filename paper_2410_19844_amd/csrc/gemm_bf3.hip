@@ -753,13 +753,15 @@ __global__ __launch_bounds__(NT) void k_rw_adam_bf3(RwAdamArgs a) {
     // Adam on the quarter (row-major, coalesced in W, m, v), the forward copy,
     // and the bf16 of the new W into tb for the transposed copy.  Each thread
     // takes four consecutive elements of a row at a time (one 16-byte access
-    // per array when rows start 16-byte aligned; 4-byte accesses measured
-    // 5% slower over the whole kernel and spilled), and the loads of the
-    // next four are issued before the current four are computed, so HBM
-    // latency overlaps the work.
+    // per array when rows start 16-byte aligned, two 8-byte ones when they
+    // start 8-byte aligned; 4-byte accesses measured 5% slower over the whole
+    // kernel at n=12, d=6 and 20% at the hundred-variable quartic, k = 5050),
+    // and the loads of the next four are issued before the current four are
+    // computed, so HBM latency overlaps the work.
     constexpr int PER = QROWS * TM / NT;
     constexpr int EB = 4;   // four consecutive elements of one row per fetch batch (one 16-byte access per array)
-    const bool vec = (r.k & 3) == 0;  // rows start 16-byte aligned
+    const bool vec = (r.k & 3) == 0;       // rows start 16-byte aligned
+    const bool vec2 = !vec && (r.k & 1) == 0;  // rows start 8-byte aligned: two 8-byte accesses
     float4 wv[2], mv[2], vv[2];
     auto fetch = [&](int b8, int buf) {
       const int e0 = EB * (threadIdx.x + NT * b8);
@@ -771,6 +773,13 @@ __global__ __launch_bounds__(NT) void k_rw_adam_bf3(RwAdamArgs a) {
           wv[buf] = *(const float4*)(a.W + o);
           mv[buf] = *(const float4*)(a.m + o);
           vv[buf] = *(const float4*)(a.v + o);
+        } else if (vec2 && l0 + 3 < r.k) {
+          const float2 w0 = *(const float2*)(a.W + o), w1 = *(const float2*)(a.W + o + 2);
+          const float2 m0 = *(const float2*)(a.m + o), m1 = *(const float2*)(a.m + o + 2);
+          const float2 v0 = *(const float2*)(a.v + o), v1 = *(const float2*)(a.v + o + 2);
+          wv[buf] = make_float4(w0.x, w0.y, w1.x, w1.y);
+          mv[buf] = make_float4(m0.x, m0.y, m1.x, m1.y);
+          vv[buf] = make_float4(v0.x, v0.y, v1.x, v1.y);
         } else {
 #pragma unroll
           for (int u = 0; u < EB; ++u)
@@ -806,6 +815,13 @@ __global__ __launch_bounds__(NT) void k_rw_adam_bf3(RwAdamArgs a) {
           *(float4*)(a.m + o) = mn;
           *(float4*)(a.v + o) = vn;
           *(float4*)(a.W + o) = wn;
+        } else if (vec2 && l0 + 3 < r.k) {
+          *(float2*)(a.m + o) = make_float2(mn.x, mn.y);
+          *(float2*)(a.m + o + 2) = make_float2(mn.z, mn.w);
+          *(float2*)(a.v + o) = make_float2(vn.x, vn.y);
+          *(float2*)(a.v + o + 2) = make_float2(vn.z, vn.w);
+          *(float2*)(a.W + o) = make_float2(wn.x, wn.y);
+          *(float2*)(a.W + o + 2) = make_float2(wn.z, wn.w);
         } else {
 #pragma unroll
           for (int u = 0; u < EB; ++u)
