@@ -281,7 +281,12 @@ int sos_pair_ranks(sos_plan_t plan, int32_t* d_out, void* stream);
  *   d_loss: 1 double, receives L = ||r||^2
  *   d_grad: N x rank in W's type, receives 4 R W; may be NULL (forward only)
  *   d_r:    M doubles, receives r = coeff(W W^T) - p; may be NULL
- *   flags:  SOS_FLAG_EXACT_FORWARD or 0                                    */
+ *   flags:  0 (the plan's own forward) or the SOS_FLAG_* values above that
+ *           select a forward (EXACT, OZAKI with FIVE_SLICES or FOUR_SLICES,
+ *           FP32, SINGLE) or a variant of it (DETERMINISTIC, UNFUSED_SCATTER,
+ *           UNMERGED_SCATTER), and SOS_FLAG_SINGLE_BACKWARD; each flag's
+ *           comment states the plans it applies to and its SOS_EINVAL cases;
+ *           any other bit is SOS_EINVAL                                    */
 int sos_loss_grad(sos_plan_t plan, const void* d_W, const double* d_p, double* d_loss,
                   void* d_grad, double* d_r, int flags, void* stream);
 
@@ -310,7 +315,7 @@ int sos_loss_grad_noalloc(sos_plan_t plan, const void* d_W, const double* d_p, d
 /* One Adam step at iteration t (1-based): computes the loss and gradient
  * at W (written to d_loss), then updates W, m, v in place.
  *   d_state: state_bytes from sos_plan_query; zero it before t = 1.
- *   flags:   SOS_FLAG_EXACT_FORWARD and/or SOS_FLAG_COPIES_VALID.          */
+ *   flags:   those of sos_loss_grad, and SOS_FLAG_COPIES_VALID.            */
 int sos_step(sos_plan_t plan, void* d_W, void* d_state, int64_t t, const double* d_p,
              const sos_adam_t* adam, double* d_loss, int flags, void* stream);
 
