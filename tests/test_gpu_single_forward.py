@@ -118,21 +118,22 @@ def test_single_forward_fused_step():
     assert L2 < L0
 
 
-def test_fast_start_solve_certified_by_the_oracle():
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3"])
+def test_fast_start_solve_certified_by_the_oracle(prec):
     """The ladder starting with the single-product forward (single_rel) goes
-    on to the three products and the five-slice finisher, and reaches an
-    FP64-verified 1e-8 that the oracle confirms."""
+    on to the three products and the finisher (four, then five int8 slices),
+    and reaches an FP64-verified 1e-8 that the oracle confirms."""
     n, d = 6, 4
     N = comb(n + d, d)
     k = 2 * N
     pr = O.pair_ranks(n, d)
     p = O.coefficients(gaussian((N, N // 2), 0) / math.sqrt(N // 2), n, d, pr)
-    pl = S.Plan(n, d, k, "bf16x3")
+    pl = S.Plan(n, d, k, prec)
     Wd = torch.tensor(gaussian((N, k), 1, 1 / math.sqrt(k)), dtype=torch.float32, device="cuda")
     res = pl.solve(Wd, torch.tensor(p, dtype=torch.float64, device="cuda"), S.Adam(lr=3e-3), tol=1e-8,
                    max_steps=20000, check_every=10, ladder=True, stall_checks=6, stall_ratio=0.8,
                    switch_rel=3e-6, lr_exact=1e-3, rollback_ratio=10.0, single_backward=True, finisher="ozaki5",
-                   single_rel=1e-2)
+                   single_rel=1e-2, four_rel=1e-7)
     assert res["status"] == S.OK and res["phase"] == 2 and res["exact_steps"] > 0, res
     W64 = Wd.double().cpu().numpy()
     rel_o = float(np.linalg.norm(O.residual(W64, p, n, d, pr)) / np.linalg.norm(p))
