@@ -5,7 +5,9 @@ backward), through the C ABI.
 * Coefficients: a seeded sample of coefficient positions (plus the extreme
   ones: x1^12, with one pair, and the constant, with one pair), each summed
   pair by pair by the oracle, against c = r + p from the fast forward
-  (split-bf16 bound) and from the exact forward (1e-10).
+  (split-bf16 bound), the exact forward (1e-10), the int8 Ozaki forwards
+  (six, five and four slices, each under its truncation bound) and the
+  single-product forward (its rounding bound).
 * Gradient rows, element by element: the oracle forms the whole residual
   once (its own pair map, a plain matmul for W W^T, a bincount over the
   ordered pairs; about a minute of host time), then sampled rows
@@ -60,9 +62,13 @@ def full():
     L_fast, g, r_fast = pl.loss_grad(Wd, pd, grad=True, want_r=True, single_backward=True)
     L_ex, _, r_ex = pl.loss_grad(Wd, pd, grad=False, want_r=True, exact=True)
     L_oz, _, r_oz = pl.loss_grad(Wd, pd, grad=False, want_r=True, ozaki=True)
+    # the ladder's other rungs: five and four int8 slices, the single-product forward
+    _, _, r_oz5 = pl.loss_grad(Wd, pd, grad=False, want_r=True, ozaki=5)
+    _, _, r_oz4 = pl.loss_grad(Wd, pd, grad=False, want_r=True, ozaki=4)
+    _, _, r_single = pl.loss_grad(Wd, pd, grad=False, want_r=True, single_forward=True)
     torch.cuda.synchronize()
-    return dict(c=c, pl=pl, W=Wd, p=p, pd=pd, g=g, r_fast=r_fast, r_ex=r_ex, r_oz=r_oz,
-                L_fast=float(L_fast.item()), L_ex=float(L_ex.item()), L_oz=float(L_oz.item()))
+    return dict(c=c, pl=pl, W=Wd, p=p, pd=pd, g=g, r_fast=r_fast, r_ex=r_ex, r_oz=r_oz, r_oz5=r_oz5, r_oz4=r_oz4,
+                r_single=r_single, L_fast=float(L_fast.item()), L_ex=float(L_ex.item()), L_oz=float(L_oz.item()))
 
 
 def sample_betas(M, count=96, seed=21):
@@ -97,6 +103,33 @@ def test_fullsize_sampled_coefficients(full):
     err = np.abs(got_oz - want)
     assert np.max(err / (7.05 * 2.0 ** -42 * c.rank * cs + 1e-13 * cabs + slack)) <= 1.0
     assert np.max(err / (1e-10 * cabs + slack)) <= 1.0, "Ozaki forward"
+
+
+def test_fullsize_sampled_coefficients_ladder_rungs(full):
+    """The reduced forms the ladder runs at this size: the five- and
+    four-slice Ozaki forwards under their truncation bounds (S + 1.05) 2^-7S
+    K 2^(e_i + e_j) per Gram entry and their statistical bars (2e-9 and 5e-7
+    of cabs), and the single-product forward under 2^-7 + 2^-16 + gamma(K) + u
+    of cabs."""
+    c, W = full["c"], full["W"]
+    betas = sample_betas(c.M, seed=23)
+    W64 = W.double().cpu().numpy()
+    basis = O.monomials(c.n, c.d)
+    bidx, cidx = O.MonomialIndex(c.n, c.d), O.MonomialIndex(c.n, 2 * c.d)
+    want = O.sample_coefficients(W64, c.n, c.d, betas, basis, bidx, cidx)
+    cabs = O.sample_coefficients(np.abs(W64), c.n, c.d, betas, basis, bidx, cidx)
+    _, e = np.frexp(np.abs(W64).max(axis=1))
+    cs = O.sample_coefficients(np.ldexp(1.0, e)[:, None], c.n, c.d, betas, basis, bidx, cidx)
+    p = full["p"][betas]
+    slack = 1e-15 * np.abs(p)
+    idx = torch.as_tensor(betas, device=W.device)
+    for key, S_, bar in (("r_oz5", 5, 2e-9), ("r_oz4", 4, 5e-7)):
+        err = np.abs(full[key][idx].cpu().numpy() + p - want)
+        worst = (S_ + 1.05) * 2.0 ** (-7 * S_) * c.rank * cs + 1e-13 * cabs + slack
+        assert np.max(err / worst) <= 1.0, key
+        assert np.max(err / (bar * cabs + slack)) <= 1.0, key
+    err = np.abs(full["r_single"][idx].cpu().numpy() + p - want)
+    assert np.max(err / ((2.0 ** -7 + 2.0 ** -16 + gamma(c.rank) + U32) * cabs + slack)) <= 1.0, "single forward"
 
 
 def test_fullsize_loss_matches_residual(full):
