@@ -1,10 +1,11 @@
 """An independent FP64 certificate of the full-size solve (n = 12, d = 6:
 N = k = 18,564, M = 2,704,156).
 
-The GPU runs the mixed-precision ladder (split-BF16 bulk steps with the
-single-product backward, then exact-forward steps) to an FP64-verified
-relative residual of 1e-8, in the configuration the time-to-target benchmark
-uses.  The oracle then checks the W the GPU returned on the host, in its own
+The GPU runs the mixed-precision ladder (single-product forward to 3e-3,
+split-BF16 bulk steps to 3e-6, both with the single-product backward, then
+the int8 Ozaki forward with four slices to 2e-7 and five after) to an
+FP64-verified relative residual of 1e-8, in the configuration the
+time-to-target benchmark uses.  The oracle then checks the W the GPU returned on the host, in its own
 way: its own p from the same FP32-rounded W0, its own pair map (dictionary
 lookup of exponent codes), a plain matmul for W W^T and a bincount over the
 ordered pairs (eq. nonconvex).  Its relative residual ||r|| / ||p||
@@ -37,7 +38,7 @@ def test_fullsize_solve_certified_by_the_oracle(pair_ranks_n12d6):
     pl = S.Plan(c.n, c.d, c.rank, "bf16x3")
     res = pl.solve(W, p, S.Adam(lr=3e-3), tol=1e-8, max_steps=3000, check_every=10, ladder=True,
                    stall_checks=6, stall_ratio=0.8, switch_rel=3e-6, lr_exact=1e-3, rollback_ratio=10.0,
-                   single_backward=True)
+                   single_backward=True, finisher="ozaki5", single_rel=3e-3, four_rel=2e-7)
     assert res["status"] == S.OK, res
     assert res["rel"] <= 1e-8, res
     Wf = W.double().cpu().numpy()
