@@ -170,8 +170,9 @@ def test_ozaki_forward_agrees_with_exact_forward_at_a_fit():
     assert np.all(np.abs(r_oz.cpu().numpy()) <= dc)
 
 
-@pytest.mark.parametrize("finisher,four_rel", [("ozaki", 0.0), ("ozaki5", 0.0), ("ozaki5", 1e-7)])
-def test_ozaki_finisher_solve_certified_by_the_oracle(finisher, four_rel):
+@pytest.mark.parametrize("prec,finisher,four_rel", [("bf16x3", "ozaki", 0.0), ("bf16x3", "ozaki5", 0.0),
+                                                    ("bf16x3", "ozaki5", 1e-7), ("fp32", "ozaki5", 1e-7)])
+def test_ozaki_finisher_solve_certified_by_the_oracle(prec, finisher, four_rel):
     """The ladder with the Ozaki forward (six or five slices) in its exact
     phase reaches an FP64-verified 1e-8 (the certificate is the FP64-MFMA
     forward), and the oracle agrees on the returned W."""
@@ -180,7 +181,7 @@ def test_ozaki_finisher_solve_certified_by_the_oracle(finisher, four_rel):
     k = 2 * N
     pr = O.pair_ranks(n, d)
     p = O.coefficients(gaussian((N, N // 2), 0) / math.sqrt(N // 2), n, d, pr)
-    pl = S.Plan(n, d, k, "bf16x3")
+    pl = S.Plan(n, d, k, prec)
     Wd = torch.tensor(gaussian((N, k), 1, 1 / math.sqrt(k)), dtype=torch.float32, device="cuda")
     res = pl.solve(Wd, torch.tensor(p, dtype=torch.float64, device="cuda"), S.Adam(lr=3e-3), tol=1e-8,
                    max_steps=20000, check_every=10, ladder=True, stall_checks=6, stall_ratio=0.8,
